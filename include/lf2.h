@@ -1,0 +1,180 @@
+/*
+ * lf2.h -- C ABI of the lf2 library: LATfield2's integrated 3-D FFT, the
+ * spectral Poisson solve and the power-spectrum binning built on it
+ * (Daverio, Hindmarsh & Bevis, arXiv:1508.05610), for one AMD MI355X
+ * (gfx950).
+ *
+ * Problem statement follows the paper's objects:
+ *   - Lattice (section 3.2): a periodic Cartesian lattice given by its
+ *     dimension, the size of every dimension and a halo width h.
+ *   - Field (section 3.3): data on every site with `ncomp` components.
+ *     Sites are stored row-major with dimension 0 fastest (section 3.4);
+ *     the components of a site are stored together, innermost (each element
+ *     of a field is the list of its components, section 3.5).  Every
+ *     dimension carries h halo sites on both sides (section 3.3.1), so the
+ *     memory jump along dimension 1 is N0 + 2h sites, and so on (3.4).
+ *   - PlanFFT (section 3.6): a plan links a real-space field with its
+ *     Fourier-space representation; out-of-place is the default; temporary
+ *     memory is shared between plans.
+ *
+ * Layouts used by every call (N = N0*N1*N2, Nh = N0/2 + 1):
+ *   real field      float [N2+2h][N1+2h][N0+2h][ncomp]    (h = lattice halo)
+ *   complex field   float2[N2+2h][N1+2h][N0+2h][ncomp]    (c2c, x space)
+ *   half spectrum   float2[N2][N1][Nh][ncomp]             (r2c k space, no halo)
+ *   full spectrum   float2[N2][N1][N0][ncomp]             (c2c k space, no halo)
+ * The halo sites of an input are never read; those of an output are never
+ * written.  float2 is (re, im).
+ *
+ * Transform convention: forward uses exp(-2 pi i k.x/N), backward
+ * exp(+2 pi i k.x/N); neither is normalised, so c2r(r2c(f)) = N f (the
+ * convention of FFTW, whose 1-d transforms the paper's FFT is built on).
+ * The r2c transform halves dimension 0.  c2r applies to any half spectrum
+ * G and returns sum over half-spectrum modes of c(kx) Re(G_k e^{+ik.x}),
+ * c = 1 for kx in {0, N0/2} and 2 otherwise (the imaginary parts of the
+ * kx = 0 and kx = N0/2 entries are ignored).
+ *
+ * Memory ownership: every field pointer is device memory owned by the
+ * caller and must stay valid until the work enqueued on `stream` has
+ * finished.  The library owns plans, twiddle and wavevector tables and a
+ * workspace that plans share (the paper's shared temporary memory); the
+ * workspace grows on demand with hipMalloc inside execute calls, and is
+ * meant for calls issued on one stream at a time -- callers that run plans
+ * concurrently on several streams give each plan its own workspace with
+ * lf2_plan_set_workspace.
+ *
+ * Streams: `stream` is a hipStream_t (NULL = legacy default stream).  All
+ * execute calls are asynchronous with respect to the host.
+ *
+ * Errors: argument and shape errors are detected before anything is
+ * enqueued and returned synchronously; a HIP launch or allocation failure
+ * returns LF2_ERR_DEVICE or LF2_ERR_OUT_OF_MEMORY.  Nothing throws across
+ * this interface.  lf2_last_error() gives a thread-local message for the
+ * last failing call.
+ */
+#ifndef LF2_H
+#define LF2_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    LF2_OK = 0,
+    LF2_ERR_INVALID_ARG = -1,  /* null pointer, bad size, bad enum, misaligned pointer */
+    LF2_ERR_UNSUPPORTED = -2,  /* valid request outside what this build implements */
+    LF2_ERR_OUT_OF_MEMORY = -3,
+    LF2_ERR_DEVICE = -4,       /* HIP runtime error */
+    LF2_ERR_BUDGET = -5,       /* server: request larger than the memory budget */
+    LF2_ERR_BUSY = -6,         /* server: queue full, try again */
+    LF2_ERR_NOT_READY = -7     /* server: ticket not finished yet */
+} lf2_status;
+
+/* Lattice (section 3.2): dim must be 3; size[i] >= 1; halo >= 0. */
+typedef struct {
+    int32_t dim;
+    int32_t halo;
+    int64_t size[3];
+} lf2_lattice;
+
+typedef enum { LF2_R2C = 0, LF2_C2C = 1 } lf2_fft_kind;
+typedef enum { LF2_FORWARD = -1, LF2_BACKWARD = +1 } lf2_direction;
+
+/* Plan flags. */
+#define LF2_OUT_OF_PLACE 0u           /* default (section 3.6) */
+/* Poisson flags. */
+#define LF2_POISSON_CONTINUOUS_K2 0u  /* k^2 = sum_i (2 pi nt_i / (N_i dx))^2 (default) */
+#define LF2_POISSON_DISCRETE_K2 1u    /* k^2 = sum_i (2/dx)^2 sin^2(pi n_i / N_i) */
+#define LF2_PK_OF_PHI 2u              /* bin the spectrum of phi instead of rho */
+
+typedef struct lf2_plan_s *lf2_plan;
+
+/*
+ * Create a plan for a 3-D transform on `lat` with `ncomp` components
+ * (PlanFFT, section 3.6).  Extents must factor into 2, 3 and 5 with at
+ * most one factor 3 or 5 per extent (LF2_ERR_UNSUPPORTED otherwise); r2c
+ * needs an even N0.  The plan is bound to the current HIP device; its
+ * twiddles (generated in FP64 on the device, rounded once to FP32) stay
+ * resident until lf2_plan_destroy.  Synchronises the device once.
+ */
+lf2_status lf2_fft_plan(lf2_plan *out, const lf2_lattice *lat, int32_t ncomp, lf2_fft_kind kind,
+                        uint32_t flags);
+
+/*
+ * k-space geometry of a plan (the rKSite / cKSite analogue, section 3.6):
+ * ksize = extents of the spectrum in sites (Nh or N0, N1, N2) and kstride =
+ * the jump between neighbouring sites along each dimension, in complex
+ * elements (components innermost, so kstride[0] = ncomp).  Either pointer
+ * may be NULL.
+ */
+lf2_status lf2_fft_kspace(lf2_plan p, int64_t ksize[3], int64_t kstride[3]);
+
+/* Bytes of shared workspace an execute call on this plan may use. */
+lf2_status lf2_plan_workspace_bytes(lf2_plan p, size_t *bytes);
+
+/* Give the plan its own workspace (device memory of at least
+ * lf2_plan_workspace_bytes, 256-byte aligned, owned by the caller);
+ * NULL returns the plan to the shared workspace. */
+lf2_status lf2_plan_set_workspace(lf2_plan p, void *dev_ptr, size_t bytes);
+
+/*
+ * Execute a transform (section 3.6; forward and backward, section 4).
+ *   r2c plan, LF2_FORWARD : in = real field, out = half spectrum
+ *   r2c plan, LF2_BACKWARD: in = half spectrum (not modified), out = real field
+ *   c2c plan, either      : in = complex field / spectrum, out = spectrum / field
+ * in and out must not overlap.  Pointers must be 8-byte aligned.
+ */
+lf2_status lf2_fft_execute(lf2_plan p, lf2_direction dir, const void *in, void *out,
+                           void *stream);
+
+/*
+ * Spectral Poisson solve, laplacian(phi) = rho, periodic, zero mode
+ * removed (the Poisson-solver example of sections 2 and 3.6):
+ *   phi_hat = -rho_hat / k^2 (k != 0), phi_hat(0) = 0, phi = c2r(phi_hat)/N,
+ * with the FP64 factor -1/(N k^2) applied in one pass between the forward
+ * and backward transforms along dimension 2.  r2c plan with ncomp = 1.
+ * rho and phi are real fields (halo as in the plan) and must not overlap.
+ * dx > 0 is the lattice spacing.
+ * If nbins > 0, the power spectrum of rho (or of phi with LF2_PK_OF_PHI) is
+ * binned as in lf2_power_spectrum into d_pk, d_kmean, d_count (device
+ * arrays of nbins doubles; any may be NULL).  d_parseval (nullable device
+ * array of 2 doubles) receives { sum_x rho^2, (1/N) sum_k w |rho_hat|^2 }.
+ */
+lf2_status lf2_poisson_solve(lf2_plan p, const float *rho, float *phi, double dx, uint32_t flags,
+                             int32_t nbins, double *d_pk, double *d_kmean, double *d_count,
+                             double *d_parseval, void *stream);
+
+/*
+ * Spherical-shell power spectrum (spectral analysis, section 1).  For
+ * every mode n != 0 with integer squared radius q = sum_i (nt_i L/N_i)^2,
+ * L = lcm(N0, N1, N2), q_max = sum_i (floor(N_i/2) L/N_i)^2, the bin is
+ *   b = min(nbins-1, max{b : b^2 q_max <= nbins^2 q})   (exact integers),
+ * and per bin
+ *   count = sum w,  pk = (dx^3/N) sum w |F|^2 / count,
+ *   kmean = sum w |k| / count,  |k| = 2 pi sqrt(q) / (L dx),
+ * with w = 1 at kx in {0, N0/2} and 2 elsewhere for an r2c plan (half
+ * spectrum) and w = 1 for a c2c plan.  Empty bins give 0.  Sums are FP64.
+ * field_is_kspace = 0: `field` is a real-space field (r2c: real; c2c:
+ * complex), transformed on the way without being modified;
+ * field_is_kspace = 1: `field` is already the spectrum.  ncomp must be 1.
+ * d_pk, d_kmean, d_count: device arrays of nbins doubles (any may be NULL).
+ */
+lf2_status lf2_power_spectrum(lf2_plan p, const void *field, int32_t field_is_kspace,
+                              int32_t nbins, double dx, double *d_pk, double *d_kmean,
+                              double *d_count, void *stream);
+
+lf2_status lf2_plan_destroy(lf2_plan p);
+
+const char *lf2_status_string(lf2_status s);
+const char *lf2_last_error(void);
+
+/* Library version, e.g. "lf2 0.1.0 gfx950". */
+const char *lf2_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LF2_H */

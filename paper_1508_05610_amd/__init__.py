@@ -1,0 +1,146 @@
+"""lf2 for MI355X: LATfield2's 3-D FFT, spectral Poisson solve and power
+spectrum (arXiv:1508.05610) as hand-written HIP kernels behind a C ABI.
+
+PyTorch supplies device memory and streams only; every step of a transform
+runs in the library's kernels.  ``Plan`` is the torch-facing helper over the
+C calls in ``_lib`` (which keep the C names).
+
+Layouts (N0 fastest, paper section 3.4; components innermost, 3.5):
+  real field     torch.float32 of shape (N2+2h, N1+2h, N0+2h[, ncomp])
+  complex field  torch.complex64 of the same shape
+  half spectrum  torch.complex64 of shape (N2, N1, N0//2+1[, ncomp])
+  full spectrum  torch.complex64 of shape (N2, N1, N0[, ncomp])
+"""
+from __future__ import annotations
+
+from . import _lib
+from ._lib import (LF2_BACKWARD, LF2_C2C, LF2_FORWARD, LF2_PK_OF_PHI, LF2_POISSON_DISCRETE_K2,
+                   LF2_R2C, LF2Error, lf2_fft_execute, lf2_fft_kspace, lf2_fft_plan,
+                   lf2_plan_destroy, lf2_plan_set_workspace, lf2_plan_workspace_bytes,
+                   lf2_poisson_solve, lf2_power_spectrum, lf2_version)
+
+__all__ = ["Plan", "LF2Error", "LF2_R2C", "LF2_C2C", "LF2_FORWARD", "LF2_BACKWARD",
+           "LF2_POISSON_DISCRETE_K2", "LF2_PK_OF_PHI", "lf2_fft_plan", "lf2_fft_execute",
+           "lf2_fft_kspace", "lf2_poisson_solve", "lf2_power_spectrum", "lf2_plan_destroy",
+           "lf2_plan_workspace_bytes", "lf2_plan_set_workspace", "lf2_version", "load"]
+
+
+def load():
+    """Load liblf2.so (raises ImportError if it was not built)."""
+    return _lib.load()
+
+
+def _stream_handle(stream=None) -> int:
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return int(s.cuda_stream)
+
+
+def _ptr(t, what, dtype, shape):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{what} must be a CUDA (HIP) torch tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{what} must be {dtype}, got {t.dtype}")
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{what} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+    if not t.is_contiguous():
+        raise ValueError(f"{what} must be contiguous")
+    return t.data_ptr()
+
+
+class Plan:
+    """A PlanFFT (paper section 3.6) on an N0 x N1 x N2 lattice with halo h."""
+
+    def __init__(self, sizes, kind=LF2_R2C, ncomp=1, halo=0):
+        self.sizes = tuple(int(s) for s in sizes)
+        self.kind = kind
+        self.ncomp = int(ncomp)
+        self.halo = int(halo)
+        self.handle = lf2_fft_plan(self.sizes, self.halo, self.ncomp, kind)
+        self.ksize, self.kstride = lf2_fft_kspace(self.handle)
+
+    def close(self):
+        if self.handle:
+            lf2_plan_destroy(self.handle)
+            self.handle = 0
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # shapes ---------------------------------------------------------------
+    def _comp(self):
+        return (self.ncomp,) if self.ncomp > 1 else ()
+
+    @property
+    def x_shape(self):
+        n0, n1, n2 = self.sizes
+        h = self.halo
+        return (n2 + 2 * h, n1 + 2 * h, n0 + 2 * h) + self._comp()
+
+    @property
+    def k_shape(self):
+        return (self.ksize[2], self.ksize[1], self.ksize[0]) + self._comp()
+
+    # transforms -------------------------------------------------------------
+    def forward(self, x, out=None, stream=None):
+        import torch
+        xdt = torch.float32 if self.kind == LF2_R2C else torch.complex64
+        xp = _ptr(x, "x", xdt, self.x_shape)
+        if out is None:
+            out = torch.empty(self.k_shape, dtype=torch.complex64, device=x.device)
+        op = _ptr(out, "out", torch.complex64, self.k_shape)
+        lf2_fft_execute(self.handle, LF2_FORWARD, xp, op, _stream_handle(stream))
+        return out
+
+    def backward(self, k, out=None, stream=None):
+        import torch
+        kp = _ptr(k, "k", torch.complex64, self.k_shape)
+        xdt = torch.float32 if self.kind == LF2_R2C else torch.complex64
+        if out is None:
+            out = torch.zeros(self.x_shape, dtype=xdt, device=k.device)
+        op = _ptr(out, "out", xdt, self.x_shape)
+        lf2_fft_execute(self.handle, LF2_BACKWARD, kp, op, _stream_handle(stream))
+        return out
+
+    def poisson(self, rho, phi=None, dx=1.0, flags=0, nbins=0, parseval=False, stream=None):
+        """Solve laplacian(phi) = rho; returns phi or (phi, pk, kmean, count[, parseval])."""
+        import torch
+        rp = _ptr(rho, "rho", torch.float32, self.x_shape)
+        if phi is None:
+            phi = torch.zeros(self.x_shape, dtype=torch.float32, device=rho.device)
+        pp = _ptr(phi, "phi", torch.float32, self.x_shape)
+        dev = rho.device
+        pk = kmean = count = pv = None
+        if nbins > 0:
+            pk = torch.empty(nbins, dtype=torch.float64, device=dev)
+            kmean = torch.empty(nbins, dtype=torch.float64, device=dev)
+            count = torch.empty(nbins, dtype=torch.float64, device=dev)
+        if parseval:
+            pv = torch.empty(2, dtype=torch.float64, device=dev)
+        ptr = lambda t: t.data_ptr() if t is not None else 0  # noqa: E731
+        lf2_poisson_solve(self.handle, rp, pp, dx, flags, nbins, ptr(pk), ptr(kmean), ptr(count),
+                          ptr(pv), _stream_handle(stream))
+        if nbins == 0 and not parseval:
+            return phi
+        res = (phi, pk, kmean, count)
+        return res + (pv,) if parseval else res
+
+    def power_spectrum(self, field, nbins, dx=1.0, field_is_kspace=False, stream=None):
+        """Returns (pk, kmean, count) as float64 device tensors."""
+        import torch
+        if field_is_kspace:
+            fp = _ptr(field, "field", torch.complex64, self.k_shape)
+        else:
+            xdt = torch.float32 if self.kind == LF2_R2C else torch.complex64
+            fp = _ptr(field, "field", xdt, self.x_shape)
+        dev = field.device
+        pk = torch.empty(nbins, dtype=torch.float64, device=dev)
+        kmean = torch.empty(nbins, dtype=torch.float64, device=dev)
+        count = torch.empty(nbins, dtype=torch.float64, device=dev)
+        lf2_power_spectrum(self.handle, fp, int(bool(field_is_kspace)), nbins, dx, pk.data_ptr(),
+                           kmean.data_ptr(), count.data_ptr(), _stream_handle(stream))
+        return pk, kmean, count

@@ -1,0 +1,155 @@
+"""ctypes binding of liblf2.so (include/lf2.h); argument marshalling only.
+
+The functions here carry the C names and take plain integers for device
+pointers and streams.  ``paper_1508_05610_amd.Plan`` wraps them for torch
+tensors.  Loading fails loudly when the library has not been built: there is
+no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liblf2.so")
+
+LF2_OK = 0
+LF2_ERR_INVALID_ARG = -1
+LF2_ERR_UNSUPPORTED = -2
+LF2_ERR_OUT_OF_MEMORY = -3
+LF2_ERR_DEVICE = -4
+LF2_ERR_BUDGET = -5
+LF2_ERR_BUSY = -6
+LF2_ERR_NOT_READY = -7
+
+LF2_R2C = 0
+LF2_C2C = 1
+LF2_FORWARD = -1
+LF2_BACKWARD = 1
+
+LF2_POISSON_CONTINUOUS_K2 = 0
+LF2_POISSON_DISCRETE_K2 = 1
+LF2_PK_OF_PHI = 2
+
+
+class lf2_lattice(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int32), ("halo", ctypes.c_int32), ("size", ctypes.c_int64 * 3)]
+
+
+class LF2Error(RuntimeError):
+    def __init__(self, status: int, func: str, detail: str):
+        self.status = status
+        super().__init__(f"{func}: {status_string(status)} ({detail})")
+
+
+_lib = None
+
+# C signatures: name -> (restype, argtypes)
+_vp, _i32, _u32, _i64, _f64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_uint32, ctypes.c_int64, ctypes.c_double
+_SIGS = {
+    "lf2_fft_plan": (_i32, [ctypes.POINTER(_vp), ctypes.POINTER(lf2_lattice), _i32, _i32, _u32]),
+    "lf2_fft_kspace": (_i32, [_vp, ctypes.POINTER(_i64), ctypes.POINTER(_i64)]),
+    "lf2_plan_workspace_bytes": (_i32, [_vp, ctypes.POINTER(ctypes.c_size_t)]),
+    "lf2_plan_set_workspace": (_i32, [_vp, _vp, ctypes.c_size_t]),
+    "lf2_fft_execute": (_i32, [_vp, _i32, _vp, _vp, _vp]),
+    "lf2_poisson_solve": (_i32, [_vp, _vp, _vp, _f64, _u32, _i32, _vp, _vp, _vp, _vp, _vp]),
+    "lf2_power_spectrum": (_i32, [_vp, _vp, _i32, _i32, _f64, _vp, _vp, _vp, _vp]),
+    "lf2_plan_destroy": (_i32, [_vp]),
+    "lf2_status_string": (ctypes.c_char_p, [_i32]),
+    "lf2_last_error": (ctypes.c_char_p, []),
+    "lf2_version": (ctypes.c_char_p, []),
+}
+
+
+def exported_names():
+    return list(_SIGS)
+
+
+def load(path: str = LIB_PATH):
+    global _lib
+    if _lib is None:
+        if not os.path.exists(path):
+            raise ImportError(f"{path} is not built; run __graft_entry__.build() first")
+        lib = ctypes.CDLL(path)
+        for name, (res, args) in _SIGS.items():
+            fn = getattr(lib, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = lib
+    return _lib
+
+
+def status_string(status: int) -> str:
+    return load().lf2_status_string(status).decode()
+
+
+def last_error() -> str:
+    return load().lf2_last_error().decode()
+
+
+def _check(status: int, func: str):
+    if status != LF2_OK:
+        raise LF2Error(status, func, last_error())
+
+
+def lf2_version() -> str:
+    return load().lf2_version().decode()
+
+
+def lf2_fft_plan(sizes, halo: int, ncomp: int, kind: int, flags: int = 0) -> int:
+    lat = lf2_lattice(3, int(halo), (ctypes.c_int64 * 3)(*[int(s) for s in sizes]))
+    out = _vp()
+    _check(load().lf2_fft_plan(ctypes.byref(out), ctypes.byref(lat), int(ncomp), int(kind),
+                               int(flags)), "lf2_fft_plan")
+    return out.value
+
+
+def lf2_fft_plan_status(sizes, halo: int, ncomp: int, kind: int, flags: int = 0, dim: int = 3):
+    """Raw status of lf2_fft_plan (for argument-validation tests); destroys any plan made."""
+    lat = lf2_lattice(int(dim), int(halo), (ctypes.c_int64 * 3)(*[int(s) for s in sizes]))
+    out = _vp()
+    st = load().lf2_fft_plan(ctypes.byref(out), ctypes.byref(lat), int(ncomp), int(kind), int(flags))
+    if st == LF2_OK and out.value:
+        load().lf2_plan_destroy(out)
+    return st
+
+
+def lf2_fft_kspace(plan: int):
+    ks = (_i64 * 3)()
+    st = (_i64 * 3)()
+    _check(load().lf2_fft_kspace(plan, ks, st), "lf2_fft_kspace")
+    return tuple(ks), tuple(st)
+
+
+def lf2_plan_workspace_bytes(plan: int) -> int:
+    b = ctypes.c_size_t()
+    _check(load().lf2_plan_workspace_bytes(plan, ctypes.byref(b)), "lf2_plan_workspace_bytes")
+    return int(b.value)
+
+
+def lf2_plan_set_workspace(plan: int, ptr: int, nbytes: int):
+    _check(load().lf2_plan_set_workspace(plan, ptr or None, int(nbytes)), "lf2_plan_set_workspace")
+
+
+def lf2_fft_execute(plan: int, direction: int, in_ptr: int, out_ptr: int, stream: int = 0):
+    _check(load().lf2_fft_execute(plan, int(direction), in_ptr, out_ptr, stream or None),
+           "lf2_fft_execute")
+
+
+def lf2_poisson_solve(plan: int, rho_ptr: int, phi_ptr: int, dx: float, flags: int, nbins: int,
+                      pk_ptr: int = 0, kmean_ptr: int = 0, count_ptr: int = 0,
+                      parseval_ptr: int = 0, stream: int = 0):
+    _check(load().lf2_poisson_solve(plan, rho_ptr, phi_ptr, float(dx), int(flags), int(nbins),
+                                    pk_ptr or None, kmean_ptr or None, count_ptr or None,
+                                    parseval_ptr or None, stream or None), "lf2_poisson_solve")
+
+
+def lf2_power_spectrum(plan: int, field_ptr: int, field_is_kspace: int, nbins: int, dx: float,
+                       pk_ptr: int = 0, kmean_ptr: int = 0, count_ptr: int = 0, stream: int = 0):
+    _check(load().lf2_power_spectrum(plan, field_ptr, int(field_is_kspace), int(nbins), float(dx),
+                                     pk_ptr or None, kmean_ptr or None, count_ptr or None,
+                                     stream or None), "lf2_power_spectrum")
+
+
+def lf2_plan_destroy(plan: int):
+    _check(load().lf2_plan_destroy(plan), "lf2_plan_destroy")

@@ -1,0 +1,727 @@
+// lf2_api.cpp -- plans, validation and the C ABI (include/lf2.h).
+//
+// A plan holds the per-axis twiddle tables (FP64 on the device, rounded once
+// to FP32), the integer wavevector tables used by the binning, lazily built
+// k^2 tables (per lattice spacing) and shell tables (per bin count).  The
+// pass sequence per call:
+//   r2c forward : x r2c (in -> out), y (out), z (out)
+//   c2r         : z (in -> W), y (W), x c2r (W -> out)       input untouched
+//   c2c         : x (in -> out), y (out), z (out) / z, y, x backward
+//   Poisson     : x r2c (rho -> W), y (W), z fwd * -1/(N k^2) * z bwd with
+//                 optional binning (W), y bwd (W), x c2r (W -> phi)
+//   P(k)        : x, y (into W), z forward with a read-only binning epilogue
+// followed, when binning, by a fixed-order FP64 reduction and finalize.
+#include "../../include/lf2.h"
+
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <cmath>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "lf2_internal.hpp"
+
+using namespace lf2;
+
+namespace {
+
+thread_local std::string g_err;
+
+lf2_status fail(lf2_status st, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return st;
+}
+
+#define LF2_HIP(call)                                                                       \
+    do {                                                                                    \
+        hipError_t e_ = (call);                                                             \
+        if (e_ != hipSuccess) {                                                             \
+            return fail(e_ == hipErrorOutOfMemory ? LF2_ERR_OUT_OF_MEMORY : LF2_ERR_DEVICE, \
+                        "%s failed: %s", #call, hipGetErrorString(e_));                     \
+        }                                                                                   \
+    } while (0)
+
+constexpr int kMaxDevices = 64;
+constexpr int kPkGrid = 1024;          // blocks of a binning pass (partials rows)
+constexpr int kStridedGridCap = 1 << 30;
+
+// Shared workspace per device (the paper's temporary memory shared by plans).
+struct SharedWs {
+    std::mutex mu;
+    void *ptr = nullptr;
+    size_t bytes = 0;
+};
+SharedWs g_ws[kMaxDevices];
+
+int64_t gcd64(int64_t a, int64_t b)
+{
+    while (b) {
+        int64_t t = a % b;
+        a = b;
+        b = t;
+    }
+    return a;
+}
+
+bool radix_ok(int64_t n)
+{
+    // 2^a * 3^b * 5^c with b + c <= 1 (one odd stage per line)
+    if (n < 1) return false;
+    int odd = 0;
+    while (n % 3 == 0) {
+        n /= 3;
+        ++odd;
+    }
+    while (n % 5 == 0) {
+        n /= 5;
+        ++odd;
+    }
+    while (n % 2 == 0) n /= 2;
+    return n == 1 && odd <= 1;
+}
+
+size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+}  // namespace
+
+struct K2Entry {
+    double dx;
+    int discrete;
+    double *tab[3];
+};
+
+struct ShellEntry {
+    int nbins;
+    int64_t *thresh;  // nbins + 1
+    double *count;    // nbins
+    double *sumk;     // nbins (sum w sqrt(q))
+};
+
+struct lf2_plan_s {
+    int device = 0;
+    lf2_fft_kind kind = LF2_R2C;
+    int nc = 1;
+    int halo = 0;
+    uint32_t flags = 0;
+    int64_t n[3] = {0, 0, 0};
+    int64_t nh = 0;    // N0/2 + 1
+    int64_t nxk = 0;   // k-space extent of dimension 0
+    int64_t ntot = 0;  // N0 N1 N2
+    int len[3] = {0, 0, 0};
+    void *tw[3] = {nullptr, nullptr, nullptr};
+    void *tw_post = nullptr;
+    int64_t *q[3] = {nullptr, nullptr, nullptr};
+    int64_t lcm = 1, qmax = 0;
+    std::vector<K2Entry> k2;
+    std::vector<ShellEntry> shells;
+    void *own_ws = nullptr;
+    size_t own_ws_bytes = 0;
+    std::vector<void *> allocs;
+};
+
+namespace {
+
+lf2_status plan_alloc(lf2_plan p, void **dst, size_t bytes)
+{
+    void *ptr = nullptr;
+    hipError_t e = hipMalloc(&ptr, bytes < 256 ? 256 : bytes);
+    if (e != hipSuccess)
+        return fail(LF2_ERR_OUT_OF_MEMORY, "hipMalloc(%zu) failed: %s", bytes, hipGetErrorString(e));
+    p->allocs.push_back(ptr);
+    *dst = ptr;
+    return LF2_OK;
+}
+
+// Bytes of spectrum-sized workspace W for a call.
+size_t spectrum_bytes(const lf2_plan_s *p)
+{
+    return (size_t)p->nxk * p->n[1] * p->n[2] * p->nc * 8;
+}
+
+int x_grid_blocks(const lf2_plan_s *p)
+{
+    int rb = x_rows_per_block(p->len[0], p->nc);
+    return (int)((p->n[1] * p->n[2] + rb - 1) / rb);
+}
+
+// Workspace layout: [W spectrum][pk partials][bin sums][sumsq partials][sumsq]
+struct WsLayout {
+    size_t w, part, sums, sq, sqt, total;
+};
+
+WsLayout ws_layout(const lf2_plan_s *p, bool need_w, int nbins, bool parseval)
+{
+    WsLayout l{};
+    size_t off = 0;
+    l.w = off;
+    off += need_w ? align256(spectrum_bytes(p)) : 0;
+    l.part = off;
+    off += nbins > 0 ? align256((size_t)kPkGrid * (nbins + 1) * 8) : 0;
+    l.sums = off;
+    off += nbins > 0 ? align256((size_t)(nbins + 1) * 8) : 0;
+    l.sq = off;
+    off += parseval ? align256((size_t)x_grid_blocks(p) * 8) : 0;
+    l.sqt = off;
+    off += parseval ? 256 : 0;
+    l.total = off;
+    return l;
+}
+
+lf2_status get_workspace(lf2_plan p, size_t need, char **out)
+{
+    if (need == 0) {
+        *out = nullptr;
+        return LF2_OK;
+    }
+    if (p->own_ws) {
+        if (p->own_ws_bytes < need)
+            return fail(LF2_ERR_INVALID_ARG, "plan workspace of %zu bytes is smaller than the %zu needed",
+                        p->own_ws_bytes, need);
+        *out = (char *)p->own_ws;
+        return LF2_OK;
+    }
+    SharedWs &ws = g_ws[p->device];
+    std::lock_guard<std::mutex> lk(ws.mu);
+    if (ws.bytes < need) {
+        if (ws.ptr) {
+            LF2_HIP(hipDeviceSynchronize());
+            LF2_HIP(hipFree(ws.ptr));
+            ws.ptr = nullptr;
+            ws.bytes = 0;
+        }
+        void *ptr = nullptr;
+        hipError_t e = hipMalloc(&ptr, need);
+        if (e != hipSuccess)
+            return fail(LF2_ERR_OUT_OF_MEMORY, "workspace hipMalloc(%zu) failed: %s", need,
+                        hipGetErrorString(e));
+        ws.ptr = ptr;
+        ws.bytes = need;
+    }
+    *out = (char *)ws.ptr;
+    return LF2_OK;
+}
+
+lf2_status check_device(const lf2_plan_s *p)
+{
+    int dev = -1;
+    LF2_HIP(hipGetDevice(&dev));
+    if (dev != p->device)
+        return fail(LF2_ERR_INVALID_ARG, "plan was made on device %d but device %d is current",
+                    p->device, dev);
+    return LF2_OK;
+}
+
+ModeTables base_tables(const lf2_plan_s *p)
+{
+    ModeTables mt{};
+    mt.nxk = (int)p->nxk;
+    mt.n0 = (int)p->n[0];
+    mt.half = p->kind == LF2_R2C ? 1 : 0;
+    for (int i = 0; i < 3; ++i) {
+        mt.k2[i] = nullptr;
+        mt.q[i] = p->q[i];
+    }
+    mt.thresh = nullptr;
+    mt.nbins = 0;
+    mt.qmax = (double)p->qmax;
+    mt.scale_n = 1.0 / (double)p->ntot;
+    return mt;
+}
+
+lf2_status get_k2(lf2_plan p, double dx, int discrete, hipStream_t s, const double *out[3])
+{
+    for (auto &e : p->k2)
+        if (e.dx == dx && e.discrete == discrete) {
+            for (int i = 0; i < 3; ++i) out[i] = e.tab[i];
+            return LF2_OK;
+        }
+    K2Entry e{dx, discrete, {nullptr, nullptr, nullptr}};
+    const int64_t cnt[3] = {p->nxk, p->n[1], p->n[2]};
+    for (int i = 0; i < 3; ++i) {
+        void *ptr;
+        lf2_status st = plan_alloc(p, &ptr, (size_t)cnt[i] * 8);
+        if (st) return st;
+        e.tab[i] = (double *)ptr;
+        LF2_HIP(launch_k2_table(e.tab[i], (int)p->n[i], (int)cnt[i], dx, discrete, s));
+    }
+    p->k2.push_back(e);
+    for (int i = 0; i < 3; ++i) out[i] = e.tab[i];
+    return LF2_OK;
+}
+
+lf2_status get_shell(lf2_plan p, int nbins, hipStream_t s, ShellEntry *out)
+{
+    for (auto &e : p->shells)
+        if (e.nbins == nbins) {
+            *out = e;
+            return LF2_OK;
+        }
+    ShellEntry e{nbins, nullptr, nullptr, nullptr};
+    void *ptr;
+    lf2_status st = plan_alloc(p, &ptr, (size_t)(nbins + 1) * 8);
+    if (st) return st;
+    e.thresh = (int64_t *)ptr;
+    if ((st = plan_alloc(p, &ptr, (size_t)nbins * 8))) return st;
+    e.count = (double *)ptr;
+    if ((st = plan_alloc(p, &ptr, (size_t)nbins * 8))) return st;
+    e.sumk = (double *)ptr;
+    LF2_HIP(launch_thresholds(e.thresh, nbins, p->qmax, s));
+    // shell sums over the lattice (plan-time work, kept with the plan)
+    const int grid = 512;
+    double *pc = nullptr, *pkk = nullptr;
+    LF2_HIP(hipMalloc(&pc, (size_t)grid * nbins * 8));
+    hipError_t e2 = hipMalloc(&pkk, (size_t)grid * nbins * 8);
+    if (e2 != hipSuccess) {
+        (void)hipFree(pc);
+        return fail(LF2_ERR_OUT_OF_MEMORY, "hipMalloc failed: %s", hipGetErrorString(e2));
+    }
+    ModeTables mt = base_tables(p);
+    mt.thresh = e.thresh;
+    mt.nbins = nbins;
+    hipError_t e3 = launch_shell_partials(mt, (int)p->n[1], (int)p->n[2], 0.0, pc, pkk, grid, s);
+    if (e3 == hipSuccess) e3 = launch_reduce_cols(pc, grid, nbins, e.count, s);
+    if (e3 == hipSuccess) e3 = launch_reduce_cols(pkk, grid, nbins, e.sumk, s);
+    if (e3 == hipSuccess) e3 = hipStreamSynchronize(s);
+    (void)hipFree(pc);
+    (void)hipFree(pkk);
+    if (e3 != hipSuccess) return fail(LF2_ERR_DEVICE, "shell table: %s", hipGetErrorString(e3));
+    p->shells.push_back(e);
+    *out = e;
+    return LF2_OK;
+}
+
+lf2_status check_ptr(const void *ptr, const char *what, size_t align)
+{
+    if (!ptr) return fail(LF2_ERR_INVALID_ARG, "%s is NULL", what);
+    if (((uintptr_t)ptr) % align)
+        return fail(LF2_ERR_INVALID_ARG, "%s is not %zu-byte aligned", what, align);
+    return LF2_OK;
+}
+
+// ------------------------------------------------------------- pass runners
+
+XArgs x_args(const lf2_plan_s *p, const void *in, void *out, bool in_is_x, bool out_is_x,
+             bool real_x)
+{
+    // x-space arrays carry the halo; k-space arrays do not.  Units are the
+    // array's elements: floats for real fields, complex for complex ones.
+    XArgs a{};
+    a.in = in;
+    a.out = out;
+    a.nrows = p->n[1] * p->n[2];
+    a.n1 = (int)p->n[1];
+    const int64_t h = p->halo, nc = p->nc;
+    const int64_t xrow = (p->n[0] + 2 * h) * nc, xplane = (p->n[1] + 2 * h) * xrow;
+    const int64_t xoff = h * nc + h * xrow + h * xplane;
+    const int64_t krow = p->nxk * nc, kplane = p->n[1] * krow;
+    (void)real_x;
+    if (in_is_x) {
+        a.in_off = xoff;
+        a.in_row = xrow;
+        a.in_plane = xplane;
+    } else {
+        a.in_off = 0;
+        a.in_row = krow;
+        a.in_plane = kplane;
+    }
+    if (out_is_x) {
+        a.out_off = xoff;
+        a.out_row = xrow;
+        a.out_plane = xplane;
+    } else {
+        a.out_off = 0;
+        a.out_row = krow;
+        a.out_plane = kplane;
+    }
+    a.tw = p->tw[0];
+    a.tw_post = p->tw_post;
+    a.sumsq = nullptr;
+    return a;
+}
+
+SArgs s_args(const lf2_plan_s *p, int axis, const void *in, void *out, int epi)
+{
+    SArgs a{};
+    a.in = in;
+    a.out = out;
+    const int64_t C1 = p->nxk * p->nc;
+    if (axis == 1) {
+        a.stride = C1;
+        a.ncols_inner = C1;
+        a.outer = p->n[1] * C1;
+        a.ncols = p->n[2] * C1;
+    } else {
+        a.stride = p->n[1] * C1;
+        a.ncols_inner = p->n[1] * C1;
+        a.outer = 0;
+        a.ncols = p->n[1] * C1;
+    }
+    a.epi = epi;
+    a.tw = p->tw[axis];
+    a.mt = base_tables(p);
+    a.partial = nullptr;
+    return a;
+}
+
+lf2_status run_strided(const lf2_plan_s *p, int axis, int sign, const SArgs &a, int grid_cap,
+                       hipStream_t s, int *grid_used)
+{
+    hipError_t e = launch_strided(p->len[axis], sign, a, grid_cap, s, grid_used);
+    if (e != hipSuccess)
+        return fail(LF2_ERR_DEVICE, "strided pass (axis %d, L=%d) launch: %s", axis, p->len[axis],
+                    hipGetErrorString(e));
+    return LF2_OK;
+}
+
+lf2_status run_x(const lf2_plan_s *p, int which, int sign, const XArgs &a, hipStream_t s)
+{
+    hipError_t e;
+    if (which == 0)
+        e = launch_x_r2c(p->len[0], p->nc, a, s);
+    else if (which == 1)
+        e = launch_x_c2r(p->len[0], p->nc, a, s);
+    else
+        e = launch_x_c2c(p->len[0], p->nc, sign, a, s);
+    if (e != hipSuccess)
+        return fail(LF2_ERR_DEVICE, "x pass (L=%d) launch: %s", p->len[0], hipGetErrorString(e));
+    return LF2_OK;
+}
+
+// Binning tail: reduce partials, finalize into the caller's arrays.
+lf2_status pk_tail(lf2_plan p, const ShellEntry &sh, double *part, int grid, double *sums,
+                   double dx, double vscale, double *d_pk, double *d_kmean, double *d_count,
+                   double *d_parseval, const double *sumsq_total, hipStream_t s)
+{
+    const int nb = sh.nbins;
+    LF2_HIP(launch_reduce_cols(part, grid, nb + 1, sums, s));
+    const double norm = dx * dx * dx / (double)p->ntot;
+    const double kscale = 6.283185307179586476925286766559 / ((double)p->lcm * dx);
+    LF2_HIP(launch_pk_finalize(sums, nb, sh.count, sh.sumk, norm, vscale, kscale, d_pk, d_kmean,
+                               d_count, d_parseval, sumsq_total, 1.0 / (double)p->ntot, s));
+    return LF2_OK;
+}
+
+}  // namespace
+
+// ===================================================================== C ABI
+
+extern "C" {
+
+const char *lf2_status_string(lf2_status s)
+{
+    switch (s) {
+    case LF2_OK: return "LF2_OK";
+    case LF2_ERR_INVALID_ARG: return "LF2_ERR_INVALID_ARG";
+    case LF2_ERR_UNSUPPORTED: return "LF2_ERR_UNSUPPORTED";
+    case LF2_ERR_OUT_OF_MEMORY: return "LF2_ERR_OUT_OF_MEMORY";
+    case LF2_ERR_DEVICE: return "LF2_ERR_DEVICE";
+    case LF2_ERR_BUDGET: return "LF2_ERR_BUDGET";
+    case LF2_ERR_BUSY: return "LF2_ERR_BUSY";
+    case LF2_ERR_NOT_READY: return "LF2_ERR_NOT_READY";
+    }
+    return "LF2_ERR_UNKNOWN";
+}
+
+const char *lf2_last_error(void) { return g_err.c_str(); }
+
+const char *lf2_version(void) { return "lf2 0.1.0 gfx950"; }
+
+lf2_status lf2_fft_plan(lf2_plan *out, const lf2_lattice *lat, int32_t ncomp, lf2_fft_kind kind,
+                        uint32_t flags)
+{
+    if (!out) return fail(LF2_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    if (!lat) return fail(LF2_ERR_INVALID_ARG, "lattice is NULL");
+    if (lat->dim != 3) return fail(LF2_ERR_UNSUPPORTED, "dim %d: only 3-d lattices have an FFT", lat->dim);
+    if (lat->halo < 0) return fail(LF2_ERR_INVALID_ARG, "halo %d < 0", lat->halo);
+    if (kind != LF2_R2C && kind != LF2_C2C) return fail(LF2_ERR_INVALID_ARG, "bad kind %d", (int)kind);
+    if (ncomp < 1) return fail(LF2_ERR_INVALID_ARG, "ncomp %d < 1", ncomp);
+    if (flags != 0) return fail(LF2_ERR_UNSUPPORTED, "plan flags 0x%x not supported", flags);
+    for (int i = 0; i < 3; ++i) {
+        if (lat->size[i] < 1) return fail(LF2_ERR_INVALID_ARG, "size[%d] = %lld < 1", i, (long long)lat->size[i]);
+        if (lat->size[i] > (1 << 20)) return fail(LF2_ERR_UNSUPPORTED, "size[%d] too large", i);
+        if (!radix_ok(lat->size[i]))
+            return fail(LF2_ERR_UNSUPPORTED,
+                        "size[%d] = %lld must be 2^a, 3*2^a or 5*2^a", i, (long long)lat->size[i]);
+    }
+    if (kind == LF2_R2C && lat->size[0] % 2)
+        return fail(LF2_ERR_UNSUPPORTED, "r2c needs an even size[0] (got %lld)", (long long)lat->size[0]);
+    int lens[3] = {(int)(kind == LF2_R2C ? lat->size[0] / 2 : lat->size[0]), (int)lat->size[1],
+                   (int)lat->size[2]};
+    if (!x_supported(lens[0], ncomp))
+        return fail(LF2_ERR_UNSUPPORTED, "no x-pass kernel for line length %d with %d components", lens[0], ncomp);
+    for (int i = 1; i < 3; ++i)
+        if (!s_supported(lens[i]))
+            return fail(LF2_ERR_UNSUPPORTED, "no strided kernel for line length %d", lens[i]);
+
+    lf2_plan p = new (std::nothrow) lf2_plan_s();
+    if (!p) return fail(LF2_ERR_OUT_OF_MEMORY, "plan allocation");
+    hipError_t e = hipGetDevice(&p->device);
+    if (e != hipSuccess || p->device < 0 || p->device >= kMaxDevices) {
+        delete p;
+        return fail(LF2_ERR_DEVICE, "hipGetDevice: %s", hipGetErrorString(e));
+    }
+    p->kind = kind;
+    p->nc = ncomp;
+    p->halo = lat->halo;
+    p->flags = flags;
+    for (int i = 0; i < 3; ++i) {
+        p->n[i] = lat->size[i];
+        p->len[i] = lens[i];
+    }
+    p->nh = p->n[0] / 2 + 1;
+    p->nxk = kind == LF2_R2C ? p->nh : p->n[0];
+    p->ntot = p->n[0] * p->n[1] * p->n[2];
+    p->lcm = p->n[0];
+    p->lcm = p->lcm / gcd64(p->lcm, p->n[1]) * p->n[1];
+    p->lcm = p->lcm / gcd64(p->lcm, p->n[2]) * p->n[2];
+    p->qmax = 0;
+    for (int i = 0; i < 3; ++i) {
+        int64_t a = (p->n[i] / 2) * (p->lcm / p->n[i]);
+        p->qmax += a * a;
+    }
+    hipStream_t s = nullptr;
+    lf2_status st = LF2_OK;
+    for (int i = 0; i < 3 && st == LF2_OK; ++i) {
+        st = plan_alloc(p, &p->tw[i], (size_t)p->len[i] * 8);
+        if (st == LF2_OK && launch_twiddles(p->tw[i], p->len[i], s) != hipSuccess)
+            st = fail(LF2_ERR_DEVICE, "twiddle kernel launch");
+    }
+    if (st == LF2_OK && kind == LF2_R2C) {
+        st = plan_alloc(p, &p->tw_post, (size_t)p->nh * 8);
+        if (st == LF2_OK && launch_twiddles(p->tw_post, -(int)p->n[0], s) != hipSuccess)
+            st = fail(LF2_ERR_DEVICE, "twiddle kernel launch");
+    }
+    const int64_t cnt[3] = {p->nxk, p->n[1], p->n[2]};
+    for (int i = 0; i < 3 && st == LF2_OK; ++i) {
+        void *ptr = nullptr;
+        st = plan_alloc(p, &ptr, (size_t)cnt[i] * 8);
+        p->q[i] = (int64_t *)ptr;
+        if (st == LF2_OK && launch_q_table(p->q[i], (int)p->n[i], (int)cnt[i], p->lcm / p->n[i], s) != hipSuccess)
+            st = fail(LF2_ERR_DEVICE, "q table launch");
+    }
+    if (st == LF2_OK) {
+        e = hipDeviceSynchronize();
+        if (e != hipSuccess) st = fail(LF2_ERR_DEVICE, "plan setup: %s", hipGetErrorString(e));
+    }
+    if (st != LF2_OK) {
+        lf2_plan_destroy(p);
+        return st;
+    }
+    *out = p;
+    return LF2_OK;
+}
+
+lf2_status lf2_plan_destroy(lf2_plan p)
+{
+    if (!p) return fail(LF2_ERR_INVALID_ARG, "plan is NULL");
+    for (void *ptr : p->allocs) (void)hipFree(ptr);
+    delete p;
+    return LF2_OK;
+}
+
+lf2_status lf2_fft_kspace(lf2_plan p, int64_t ksize[3], int64_t kstride[3])
+{
+    if (!p) return fail(LF2_ERR_INVALID_ARG, "plan is NULL");
+    if (ksize) {
+        ksize[0] = p->nxk;
+        ksize[1] = p->n[1];
+        ksize[2] = p->n[2];
+    }
+    if (kstride) {
+        kstride[0] = p->nc;
+        kstride[1] = p->nc * p->nxk;
+        kstride[2] = p->nc * p->nxk * p->n[1];
+    }
+    return LF2_OK;
+}
+
+lf2_status lf2_plan_workspace_bytes(lf2_plan p, size_t *bytes)
+{
+    if (!p || !bytes) return fail(LF2_ERR_INVALID_ARG, "NULL argument");
+    *bytes = ws_layout(p, true, kMaxBins, true).total;
+    return LF2_OK;
+}
+
+lf2_status lf2_plan_set_workspace(lf2_plan p, void *dev_ptr, size_t bytes)
+{
+    if (!p) return fail(LF2_ERR_INVALID_ARG, "plan is NULL");
+    if (dev_ptr && ((uintptr_t)dev_ptr % 256))
+        return fail(LF2_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
+    p->own_ws = dev_ptr;
+    p->own_ws_bytes = dev_ptr ? bytes : 0;
+    return LF2_OK;
+}
+
+lf2_status lf2_fft_execute(lf2_plan p, lf2_direction dir, const void *in, void *out, void *stream)
+{
+    if (!p) return fail(LF2_ERR_INVALID_ARG, "plan is NULL");
+    if (dir != LF2_FORWARD && dir != LF2_BACKWARD) return fail(LF2_ERR_INVALID_ARG, "bad direction %d", (int)dir);
+    lf2_status st;
+    if ((st = check_ptr(in, "in", 8)) || (st = check_ptr(out, "out", 8))) return st;
+    if (in == out) return fail(LF2_ERR_UNSUPPORTED, "in-place transforms are not supported (in == out)");
+    if ((st = check_device(p))) return st;
+    hipStream_t s = (hipStream_t)stream;
+    if (p->kind == LF2_R2C && dir == LF2_FORWARD) {
+        if ((st = run_x(p, 0, -1, x_args(p, in, out, true, false, true), s))) return st;
+        if ((st = run_strided(p, 1, -1, s_args(p, 1, out, out, EPI_STORE), kStridedGridCap, s, nullptr))) return st;
+        return run_strided(p, 2, -1, s_args(p, 2, out, out, EPI_STORE), kStridedGridCap, s, nullptr);
+    }
+    if (p->kind == LF2_R2C) {
+        WsLayout L = ws_layout(p, true, 0, false);
+        char *ws;
+        if ((st = get_workspace(p, L.total, &ws))) return st;
+        void *W = ws + L.w;
+        if ((st = run_strided(p, 2, +1, s_args(p, 2, in, W, EPI_STORE), kStridedGridCap, s, nullptr))) return st;
+        if ((st = run_strided(p, 1, +1, s_args(p, 1, W, W, EPI_STORE), kStridedGridCap, s, nullptr))) return st;
+        return run_x(p, 1, +1, x_args(p, W, out, false, true, true), s);
+    }
+    // c2c
+    const int sg = (int)dir;
+    if (dir == LF2_FORWARD) {
+        if ((st = run_x(p, 2, sg, x_args(p, in, out, true, false, false), s))) return st;
+        if ((st = run_strided(p, 1, sg, s_args(p, 1, out, out, EPI_STORE), kStridedGridCap, s, nullptr))) return st;
+        return run_strided(p, 2, sg, s_args(p, 2, out, out, EPI_STORE), kStridedGridCap, s, nullptr);
+    }
+    if (p->halo == 0) {
+        if ((st = run_strided(p, 2, sg, s_args(p, 2, in, out, EPI_STORE), kStridedGridCap, s, nullptr))) return st;
+        if ((st = run_strided(p, 1, sg, s_args(p, 1, out, out, EPI_STORE), kStridedGridCap, s, nullptr))) return st;
+        return run_x(p, 2, sg, x_args(p, out, out, false, true, false), s);
+    }
+    WsLayout L = ws_layout(p, true, 0, false);
+    char *ws;
+    if ((st = get_workspace(p, L.total, &ws))) return st;
+    void *W = ws + L.w;
+    if ((st = run_strided(p, 2, sg, s_args(p, 2, in, W, EPI_STORE), kStridedGridCap, s, nullptr))) return st;
+    if ((st = run_strided(p, 1, sg, s_args(p, 1, W, W, EPI_STORE), kStridedGridCap, s, nullptr))) return st;
+    return run_x(p, 2, sg, x_args(p, W, out, false, true, false), s);
+}
+
+static lf2_status check_bins(const lf2_plan_s *p, int32_t nbins)
+{
+    if (nbins < 0) return fail(LF2_ERR_INVALID_ARG, "nbins %d < 0", nbins);
+    if (nbins > kMaxBins) return fail(LF2_ERR_UNSUPPORTED, "nbins %d > %d", nbins, kMaxBins);
+    if (nbins > 0) {
+        // nbins^2 * qmax must fit the exact integer bin rule
+        long double lim = (long double)nbins * nbins * (long double)p->qmax;
+        if (lim > 4.0e18L) return fail(LF2_ERR_UNSUPPORTED, "nbins^2 * qmax overflows the integer bin rule");
+    }
+    return LF2_OK;
+}
+
+lf2_status lf2_poisson_solve(lf2_plan p, const float *rho, float *phi, double dx, uint32_t flags,
+                             int32_t nbins, double *d_pk, double *d_kmean, double *d_count,
+                             double *d_parseval, void *stream)
+{
+    if (!p) return fail(LF2_ERR_INVALID_ARG, "plan is NULL");
+    if (p->kind != LF2_R2C || p->nc != 1)
+        return fail(LF2_ERR_UNSUPPORTED, "Poisson needs an r2c plan with ncomp = 1");
+    lf2_status st;
+    if ((st = check_ptr(rho, "rho", 4)) || (st = check_ptr(phi, "phi", 4))) return st;
+    if ((const void *)rho == (const void *)phi) return fail(LF2_ERR_INVALID_ARG, "rho and phi must not alias");
+    if (!(dx > 0.0) || !std::isfinite(dx)) return fail(LF2_ERR_INVALID_ARG, "dx must be > 0");
+    if (flags & ~(uint32_t)(LF2_POISSON_DISCRETE_K2 | LF2_PK_OF_PHI))
+        return fail(LF2_ERR_INVALID_ARG, "unknown Poisson flags 0x%x", flags);
+    if ((st = check_bins(p, nbins))) return st;
+    if (d_parseval && (flags & LF2_PK_OF_PHI))
+        return fail(LF2_ERR_INVALID_ARG, "Parseval sums are defined for rho; drop LF2_PK_OF_PHI");
+    if ((st = check_device(p))) return st;
+    hipStream_t s = (hipStream_t)stream;
+    const bool parseval = d_parseval != nullptr;
+    const int nb = nbins > 0 ? nbins : (parseval ? 1 : 0);
+    WsLayout L = ws_layout(p, true, nb, parseval);
+    char *ws;
+    if ((st = get_workspace(p, L.total, &ws))) return st;
+    void *W = ws + L.w;
+    const double *k2[3];
+    if ((st = get_k2(p, dx, (flags & LF2_POISSON_DISCRETE_K2) ? 1 : 0, s, k2))) return st;
+    ShellEntry sh{};
+    if (nb > 0 && (st = get_shell(p, nb, s, &sh))) return st;
+
+    XArgs xa = x_args(p, rho, W, true, false, true);
+    if (parseval) xa.sumsq = (double *)(ws + L.sq);
+    if ((st = run_x(p, 0, -1, xa, s))) return st;
+    if ((st = run_strided(p, 1, -1, s_args(p, 1, W, W, EPI_STORE), kStridedGridCap, s, nullptr))) return st;
+    int epi = EPI_STORE | EPI_POISSON;
+    if (nb > 0) epi |= (flags & LF2_PK_OF_PHI) ? EPI_PK_AFTER : EPI_PK;
+    SArgs za = s_args(p, 2, W, W, epi);
+    for (int i = 0; i < 3; ++i) za.mt.k2[i] = k2[i];
+    int grid = 0;
+    if (nb > 0) {
+        za.mt.thresh = sh.thresh;
+        za.mt.nbins = nb;
+        za.partial = (double *)(ws + L.part);
+    }
+    if ((st = run_strided(p, 2, -1, za, nb > 0 ? kPkGrid : kStridedGridCap, s, &grid))) return st;
+    if ((st = run_strided(p, 1, +1, s_args(p, 1, W, W, EPI_STORE), kStridedGridCap, s, nullptr))) return st;
+    if ((st = run_x(p, 1, +1, x_args(p, W, phi, false, true, true), s))) return st;
+    if (nb > 0) {
+        double *sqt = nullptr;
+        if (parseval) {
+            sqt = (double *)(ws + L.sqt);
+            LF2_HIP(launch_reduce_cols((double *)(ws + L.sq), x_grid_blocks(p), 1, sqt, s));
+        }
+        const double vscale = (flags & LF2_PK_OF_PHI) ? (double)p->ntot * (double)p->ntot : 1.0;
+        const bool user_bins = nbins > 0;
+        if ((st = pk_tail(p, sh, (double *)(ws + L.part), grid, (double *)(ws + L.sums), dx, vscale,
+                          user_bins ? d_pk : nullptr, user_bins ? d_kmean : nullptr,
+                          user_bins ? d_count : nullptr, d_parseval, sqt, s)))
+            return st;
+    }
+    return LF2_OK;
+}
+
+lf2_status lf2_power_spectrum(lf2_plan p, const void *field, int32_t field_is_kspace, int32_t nbins,
+                              double dx, double *d_pk, double *d_kmean, double *d_count,
+                              void *stream)
+{
+    if (!p) return fail(LF2_ERR_INVALID_ARG, "plan is NULL");
+    if (p->nc != 1) return fail(LF2_ERR_UNSUPPORTED, "power spectrum needs ncomp = 1");
+    lf2_status st;
+    if ((st = check_ptr(field, "field", field_is_kspace || p->kind == LF2_C2C ? 8 : 4))) return st;
+    if (nbins < 1) return fail(LF2_ERR_INVALID_ARG, "nbins %d < 1", nbins);
+    if ((st = check_bins(p, nbins))) return st;
+    if (!(dx > 0.0) || !std::isfinite(dx)) return fail(LF2_ERR_INVALID_ARG, "dx must be > 0");
+    if ((st = check_device(p))) return st;
+    hipStream_t s = (hipStream_t)stream;
+    WsLayout L = ws_layout(p, !field_is_kspace, nbins, false);
+    char *ws;
+    if ((st = get_workspace(p, L.total, &ws))) return st;
+    ShellEntry sh{};
+    if ((st = get_shell(p, nbins, s, &sh))) return st;
+    double *part = (double *)(ws + L.part);
+    int grid = 0;
+    if (field_is_kspace) {
+        ModeTables mt = base_tables(p);
+        mt.thresh = sh.thresh;
+        mt.nbins = nbins;
+        grid = kPkGrid;
+        LF2_HIP(launch_pk_kspace(field, (int)p->n[1], (int)p->n[2], mt, part, grid, s));
+    } else {
+        void *W = ws + L.w;
+        if (p->kind == LF2_R2C) {
+            if ((st = run_x(p, 0, -1, x_args(p, field, W, true, false, true), s))) return st;
+        } else {
+            if ((st = run_x(p, 2, -1, x_args(p, field, W, true, false, false), s))) return st;
+        }
+        if ((st = run_strided(p, 1, -1, s_args(p, 1, W, W, EPI_STORE), kStridedGridCap, s, nullptr))) return st;
+        SArgs za = s_args(p, 2, W, W, EPI_PK);
+        za.mt.thresh = sh.thresh;
+        za.mt.nbins = nbins;
+        za.partial = part;
+        if ((st = run_strided(p, 2, -1, za, kPkGrid, s, &grid))) return st;
+    }
+    return pk_tail(p, sh, part, grid, (double *)(ws + L.sums), dx, 1.0, d_pk, d_kmean, d_count,
+                   nullptr, nullptr, s);
+}
+
+}  // extern "C"

@@ -1,0 +1,269 @@
+// lf2_device.hpp -- device-side FFT engine for gfx950.
+//
+// Radix butterflies and an LDS-resident Stockham (autosort, decimation in
+// time) driver.  One stage of radix R on a line of length L, after the
+// stages already done have combined sub-transforms of length Ns, computes
+// for every butterfly j in [0, L/R):
+//   v_r = a[j + r L/R] * W_{Ns R}^{S r (j mod Ns)}        (r = 0..R-1)
+//   v   = DFT_R(v)
+//   b[(j div Ns) Ns R + (j mod Ns) + r Ns] = v_r
+// and after the last stage the line holds its DFT in natural order.  Any
+// order of radices whose product is L works; W_n = exp(2 pi i / n), S = -1
+// forward and +1 backward.
+//
+// Lines live in LDS at address  line * LS + point * PS  (LS/PS chosen by the
+// caller: contiguous lines for the x pass, interleaved columns for the
+// strided passes so that lanes touch consecutive words).  A stage first
+// reads every butterfly input of the thread into registers, waits at a
+// barrier, then writes its outputs in place, and waits again.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lf2 {
+
+struct c32 {
+    float x, y;
+};
+
+__device__ __forceinline__ c32 mk(float a, float b) { return c32{a, b}; }
+__device__ __forceinline__ c32 add(c32 a, c32 b) { return c32{a.x + b.x, a.y + b.y}; }
+__device__ __forceinline__ c32 sub(c32 a, c32 b) { return c32{a.x - b.x, a.y - b.y}; }
+__device__ __forceinline__ c32 mul(c32 a, c32 b)
+{
+    return c32{a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+__device__ __forceinline__ c32 conjg(c32 a) { return c32{a.x, -a.y}; }
+__device__ __forceinline__ c32 scl(c32 a, float s) { return c32{a.x * s, a.y * s}; }
+// s * i * a  (s = +-1)
+template <int S>
+__device__ __forceinline__ c32 muli(c32 a)
+{
+    return S > 0 ? c32{-a.y, a.x} : c32{a.y, -a.x};
+}
+
+// ---------------------------------------------------------------- butterflies
+// In-place DFT of R values: v_k <- sum_r v_r exp(S 2 pi i r k / R).
+
+template <int R, int S>
+struct Dft;
+
+template <int S>
+struct Dft<1, S> {
+    static __device__ __forceinline__ void run(c32 *) {}
+};
+
+template <int S>
+struct Dft<2, S> {
+    static __device__ __forceinline__ void run(c32 *v)
+    {
+        c32 a = v[0], b = v[1];
+        v[0] = add(a, b);
+        v[1] = sub(a, b);
+    }
+};
+
+template <int S>
+struct Dft<3, S> {
+    static __device__ __forceinline__ void run(c32 *v)
+    {
+        const float h = 0.86602540378443864676f;  // sin(2 pi / 3)
+        c32 t = add(v[1], v[2]);
+        c32 u = sub(v[1], v[2]);
+        c32 m = c32{v[0].x - 0.5f * t.x, v[0].y - 0.5f * t.y};
+        c32 r = muli<S>(scl(u, h));
+        v[0] = add(v[0], t);
+        v[1] = add(m, r);
+        v[2] = sub(m, r);
+    }
+};
+
+template <int S>
+struct Dft<4, S> {
+    static __device__ __forceinline__ void run(c32 *v)
+    {
+        c32 a = add(v[0], v[2]), b = sub(v[0], v[2]);
+        c32 c = add(v[1], v[3]), d = muli<S>(sub(v[1], v[3]));
+        v[0] = add(a, c);
+        v[2] = sub(a, c);
+        v[1] = add(b, d);
+        v[3] = sub(b, d);
+    }
+};
+
+template <int S>
+struct Dft<5, S> {
+    static __device__ __forceinline__ void run(c32 *v)
+    {
+        const float c1 = 0.30901699437494742410f;   // cos(2 pi / 5)
+        const float c2 = -0.80901699437494742410f;  // cos(4 pi / 5)
+        const float s1 = 0.95105651629515357212f;   // sin(2 pi / 5)
+        const float s2 = 0.58778525229247312917f;   // sin(4 pi / 5)
+        c32 t1 = add(v[1], v[4]), t2 = add(v[2], v[3]);
+        c32 t3 = sub(v[1], v[4]), t4 = sub(v[2], v[3]);
+        c32 a0 = v[0];
+        c32 m1 = c32{a0.x + c1 * t1.x + c2 * t2.x, a0.y + c1 * t1.y + c2 * t2.y};
+        c32 m2 = c32{a0.x + c2 * t1.x + c1 * t2.x, a0.y + c2 * t1.y + c1 * t2.y};
+        c32 n1 = muli<S>(c32{s1 * t3.x + s2 * t4.x, s1 * t3.y + s2 * t4.y});
+        c32 n2 = muli<S>(c32{s2 * t3.x - s1 * t4.x, s2 * t3.y - s1 * t4.y});
+        v[0] = add(a0, add(t1, t2));
+        v[1] = add(m1, n1);
+        v[4] = sub(m1, n1);
+        v[2] = add(m2, n2);
+        v[3] = sub(m2, n2);
+    }
+};
+
+template <int S>
+struct Dft<8, S> {
+    static __device__ __forceinline__ void run(c32 *v)
+    {
+        const float r2 = 0.70710678118654752440f;
+        c32 e[4] = {v[0], v[2], v[4], v[6]};
+        c32 o[4] = {v[1], v[3], v[5], v[7]};
+        Dft<4, S>::run(e);
+        Dft<4, S>::run(o);
+        // o[k] *= W8^{S k}
+        o[1] = c32{r2 * (o[1].x - S * o[1].y), r2 * (o[1].y + S * o[1].x)};
+        o[2] = muli<S>(o[2]);
+        o[3] = c32{r2 * (-o[3].x - S * o[3].y), r2 * (-o[3].y + S * o[3].x)};
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            v[k] = add(e[k], o[k]);
+            v[k + 4] = sub(e[k], o[k]);
+        }
+    }
+};
+
+template <int S>
+struct Dft<16, S> {
+    static __device__ __forceinline__ void run(c32 *v)
+    {
+        // 4 x 4: inner DFT4 over n1 (stride 4), twiddle W16^{n2 k1}, outer DFT4 over n2.
+        const float c1 = 0.92387953251128675613f;  // cos(pi/8)
+        const float s1 = 0.38268343236508977173f;  // sin(pi/8)
+        const float r2 = 0.70710678118654752440f;
+        c32 t[4][4];
+#pragma unroll
+        for (int n2 = 0; n2 < 4; ++n2) {
+#pragma unroll
+            for (int n1 = 0; n1 < 4; ++n1) t[n2][n1] = v[4 * n1 + n2];
+            Dft<4, S>::run(t[n2]);
+        }
+        // twiddles W16^{S n2 k1}: angle = S 2 pi n2 k1 / 16
+        // n2 = 1: k1 = 1,2,3 -> (c1, S s1), (r2, S r2), (s1, S c1)
+        // n2 = 2: k1 = 1,2,3 -> (r2, S r2), (0, S), (-r2, S r2)
+        // n2 = 3: k1 = 1,2,3 -> (s1, S c1), (-r2, S r2), (-c1, -S s1)
+        const c32 w11 = c32{c1, S * s1}, w12 = c32{r2, S * r2}, w13 = c32{s1, S * c1};
+        const c32 w22 = c32{0.f, (float)S}, w23 = c32{-r2, S * r2};
+        const c32 w33 = c32{-c1, -S * s1};
+        t[1][1] = mul(t[1][1], w11);
+        t[1][2] = mul(t[1][2], w12);
+        t[1][3] = mul(t[1][3], w13);
+        t[2][1] = mul(t[2][1], w12);
+        t[2][2] = mul(t[2][2], w22);
+        t[2][3] = mul(t[2][3], w23);
+        t[3][1] = mul(t[3][1], w13);
+        t[3][2] = mul(t[3][2], w23);
+        t[3][3] = mul(t[3][3], w33);
+#pragma unroll
+        for (int k1 = 0; k1 < 4; ++k1) {
+            c32 u[4] = {t[0][k1], t[1][k1], t[2][k1], t[3][k1]};
+            Dft<4, S>::run(u);
+#pragma unroll
+            for (int k2 = 0; k2 < 4; ++k2) v[k1 + 4 * k2] = u[k2];
+        }
+    }
+};
+
+// ---------------------------------------------------------------- radix plan
+// Radices for a line of length L = 2^a * 3^b * 5^c: the power-of-two part in
+// ceil(a/4) stages of 2..16 with the bits spread evenly (512 -> 8,8,8;
+// 256 -> 16,16; 128 -> 16,8), then the factors 3 and 5.
+
+__host__ __device__ constexpr int ilog2c(int n) { return n <= 1 ? 0 : 1 + ilog2c(n / 2); }
+__host__ __device__ constexpr int pow2part(int n) { return (n % 2 == 0) ? 2 * pow2part(n / 2) : 1; }
+__host__ __device__ constexpr int nstages_pow2(int L) { return (ilog2c(pow2part(L)) + 3) / 4; }
+__host__ __device__ constexpr int count_factor(int n, int p) { return (n % p == 0 && n > 1) ? 1 + count_factor(n / p, p) : 0; }
+__host__ __device__ constexpr int nstages(int L)
+{
+    return nstages_pow2(L) + count_factor(L, 3) + count_factor(L, 5);
+}
+__host__ __device__ constexpr int radix_at(int L, int st)
+{
+    // power-of-two stages first
+    return st < nstages_pow2(L)
+               ? (1 << (ilog2c(pow2part(L)) / nstages_pow2(L) +
+                        (st < ilog2c(pow2part(L)) % nstages_pow2(L) ? 1 : 0)))
+               : (st < nstages_pow2(L) + count_factor(L, 3) ? 3 : 5);
+}
+__host__ __device__ constexpr int max_radix(int L, int st = 0)
+{
+    return st >= nstages(L) ? 1
+                            : (radix_at(L, st) > max_radix(L, st + 1) ? radix_at(L, st)
+                                                                      : max_radix(L, st + 1));
+}
+
+// ---------------------------------------------------------------- stage engine
+// Geometry of a group of lines in LDS.  LF (line-fast) selects the mapping of
+// butterfly index b to (line, j): LF = true -> line = b % NL (lines
+// interleaved, PS = NL, LS = 1); LF = false -> j = b % (L/R) (contiguous
+// lines, PS = 1).
+
+template <int L, int R, int NS, int S, int NL, int NT, bool LF>
+__device__ __forceinline__ void stockham_stage(c32 *buf, int nlines, int LS, int PS,
+                                               const c32 *tw, int tid)
+{
+    constexpr int Q = L / R;
+    constexpr int NBF = NL * Q;                 // butterflies if all lines are used
+    constexpr int NB = (NBF + NT - 1) / NT;     // per thread
+    const int nbf = nlines * Q;
+    c32 v[NB][R];
+#pragma unroll
+    for (int i = 0; i < NB; ++i) {
+        const int b = tid + i * NT;
+        if (b < nbf) {
+            const int l = LF ? (b % NL) : (b / Q);
+            const int j = LF ? (b / NL) : (b % Q);
+            const c32 *src = buf + l * LS + j * PS;
+#pragma unroll
+            for (int r = 0; r < R; ++r) v[i][r] = src[r * Q * PS];
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < NB; ++i) {
+        const int b = tid + i * NT;
+        if (b < nbf) {
+            const int l = LF ? (b % NL) : (b / Q);
+            const int j = LF ? (b / NL) : (b % Q);
+            const int k = j % NS;
+            if (NS > 1) {
+#pragma unroll
+                for (int r = 1; r < R; ++r) {
+                    c32 w = tw[r * k * (L / (NS * R))];
+                    if (S > 0) w = conjg(w);
+                    v[i][r] = mul(v[i][r], w);
+                }
+            }
+            Dft<R, S>::run(v[i]);
+            c32 *dst = buf + l * LS + ((j / NS) * NS * R + k) * PS;
+#pragma unroll
+            for (int r = 0; r < R; ++r) dst[r * NS * PS] = v[i][r];
+        }
+    }
+    __syncthreads();
+}
+
+template <int L, int S, int NL, int NT, bool LF, int ST = 0, int NS = 1>
+__device__ __forceinline__ void stockham(c32 *buf, int nlines, int LS, int PS, const c32 *tw,
+                                         int tid)
+{
+    if constexpr (NS < L) {
+        constexpr int R = radix_at(L, ST);
+        stockham_stage<L, R, NS, S, NL, NT, LF>(buf, nlines, LS, PS, tw, tid);
+        stockham<L, S, NL, NT, LF, ST + 1, NS * R>(buf, nlines, LS, PS, tw, tid);
+    }
+}
+
+}  // namespace lf2

@@ -1,0 +1,91 @@
+// lf2_internal.hpp -- argument blocks and launch entry points shared by the
+// host plan code and the kernel translation units (not part of the ABI).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lf2 {
+
+constexpr int kMaxBins = 4096;  // LDS histogram limit of the fused binning epilogue
+
+// Epilogue of a strided pass (applies to the last axis, k space, ncomp = 1).
+enum : int {
+    EPI_STORE = 1,    // write the transformed column back
+    EPI_PK = 2,       // accumulate w|F|^2 per bin after the forward transform
+    EPI_POISSON = 4,  // scale by -1/(N k^2) (FP64) and run the backward transform
+    EPI_PK_AFTER = 8  // accumulate after the Poisson scale instead (spectrum of phi)
+};
+
+// Description of mode (kx, ky, kz) -> tables, for the fused epilogues.
+struct ModeTables {
+    int nxk;               // k-space extent of dimension 0 (Nh or N0)
+    int n0;                // real-space N0 (weight rule)
+    int half;              // 1: r2c half spectrum weights, 0: c2c
+    const double *k2[3];   // per-axis k^2 contributions (FP64), NULL if unused
+    const int64_t *q[3];   // per-axis integer (nt L / N)^2
+    const int64_t *thresh; // nbins + 1 bin thresholds: smallest q of bin b
+    int nbins;
+    double qmax;
+    double scale_n;        // Poisson: factor 1/N applied with -1/k^2
+};
+
+struct XArgs {
+    const void *in;
+    void *out;
+    int64_t nrows;        // N1 * N2
+    int n1;               // rows per plane
+    // element offsets: base(y, z) = off + z * plane + y * row (units of the
+    // array's element: float for real arrays, complex for complex arrays)
+    int64_t in_off, in_row, in_plane;
+    int64_t out_off, out_row, out_plane;
+    const void *tw;       // FFT twiddles, length L (forward sign)
+    const void *tw_post;  // r2c/c2r: exp(-2 pi i k / N0), k = 0..N0/2
+    double *sumsq;        // optional per-block FP64 sum of squares of the real input
+                          // ([gridDim.x], r2c forward only)
+};
+
+struct SArgs {
+    const void *in;
+    void *out;
+    int64_t stride;      // elements between points of a column
+    int64_t ncols_inner; // C
+    int64_t outer;       // elements between outer column groups
+    int64_t ncols;       // total columns (O * C)
+    int epi;             // EPI_* flags
+    const void *tw;      // twiddles, length L
+    ModeTables mt;
+    double *partial;     // [gridDim.x][nbins + 1]
+};
+
+// Kernel launchers (return hipSuccess or the launch error).  `len` is the
+// transform length along the pass axis; nc the number of components.
+bool x_supported(int len, int nc);
+bool s_supported(int len);
+hipError_t launch_x_r2c(int m, int nc, const XArgs &a, hipStream_t s);
+hipError_t launch_x_c2r(int m, int nc, const XArgs &a, hipStream_t s);
+hipError_t launch_x_c2c(int len, int nc, int sign, const XArgs &a, hipStream_t s);
+hipError_t launch_strided(int len, int sign, const SArgs &a, int grid_cap, hipStream_t s,
+                          int *grid_used);
+
+// Setup and reduction kernels (FP64).
+hipError_t launch_twiddles(void *tw, int len, hipStream_t s);
+hipError_t launch_k2_table(double *dst, int n, int count, double dx, int discrete, hipStream_t s);
+hipError_t launch_q_table(int64_t *dst, int n, int count, int64_t lfac, hipStream_t s);
+hipError_t launch_thresholds(int64_t *dst, int nbins, int64_t qmax, hipStream_t s);
+hipError_t launch_shell_partials(const ModeTables &mt, int n1, int n2, double lscale,
+                                 double *partial_cnt, double *partial_k, int grid,
+                                 hipStream_t s);
+// out[b] = sum_g partial[g * width + b] in a fixed order, b < width.
+hipError_t launch_reduce_cols(const double *partial, int64_t grid, int width, double *out,
+                              hipStream_t s);
+hipError_t launch_pk_kspace(const void *F, int n1, int n2, const ModeTables &mt,
+                            double *partial, int grid, hipStream_t s);
+hipError_t launch_pk_finalize(const double *S, int nbins, const double *count, const double *sumk,
+                              double norm, double vscale, double kscale, double *pk,
+                              double *kmean, double *count_out, double *parseval,
+                              const double *sumsq, double inv_n, hipStream_t s);
+
+int x_rows_per_block(int len, int nc);
+int s_cols_per_block(int len);
+
+}  // namespace lf2

@@ -1,0 +1,416 @@
+// lf2_kernels.hpp -- pass kernels of the 3-D FFT (gfx950).
+//
+// x pass  : lines along dimension 0 are contiguous in memory.  A block loads
+//           RB rows (all components of each row) with coalesced loads,
+//           de-interleaves the components into LDS lines, runs the Stockham
+//           stages in LDS and stores coalesced.  r2c packs N0 reals into N0/2
+//           complex values, transforms and splits the result into Nh bins;
+//           c2r does the reverse.
+// strided : lines along dimension 1 or 2 have a large stride; consecutive
+//           columns are adjacent in memory.  A block takes a tile of B
+//           adjacent columns x L points, loads it row by row (B * 8 bytes
+//           contiguous per row), transforms the B columns in LDS (lanes walk
+//           adjacent columns, so LDS accesses are consecutive words) and
+//           stores the tile back.  This replaces the paper's rod transposes
+//           (the data never leaves its place; the tile is the transpose).
+//           Epilogues on the last axis: power-spectrum binning, the Poisson
+//           scale followed by the backward transform.
+#pragma once
+#include "lf2_device.hpp"
+#include "lf2_internal.hpp"
+
+namespace lf2 {
+
+constexpr int kXThreads = 256;
+constexpr int kSThreads = 256;
+
+// Rows per x-pass block: about 4096 complex values of LDS (32 KiB), at
+// most 256 rows.
+__host__ __device__ constexpr int x_rb(int L, int NC)
+{
+    return ((4096 / L) / NC) < 1 ? 1 : (((4096 / L) / NC) > 256 ? 256 : ((4096 / L) / NC));
+}
+// Columns per strided tile: 64 KiB of LDS at most, >= 128-byte row segments
+// up to L = 512.
+__host__ __device__ constexpr int s_b(int L)
+{
+    return L <= 128 ? 64 : L <= 256 ? 32 : L <= 512 ? 16 : L <= 1024 ? 8 : 4;
+}
+
+// Row base offsets of the RB rows of this block, in LDS.
+template <int RB>
+__device__ __forceinline__ void row_bases(int64_t *ib, int64_t *ob, const XArgs &a, int64_t r0,
+                                          int tid)
+{
+    for (int i = tid; i < RB; i += kXThreads) {
+        int64_t r = r0 + i;
+        if (r >= a.nrows) r = a.nrows - 1;
+        int64_t z = r / a.n1, y = r - z * a.n1;
+        ib[i] = a.in_off + z * a.in_plane + y * a.in_row;
+        ob[i] = a.out_off + z * a.out_plane + y * a.out_row;
+    }
+}
+
+// FP64 block sum, one value per block into dst[blockIdx.x].
+__device__ __forceinline__ void block_sum_f64(double v, double *dst, double *scratch)
+{
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (lane == 0) scratch[wid] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0;
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += scratch[w];
+        dst[blockIdx.x] = t;
+    }
+}
+
+// ------------------------------------------------------------------ r2c x pass
+template <int M, int NC>
+__global__ __launch_bounds__(kXThreads) void k_x_r2c(XArgs a)
+{
+    constexpr int NT = kXThreads;
+    constexpr int RB = x_rb(M, NC);
+    constexpr int NL = RB * NC;
+    constexpr int N0 = 2 * M;
+    constexpr int LP = M;
+    constexpr int NH = M + 1;
+    __shared__ c32 buf[NL * LP];
+    __shared__ c32 tw[M];
+    __shared__ c32 twp[NH];
+    __shared__ int64_t ib[RB], ob[RB];
+    __shared__ double red[NT / 64];
+    const int tid = threadIdx.x;
+    const c32 *gtw = (const c32 *)a.tw;
+    const c32 *gtp = (const c32 *)a.tw_post;
+    for (int i = tid; i < M; i += NT) tw[i] = gtw[i];
+    for (int i = tid; i < NH; i += NT) twp[i] = gtp[i];
+    const int64_t r0 = (int64_t)blockIdx.x * RB;
+    row_bases<RB>(ib, ob, a, r0, tid);
+    __syncthreads();
+    const float *in = (const float *)a.in;
+    float *fb = (float *)buf;
+    double ss = 0.0;
+    constexpr int NE = RB * N0 * NC;
+#pragma unroll 4
+    for (int i = 0; i < (NE + NT - 1) / NT; ++i) {
+        const int idx = tid + i * NT;
+        if (idx < NE) {
+            const int row = idx / (N0 * NC);
+            const int rem = idx - row * (N0 * NC);
+            const int x = rem / NC;
+            const int c = rem - x * NC;
+            float v = 0.f;
+            if (r0 + row < a.nrows) v = in[ib[row] + rem];
+            fb[(row * NC + c) * LP * 2 + x] = v;
+            ss += (double)v * (double)v;
+        }
+    }
+    if (a.sumsq) block_sum_f64(ss, a.sumsq, red);
+    __syncthreads();
+    stockham<M, -1, NL, NT, false>(buf, NL, LP, 1, tw, tid);
+    c32 *out = (c32 *)a.out;
+    constexpr int NO = RB * NH * NC;
+#pragma unroll 4
+    for (int i = 0; i < (NO + NT - 1) / NT; ++i) {
+        const int idx = tid + i * NT;
+        if (idx < NO) {
+            const int row = idx / (NH * NC);
+            const int rem = idx - row * (NH * NC);
+            const int k = rem / NC;
+            const int c = rem - k * NC;
+            if (r0 + row < a.nrows) {
+                const c32 *line = buf + (row * NC + c) * LP;
+                const c32 z = line[k == M ? 0 : k];
+                const c32 zc = conjg(line[k == 0 ? 0 : M - k]);
+                const c32 fe = scl(add(z, zc), 0.5f);
+                const c32 d = sub(z, zc);
+                const c32 fo = c32{0.5f * d.y, -0.5f * d.x};  // (z - zc) / (2i)
+                out[ob[row] + rem] = add(fe, mul(twp[k], fo));
+            }
+        }
+    }
+}
+
+// ------------------------------------------------------------------ c2r x pass
+template <int M, int NC>
+__global__ __launch_bounds__(kXThreads) void k_x_c2r(XArgs a)
+{
+    constexpr int NT = kXThreads;
+    constexpr int RB = x_rb(M, NC);
+    constexpr int NL = RB * NC;
+    constexpr int N0 = 2 * M;
+    constexpr int LP = M + 1;
+    constexpr int NH = M + 1;
+    __shared__ c32 buf[NL * LP];
+    __shared__ c32 tw[M];
+    __shared__ c32 twp[NH];
+    __shared__ int64_t ib[RB], ob[RB];
+    const int tid = threadIdx.x;
+    const c32 *gtw = (const c32 *)a.tw;
+    const c32 *gtp = (const c32 *)a.tw_post;
+    for (int i = tid; i < M; i += NT) tw[i] = gtw[i];
+    for (int i = tid; i < NH; i += NT) twp[i] = gtp[i];
+    const int64_t r0 = (int64_t)blockIdx.x * RB;
+    row_bases<RB>(ib, ob, a, r0, tid);
+    __syncthreads();
+    const c32 *in = (const c32 *)a.in;
+    constexpr int NI = RB * NH * NC;
+#pragma unroll 4
+    for (int i = 0; i < (NI + NT - 1) / NT; ++i) {
+        const int idx = tid + i * NT;
+        if (idx < NI) {
+            const int row = idx / (NH * NC);
+            const int rem = idx - row * (NH * NC);
+            const int k = rem / NC;
+            const int c = rem - k * NC;
+            c32 v = c32{0.f, 0.f};
+            if (r0 + row < a.nrows) v = in[ib[row] + rem];
+            buf[(row * NC + c) * LP + k] = v;
+        }
+    }
+    __syncthreads();
+    // Z[k] = (X[k] + conj X[M-k]) + i W^{-k} (X[k] - conj X[M-k]), k < M,
+    // with the imaginary parts of X[0] and X[M] dropped.
+    constexpr int NZ = NL * M;
+    constexpr int NZT = (NZ + NT - 1) / NT;
+    c32 zv[NZT];
+#pragma unroll
+    for (int i = 0; i < NZT; ++i) {
+        const int idx = tid + i * NT;
+        if (idx < NZ) {
+            const int l = idx / M;
+            const int k = idx - l * M;
+            const c32 *line = buf + l * LP;
+            c32 xk = line[k];
+            c32 xm = line[M - k];
+            if (k == 0) {
+                xk.y = 0.f;
+                xm.y = 0.f;
+            }
+            const c32 xmc = conjg(xm);
+            const c32 s = add(xk, xmc);
+            const c32 d = mul(conjg(twp[k]), sub(xk, xmc));
+            zv[i] = c32{s.x - d.y, s.y + d.x};  // s + i d
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < NZT; ++i) {
+        const int idx = tid + i * NT;
+        if (idx < NZ) {
+            const int l = idx / M;
+            const int k = idx - l * M;
+            buf[l * LP + k] = zv[i];
+        }
+    }
+    __syncthreads();
+    stockham<M, +1, NL, NT, false>(buf, NL, LP, 1, tw, tid);
+    float *out = (float *)a.out;
+    const float *fb = (const float *)buf;
+    constexpr int NE = RB * N0 * NC;
+#pragma unroll 4
+    for (int i = 0; i < (NE + NT - 1) / NT; ++i) {
+        const int idx = tid + i * NT;
+        if (idx < NE) {
+            const int row = idx / (N0 * NC);
+            const int rem = idx - row * (N0 * NC);
+            const int x = rem / NC;
+            const int c = rem - x * NC;
+            if (r0 + row < a.nrows) out[ob[row] + rem] = fb[(row * NC + c) * LP * 2 + x];
+        }
+    }
+}
+
+// ------------------------------------------------------------------ c2c x pass
+template <int L, int NC, int S>
+__global__ __launch_bounds__(kXThreads) void k_x_c2c(XArgs a)
+{
+    constexpr int NT = kXThreads;
+    constexpr int RB = x_rb(L, NC);
+    constexpr int NL = RB * NC;
+    constexpr int LP = L;
+    __shared__ c32 buf[NL * LP];
+    __shared__ c32 tw[L];
+    __shared__ int64_t ib[RB], ob[RB];
+    const int tid = threadIdx.x;
+    const c32 *gtw = (const c32 *)a.tw;
+    for (int i = tid; i < L; i += NT) tw[i] = gtw[i];
+    const int64_t r0 = (int64_t)blockIdx.x * RB;
+    row_bases<RB>(ib, ob, a, r0, tid);
+    __syncthreads();
+    const c32 *in = (const c32 *)a.in;
+    constexpr int NE = RB * L * NC;
+#pragma unroll 4
+    for (int i = 0; i < (NE + NT - 1) / NT; ++i) {
+        const int idx = tid + i * NT;
+        if (idx < NE) {
+            const int row = idx / (L * NC);
+            const int rem = idx - row * (L * NC);
+            const int x = rem / NC;
+            const int c = rem - x * NC;
+            c32 v = c32{0.f, 0.f};
+            if (r0 + row < a.nrows) v = in[ib[row] + rem];
+            buf[(row * NC + c) * LP + x] = v;
+        }
+    }
+    __syncthreads();
+    stockham<L, S, NL, NT, false>(buf, NL, LP, 1, tw, tid);
+    c32 *out = (c32 *)a.out;
+#pragma unroll 4
+    for (int i = 0; i < (NE + NT - 1) / NT; ++i) {
+        const int idx = tid + i * NT;
+        if (idx < NE) {
+            const int row = idx / (L * NC);
+            const int rem = idx - row * (L * NC);
+            const int x = rem / NC;
+            const int c = rem - x * NC;
+            if (r0 + row < a.nrows) out[ob[row] + rem] = buf[(row * NC + c) * LP + x];
+        }
+    }
+}
+
+// ------------------------------------------------------------------ binning
+// Exact bin of integer squared radius q: max{b <= nbins-1 : thresh[b] <= q},
+// thresh[b] = ceil(b^2 qmax / nbins^2).  The FP64 estimate is corrected by
+// integer comparisons, so the result never depends on rounding.
+__device__ __forceinline__ int bin_of(int64_t q, const int64_t *thresh, int nbins, double inv_qmax)
+{
+    int b = (int)((double)nbins * sqrt((double)q * inv_qmax));
+    b = b < 0 ? 0 : (b > nbins - 1 ? nbins - 1 : b);
+    while (b + 1 < nbins && thresh[b + 1] <= q) ++b;
+    while (b > 0 && thresh[b] > q) --b;
+    return b;
+}
+
+// ------------------------------------------------------------------ strided pass
+template <int L, int S>
+__global__ __launch_bounds__(kSThreads) void k_strided(SArgs a)
+{
+    constexpr int NT = kSThreads;
+    constexpr int B = s_b(L);
+    constexpr int RPT = NT / B;                 // rows covered by one sweep of the block
+    constexpr int NIT = (L + RPT - 1) / RPT;    // sweeps per tile
+    __shared__ c32 buf[L * B];
+    __shared__ c32 tw[L];
+    extern __shared__ double dyn[];              // hist[nbins + 1], thresh[nbins + 1]
+    const int tid = threadIdx.x;
+    const int col = tid % B;
+    const int rg = tid / B;
+    const c32 *gtw = (const c32 *)a.tw;
+    for (int i = tid; i < L; i += NT) tw[i] = gtw[i];
+    const bool pk = (a.epi & (EPI_PK | EPI_PK_AFTER)) != 0;
+    const int nb = a.mt.nbins;
+    double *hist = dyn;
+    int64_t *thresh = (int64_t *)(dyn + (nb + 1));
+    if (pk) {
+        for (int i = tid; i <= nb; i += NT) {
+            hist[i] = 0.0;
+            thresh[i] = a.mt.thresh[i];
+        }
+    }
+    __syncthreads();
+
+    const c32 *in = (const c32 *)a.in;
+    c32 *out = (c32 *)a.out;
+    const int64_t ntiles = (a.ncols + B - 1) / B;
+    // XCD-aware walk: the chip hands consecutive block ids to its XCDs in
+    // turn, so block b works on a contiguous chunk of tiles owned by XCD
+    // (b mod NX); neighbouring tiles then share that XCD's L2.
+    const int G = gridDim.x;
+    const int NX = G < 8 ? G : 8;
+    const int xcd = blockIdx.x % NX, lb = blockIdx.x / NX;
+    const int nbx = (G - xcd + NX - 1) / NX;
+    const int64_t ch = (ntiles + NX - 1) / NX;
+    const int64_t t0 = (int64_t)xcd * ch;
+    const int64_t t1 = t0 + ch < ntiles ? t0 + ch : ntiles;
+    const double inv_qmax = 1.0 / a.mt.qmax;
+
+    for (int64_t t = t0 + lb; t < t1; t += nbx) {
+        const int64_t f = t * B + col;
+        const bool valid = f < a.ncols;
+        int64_t base = 0;
+        if (valid) {
+            const int64_t o = f / a.ncols_inner;
+            base = o * a.outer + (f - o * a.ncols_inner);
+        }
+#pragma unroll
+        for (int i = 0; i < NIT; ++i) {
+            const int row = rg + i * RPT;
+            if (row < L) {
+                c32 v = c32{0.f, 0.f};
+                if (valid) v = in[base + (int64_t)row * a.stride];
+                buf[row * B + col] = v;
+            }
+        }
+        __syncthreads();
+        stockham<L, S, B, NT, true>(buf, B, 1, B, tw, tid);
+
+        if (a.epi & (EPI_PK | EPI_POISSON | EPI_PK_AFTER)) {
+            // Epilogue on the last axis: thread (col, rg) walks a contiguous run
+            // of kz so that consecutive modes mostly share a bin.
+            constexpr int EP = (L + RPT - 1) / RPT;
+            const int kx = valid ? (int)(f % a.mt.nxk) : 0;
+            const int ky = valid ? (int)(f / a.mt.nxk) : 0;
+            const double wgt =
+                (a.mt.half && !(kx == 0 || 2 * kx == a.mt.n0)) ? 2.0 : 1.0;
+            double k2xy = 0.0;
+            int64_t qxy = 0;
+            if (valid && (a.epi & EPI_POISSON)) k2xy = a.mt.k2[0][kx] + a.mt.k2[1][ky];
+            if (valid && pk) qxy = a.mt.q[0][kx] + a.mt.q[1][ky];
+            int cur = -1;
+            double acc = 0.0;
+            for (int e = 0; e < EP; ++e) {
+                const int kz = rg * EP + e;
+                if (!valid || kz >= L) break;
+                c32 v = buf[kz * B + col];
+                const bool zero = (kx == 0 && ky == 0 && kz == 0);
+                int b = nb;
+                if (pk && !zero) b = bin_of(qxy + a.mt.q[2][kz], thresh, nb, inv_qmax);
+                if (a.epi & EPI_PK) {
+                    const double p = wgt * ((double)v.x * v.x + (double)v.y * v.y);
+                    if (b != cur) {
+                        if (cur >= 0) atomicAdd(&hist[cur], acc);
+                        cur = b;
+                        acc = 0.0;
+                    }
+                    acc += p;
+                }
+                if (a.epi & EPI_POISSON) {
+                    const double sc = zero ? 0.0 : -a.mt.scale_n / (k2xy + a.mt.k2[2][kz]);
+                    v = c32{(float)((double)v.x * sc), (float)((double)v.y * sc)};
+                    buf[kz * B + col] = v;
+                }
+                if (a.epi & EPI_PK_AFTER) {
+                    const double p = wgt * ((double)v.x * v.x + (double)v.y * v.y);
+                    if (b != cur) {
+                        if (cur >= 0) atomicAdd(&hist[cur], acc);
+                        cur = b;
+                        acc = 0.0;
+                    }
+                    acc += p;
+                }
+            }
+            if (cur >= 0) atomicAdd(&hist[cur], acc);
+            __syncthreads();
+            if constexpr (S < 0) {
+                if (a.epi & EPI_POISSON) stockham<L, +1, B, NT, true>(buf, B, 1, B, tw, tid);
+            }
+        }
+
+        if (a.epi & EPI_STORE) {
+#pragma unroll
+            for (int i = 0; i < NIT; ++i) {
+                const int row = rg + i * RPT;
+                if (row < L && valid) out[base + (int64_t)row * a.stride] = buf[row * B + col];
+            }
+        }
+        __syncthreads();
+    }
+    if (pk) {
+        __syncthreads();
+        for (int i = tid; i <= nb; i += NT) a.partial[(int64_t)blockIdx.x * (nb + 1) + i] = hist[i];
+    }
+}
+
+}  // namespace lf2

@@ -1,0 +1,256 @@
+// lf2_kmisc.hip -- plan-time tables (FP64 on the device) and the FP64
+// reductions of the power spectrum.
+#include "lf2_kernels.hpp"
+
+namespace lf2 {
+
+// exp(-2 pi i m / period) for m in [0, count), evaluated in FP64 with the
+// exact integer m (< period) and rounded once to FP32.
+__global__ void k_twiddles(c32 *tw, int count, int period)
+{
+    const int m = blockIdx.x * blockDim.x + threadIdx.x;
+    if (m < count) {
+        double sn, cs;
+        sincospi(2.0 * (double)m / (double)period, &sn, &cs);
+        tw[m] = c32{(float)cs, (float)(-sn)};
+    }
+}
+
+hipError_t launch_twiddles(void *tw, int len, hipStream_t s)
+{
+    // len > 0: table of `len` entries with period len; len < 0: r2c post
+    // table of N0/2 + 1 entries with period N0 = -len.
+    const int period = len > 0 ? len : -len;
+    const int count = len > 0 ? len : period / 2 + 1;
+    hipLaunchKernelGGL(k_twiddles, dim3((count + 255) / 256), dim3(256), 0, s, (c32 *)tw, count,
+                       period);
+    return hipGetLastError();
+}
+
+// Per-axis k^2 contribution for index i of an axis of extent n:
+//   continuous: (2 pi nt / (n dx))^2, nt the signed wavenumber;
+//   discrete:   (2/dx)^2 sin^2(pi i / n).
+__global__ void k_k2_table(double *dst, int n, int count, double dx, int discrete)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count) {
+        double v;
+        if (discrete) {
+            const double sn = sinpi((double)i / (double)n);
+            v = (4.0 / (dx * dx)) * sn * sn;
+        } else {
+            const int nt = (2 * i < n) ? i : i - n;
+            const double a = 6.283185307179586476925286766559 * (double)nt / ((double)n * dx);
+            v = a * a;
+        }
+        dst[i] = v;
+    }
+}
+
+hipError_t launch_k2_table(double *dst, int n, int count, double dx, int discrete, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_k2_table, dim3((count + 255) / 256), dim3(256), 0, s, dst, n, count, dx,
+                       discrete);
+    return hipGetLastError();
+}
+
+// (nt * lfac)^2 for the signed wavenumber nt of index i.
+__global__ void k_q_table(int64_t *dst, int n, int count, int64_t lfac)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count) {
+        const int64_t nt = (2 * i < n) ? i : i - n;
+        dst[i] = (nt * lfac) * (nt * lfac);
+    }
+}
+
+hipError_t launch_q_table(int64_t *dst, int n, int count, int64_t lfac, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_q_table, dim3((count + 255) / 256), dim3(256), 0, s, dst, n, count, lfac);
+    return hipGetLastError();
+}
+
+// thresh[b] = ceil(b^2 qmax / nbins^2), b = 0..nbins: the smallest integer q
+// with b^2 qmax <= nbins^2 q.
+__global__ void k_thresholds(int64_t *dst, int nbins, int64_t qmax)
+{
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b <= nbins) {
+        const int64_t d = (int64_t)nbins * nbins;
+        const int64_t num = (int64_t)b * b * qmax;
+        dst[b] = (num + d - 1) / d;
+    }
+}
+
+hipError_t launch_thresholds(int64_t *dst, int nbins, int64_t qmax, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_thresholds, dim3((nbins + 1 + 255) / 256), dim3(256), 0, s, dst, nbins,
+                       qmax);
+    return hipGetLastError();
+}
+
+// Lattice-only shell sums: sum w and sum w sqrt(q) per bin over all modes
+// except the zero mode, as per-block partials.
+__global__ void k_shell_partials(ModeTables mt, int n1, int n2, double *pc, double *pkk)
+{
+    extern __shared__ double sh[];
+    const int nb = mt.nbins;
+    double *hc = sh;
+    double *hk = sh + nb;
+    int64_t *th = (int64_t *)(sh + 2 * nb);
+    for (int i = threadIdx.x; i < nb; i += blockDim.x) {
+        hc[i] = 0.0;
+        hk[i] = 0.0;
+    }
+    for (int i = threadIdx.x; i <= nb; i += blockDim.x) th[i] = mt.thresh[i];
+    __syncthreads();
+    const double inv_qmax = 1.0 / mt.qmax;
+    const int64_t total = (int64_t)mt.nxk * n1 * n2;
+    for (int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; m < total;
+         m += (int64_t)gridDim.x * blockDim.x) {
+        if (m == 0) continue;
+        const int kx = (int)(m % mt.nxk);
+        const int64_t r = m / mt.nxk;
+        const int ky = (int)(r % n1);
+        const int kz = (int)(r / n1);
+        const int64_t q = mt.q[0][kx] + mt.q[1][ky] + mt.q[2][kz];
+        const int b = bin_of(q, th, nb, inv_qmax);
+        const double w = (mt.half && !(kx == 0 || 2 * kx == mt.n0)) ? 2.0 : 1.0;
+        atomicAdd(&hc[b], w);
+        atomicAdd(&hk[b], w * sqrt((double)q));
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < nb; i += blockDim.x) {
+        pc[(int64_t)blockIdx.x * nb + i] = hc[i];
+        pkk[(int64_t)blockIdx.x * nb + i] = hk[i];
+    }
+}
+
+hipError_t launch_shell_partials(const ModeTables &mt, int n1, int n2, double /*lscale*/,
+                                 double *partial_cnt, double *partial_k, int grid, hipStream_t s)
+{
+    const size_t shm = (size_t)mt.nbins * 16 + (size_t)(mt.nbins + 1) * 8;
+    hipLaunchKernelGGL(k_shell_partials, dim3(grid), dim3(256), shm, s, mt, n1, n2, partial_cnt,
+                       partial_k);
+    return hipGetLastError();
+}
+
+// Fixed-order column sums: out[b] = sum over g of partial[g * width + b].
+// One block per column; thread t sums g = t, t + 256, ... in order, then a
+// fixed tree combines the 256 thread sums, so the result is reproducible.
+__global__ __launch_bounds__(256) void k_reduce_cols(const double *partial, int64_t grid,
+                                                     int width, double *out)
+{
+    __shared__ double red[256];
+    const int b = blockIdx.x;
+    double s = 0.0;
+    for (int64_t g = threadIdx.x; g < grid; g += 256) s += partial[g * width + b];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[b] = red[0];
+}
+
+hipError_t launch_reduce_cols(const double *partial, int64_t grid, int width, double *out,
+                              hipStream_t s)
+{
+    hipLaunchKernelGGL(k_reduce_cols, dim3(width), dim3(256), 0, s, partial, grid, width, out);
+    return hipGetLastError();
+}
+
+// Power spectrum of a spectrum already in k space ([n2][n1][nxk], ncomp 1).
+// Tile of 64 adjacent (kx, ky) columns; thread (col, rg) walks a contiguous
+// run of kz, flushing its running bin sum to the LDS histogram when the bin
+// changes.  Partials [grid][nbins + 1] (slot nbins = zero mode).
+__global__ __launch_bounds__(256) void k_pk_kspace(const c32 *F, int n1, int n2, ModeTables mt,
+                                                   double *partial)
+{
+    constexpr int B = 64, NT = 256, RG = NT / B;
+    extern __shared__ double sh[];
+    const int nb = mt.nbins;
+    double *hist = sh;
+    int64_t *th = (int64_t *)(sh + nb + 1);
+    for (int i = threadIdx.x; i <= nb; i += NT) {
+        hist[i] = 0.0;
+        th[i] = mt.thresh[i];
+    }
+    __syncthreads();
+    const double inv_qmax = 1.0 / mt.qmax;
+    const int64_t ncols = (int64_t)mt.nxk * n1;
+    const int64_t ntiles = (ncols + B - 1) / B;
+    const int col = threadIdx.x % B, rg = threadIdx.x / B;
+    const int ep = (n2 + RG - 1) / RG;
+    for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        const int64_t f = t * B + col;
+        if (f >= ncols) continue;
+        const int kx = (int)(f % mt.nxk), ky = (int)(f / mt.nxk);
+        const double w = (mt.half && !(kx == 0 || 2 * kx == mt.n0)) ? 2.0 : 1.0;
+        const int64_t qxy = mt.q[0][kx] + mt.q[1][ky];
+        int cur = -1;
+        double acc = 0.0;
+        for (int e = 0; e < ep; ++e) {
+            const int kz = rg * ep + e;
+            if (kz >= n2) break;
+            const c32 v = F[(int64_t)kz * ncols + f];
+            const bool zero = (kx == 0 && ky == 0 && kz == 0);
+            const int b = zero ? nb : bin_of(qxy + mt.q[2][kz], th, nb, inv_qmax);
+            const double p = w * ((double)v.x * v.x + (double)v.y * v.y);
+            if (b != cur) {
+                if (cur >= 0) atomicAdd(&hist[cur], acc);
+                cur = b;
+                acc = 0.0;
+            }
+            acc += p;
+        }
+        if (cur >= 0) atomicAdd(&hist[cur], acc);
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i <= nb; i += NT) partial[(int64_t)blockIdx.x * (nb + 1) + i] = hist[i];
+}
+
+hipError_t launch_pk_kspace(const void *F, int n1, int n2, const ModeTables &mt, double *partial,
+                            int grid, hipStream_t s)
+{
+    const size_t shm = (size_t)(mt.nbins + 1) * 16;
+    hipLaunchKernelGGL(k_pk_kspace, dim3(grid), dim3(256), shm, s, (const c32 *)F, n1, n2, mt,
+                       partial);
+    return hipGetLastError();
+}
+
+// From the bin sums S[0..nbins] (S[nbins] = zero mode) and the lattice
+// shell table: pk = norm * vscale * S_b / count_b, kmean = kscale * sumk_b /
+// count_b (0 for empty bins); parseval = { *sumsq, inv_n * vscale *
+// sum_b S_b including the zero mode }.
+__global__ void k_pk_finalize(const double *S, int nbins, const double *count, const double *sumk,
+                              double norm, double vscale, double kscale, double *pk,
+                              double *kmean, double *count_out, double *parseval,
+                              const double *sumsq, double inv_n)
+{
+    for (int b = threadIdx.x; b < nbins; b += blockDim.x) {
+        const double c = count[b];
+        if (pk) pk[b] = c > 0 ? norm * vscale * S[b] / c : 0.0;
+        if (kmean) kmean[b] = c > 0 ? kscale * sumk[b] / c : 0.0;
+        if (count_out) count_out[b] = c;
+    }
+    if (parseval && threadIdx.x == 0) {
+        double t = 0.0;
+        for (int b = 0; b <= nbins; ++b) t += S[b];
+        parseval[0] = sumsq ? *sumsq : 0.0;
+        parseval[1] = inv_n * vscale * t;
+    }
+}
+
+hipError_t launch_pk_finalize(const double *S, int nbins, const double *count, const double *sumk,
+                              double norm, double vscale, double kscale, double *pk,
+                              double *kmean, double *count_out, double *parseval,
+                              const double *sumsq, double inv_n, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_pk_finalize, dim3(1), dim3(256), 0, s, S, nbins, count, sumk, norm,
+                       vscale, kscale, pk, kmean, count_out, parseval, sumsq, inv_n);
+    return hipGetLastError();
+}
+
+}  // namespace lf2

@@ -1,0 +1,46 @@
+// lf2_ks.hip -- instantiations and launcher of the strided (y / z) pass.
+#include "lf2_kernels.hpp"
+#include "lf2_lengths.hpp"
+
+namespace lf2 {
+
+bool s_supported(int len)
+{
+    switch (len) {
+#define LF2_CASE(L) case L:
+        LF2_LENGTHS(LF2_CASE)
+#undef LF2_CASE
+        return true;
+    default:
+        return false;
+    }
+}
+
+int s_cols_per_block(int len) { return s_b(len); }
+
+hipError_t launch_strided(int len, int sign, const SArgs &a, int grid_cap, hipStream_t s,
+                          int *grid_used)
+{
+    const bool pk = (a.epi & (EPI_PK | EPI_PK_AFTER)) != 0;
+    const size_t shm = pk ? (size_t)(a.mt.nbins + 1) * 16 : 0;
+#define LF2_CASE(L)                                                                          \
+    case L: {                                                                                \
+        int64_t ntiles = (a.ncols + s_b(L) - 1) / s_b(L);                                    \
+        int g = (int)(ntiles < grid_cap ? ntiles : grid_cap);                                \
+        if (g < 1) g = 1;                                                                    \
+        if (grid_used) *grid_used = g;                                                       \
+        if (sign < 0)                                                                        \
+            hipLaunchKernelGGL((k_strided<L, -1>), dim3(g), dim3(kSThreads), shm, s, a);     \
+        else                                                                                 \
+            hipLaunchKernelGGL((k_strided<L, 1>), dim3(g), dim3(kSThreads), shm, s, a);      \
+        return hipGetLastError();                                                            \
+    }
+    switch (len) {
+        LF2_LENGTHS(LF2_CASE)
+    default:
+        return hipErrorInvalidValue;
+    }
+#undef LF2_CASE
+}
+
+}  // namespace lf2

@@ -1,0 +1,102 @@
+// lf2_kx.hip -- instantiations and launchers of the x-pass kernels.
+// LF2_KX_PART selects the family compiled by this translation unit
+// (0: r2c, 1: c2r, 2: c2c) so that the families build in parallel.
+#include "lf2_kernels.hpp"
+#include "lf2_lengths.hpp"
+
+namespace lf2 {
+
+#ifndef LF2_KX_PART
+#define LF2_KX_PART 0
+#endif
+
+static inline unsigned x_grid(int64_t nrows, int rb) { return (unsigned)((nrows + rb - 1) / rb); }
+
+#if LF2_KX_PART == 0
+bool x_supported(int len, int nc)
+{
+    if (nc != 1 && nc != 3) return false;
+    switch (len) {
+#define LF2_CASE(L) case L:
+        LF2_LENGTHS(LF2_CASE)
+#undef LF2_CASE
+        return true;
+    default:
+        return false;
+    }
+}
+
+int x_rows_per_block(int len, int nc) { return x_rb(len, nc); }
+
+hipError_t launch_x_r2c(int m, int nc, const XArgs &a, hipStream_t s)
+{
+#define LF2_CASE(L)                                                                          \
+    case L:                                                                                  \
+        if (nc == 1)                                                                         \
+            hipLaunchKernelGGL((k_x_r2c<L, 1>), dim3(x_grid(a.nrows, x_rb(L, 1))),           \
+                               dim3(kXThreads), 0, s, a);                                    \
+        else                                                                                 \
+            hipLaunchKernelGGL((k_x_r2c<L, 3>), dim3(x_grid(a.nrows, x_rb(L, 3))),           \
+                               dim3(kXThreads), 0, s, a);                                    \
+        return hipGetLastError();
+    switch (m) {
+        LF2_LENGTHS(LF2_CASE)
+    default:
+        return hipErrorInvalidValue;
+    }
+#undef LF2_CASE
+}
+#endif
+
+#if LF2_KX_PART == 1
+hipError_t launch_x_c2r(int m, int nc, const XArgs &a, hipStream_t s)
+{
+#define LF2_CASE(L)                                                                          \
+    case L:                                                                                  \
+        if (nc == 1)                                                                         \
+            hipLaunchKernelGGL((k_x_c2r<L, 1>), dim3(x_grid(a.nrows, x_rb(L, 1))),           \
+                               dim3(kXThreads), 0, s, a);                                    \
+        else                                                                                 \
+            hipLaunchKernelGGL((k_x_c2r<L, 3>), dim3(x_grid(a.nrows, x_rb(L, 3))),           \
+                               dim3(kXThreads), 0, s, a);                                    \
+        return hipGetLastError();
+    switch (m) {
+        LF2_LENGTHS(LF2_CASE)
+    default:
+        return hipErrorInvalidValue;
+    }
+#undef LF2_CASE
+}
+#endif
+
+#if LF2_KX_PART == 2
+hipError_t launch_x_c2c(int len, int nc, int sign, const XArgs &a, hipStream_t s)
+{
+#define LF2_CASE(L)                                                                          \
+    case L:                                                                                  \
+        if (sign < 0) {                                                                      \
+            if (nc == 1)                                                                     \
+                hipLaunchKernelGGL((k_x_c2c<L, 1, -1>), dim3(x_grid(a.nrows, x_rb(L, 1))),   \
+                                   dim3(kXThreads), 0, s, a);                                \
+            else                                                                             \
+                hipLaunchKernelGGL((k_x_c2c<L, 3, -1>), dim3(x_grid(a.nrows, x_rb(L, 3))),   \
+                                   dim3(kXThreads), 0, s, a);                                \
+        } else {                                                                             \
+            if (nc == 1)                                                                     \
+                hipLaunchKernelGGL((k_x_c2c<L, 1, 1>), dim3(x_grid(a.nrows, x_rb(L, 1))),    \
+                                   dim3(kXThreads), 0, s, a);                                \
+            else                                                                             \
+                hipLaunchKernelGGL((k_x_c2c<L, 3, 1>), dim3(x_grid(a.nrows, x_rb(L, 3))),    \
+                                   dim3(kXThreads), 0, s, a);                                \
+        }                                                                                    \
+        return hipGetLastError();
+    switch (len) {
+        LF2_LENGTHS(LF2_CASE)
+    default:
+        return hipErrorInvalidValue;
+    }
+#undef LF2_CASE
+}
+#endif
+
+}  // namespace lf2

@@ -1,0 +1,70 @@
+"""C-ABI checks that need no GPU: the library loads, exports every function
+include/lf2.h declares, and rejects bad arguments before any HIP call."""
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_functions():
+    text = open(os.path.join(ROOT, "include", "lf2.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(lf2_[a-z0-9_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_1508_05610_amd import _lib
+    return _lib
+
+
+def test_exports_every_declared_symbol(lib):
+    so = lib.load()
+    names = header_functions()
+    assert "lf2_fft_plan" in names and "lf2_poisson_solve" in names
+    for n in names:
+        assert hasattr(so, n), f"{n} declared in lf2.h but not exported"
+    # the binding covers the same names
+    assert set(names) <= set(lib.exported_names())
+
+
+def test_version_and_status_strings(lib):
+    assert "gfx950" in lib.lf2_version()
+    assert lib.status_string(-2) == "LF2_ERR_UNSUPPORTED"
+    assert lib.status_string(0) == "LF2_OK"
+
+
+@pytest.mark.parametrize("sizes,halo,ncomp,kind,dim,expect", [
+    ((32, 32, 32), 0, 1, 0, 2, -2),          # 2-d lattices have no FFT
+    ((32, 32, 32), -1, 1, 0, 3, -1),         # negative halo
+    ((32, 32, 32), 0, 0, 0, 3, -1),          # ncomp < 1
+    ((0, 32, 32), 0, 1, 0, 3, -1),           # empty extent
+    ((33, 32, 32), 0, 1, 1, 3, -2),          # prime factor 11
+    ((14, 32, 32), 0, 1, 0, 3, -2),          # prime factor 7
+    ((15, 32, 32), 0, 1, 1, 3, -2),          # both 3 and 5 in one extent
+    ((31, 32, 32), 0, 1, 0, 3, -2),          # odd N0 for r2c
+    ((32, 32, 32), 0, 2, 0, 3, -2),          # two components: no kernel in this build
+    ((32, 32, 32), 0, 1, 7, 3, -1),          # bad kind
+    ((4096, 32, 32), 0, 1, 1, 3, -2),        # line longer than the compiled kernels
+])
+def test_plan_validation(lib, sizes, halo, ncomp, kind, dim, expect):
+    st = lib.lf2_fft_plan_status(sizes, halo, ncomp, kind, dim=dim)
+    assert st == expect, (st, lib.last_error())
+    assert lib.last_error()
+
+
+def test_null_plan_calls(lib):
+    so = lib.load()
+    assert so.lf2_fft_execute(None, -1, None, None, None) == lib.LF2_ERR_INVALID_ARG
+    assert so.lf2_poisson_solve(None, None, None, 1.0, 0, 0, None, None, None, None, None) == -1
+    assert so.lf2_power_spectrum(None, None, 0, 8, 1.0, None, None, None, None) == -1
+    assert so.lf2_plan_destroy(None) == -1
+    assert so.lf2_fft_plan(None, None, 1, 0, 0) == -1
+
+
+def test_python_binding_raises(lib):
+    with pytest.raises(lib.LF2Error) as ei:
+        lib.lf2_fft_plan((7, 8, 8), 0, 1, 0)
+    assert ei.value.status == lib.LF2_ERR_UNSUPPORTED

@@ -1,0 +1,167 @@
+"""GPU parity of the transforms against the FP64 oracle, through the C ABI.
+
+Gate: relative L2 error <= 1e-5 * log2(N) (N = lattice points); the max
+error relative to the largest oracle value is reported beside it.  Inputs
+are the same seeded float32 values on both sides (the oracle promotes them
+to float64).
+"""
+import numpy as np
+import pytest
+
+import oracle
+from gpu_helpers import complex_field, real_field, rel_l2, rel_max, tol
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def lf2():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1508_05610_amd as m
+    m.load()
+    return m
+
+
+def dev():
+    return torch.device("cuda:0")
+
+
+R2C_SHAPES = [(32, 32, 32), (8, 8, 8), (16, 12, 10), (64, 48, 40), (2, 4, 6), (96, 20, 12),
+              (160, 6, 10), (128, 96, 80), (6, 256, 5), (256, 3, 64), (384, 16, 8),
+              (10, 24, 192), (512, 8, 4), (4, 512, 4), (4, 4, 512), (1024, 2, 2), (2, 1, 1)]
+
+
+def report(name, shape, err, errmax):
+    print(f"[{name} {shape}] rel-L2 {err:.3e} max {errmax:.3e} tol {tol(shape):.2e}", flush=True)
+
+
+@pytest.mark.parametrize("shape", R2C_SHAPES)
+def test_r2c_forward(lf2, shape):
+    print(f"case r2c_forward {shape}", flush=True)
+    dense, _ = real_field(shape, seed=1)
+    f = dense[..., 0]
+    plan = lf2.Plan(shape, lf2.LF2_R2C)
+    F = plan.forward(torch.from_numpy(f).to(dev()))
+    torch.cuda.synchronize()
+    ref = oracle.r2c(f.astype(np.float64))
+    got = F.cpu().numpy().astype(np.complex128)
+    e, em = rel_l2(got, ref), rel_max(got, ref)
+    report("r2c", shape, e, em)
+    assert e <= tol(shape)
+
+
+@pytest.mark.parametrize("shape", R2C_SHAPES)
+def test_c2r_backward(lf2, shape):
+    print(f"case c2r_backward {shape}", flush=True)
+    n0 = shape[0]
+    dense, _ = real_field(shape, seed=2)
+    H = oracle.r2c(dense[..., 0].astype(np.float64)).astype(np.complex64)
+    plan = lf2.Plan(shape, lf2.LF2_R2C)
+    Hd = torch.from_numpy(H).to(dev())
+    Hkeep = Hd.clone()
+    out = plan.backward(Hd)
+    torch.cuda.synchronize()
+    ref = oracle.c2r(H.astype(np.complex128), n0)
+    got = out.cpu().numpy().astype(np.float64)
+    e, em = rel_l2(got, ref), rel_max(got, ref)
+    report("c2r", shape, e, em)
+    assert e <= tol(shape)
+    assert torch.equal(Hd, Hkeep), "c2r modified its input"
+
+
+def test_c2r_non_hermitian_reprojection(lf2):
+    """c2r of an arbitrary half spectrum: the Re-projection the oracle defines."""
+    shape = (16, 12, 10)
+    rng = np.random.default_rng(3)
+    G = (rng.standard_normal((10, 12, 9)) + 1j * rng.standard_normal((10, 12, 9))).astype(np.complex64)
+    plan = lf2.Plan(shape, lf2.LF2_R2C)
+    out = plan.backward(torch.from_numpy(G).to(dev()))
+    torch.cuda.synchronize()
+    ref = oracle.c2r(G.astype(np.complex128), 16)
+    assert rel_l2(out.cpu().numpy(), ref) <= tol(shape)
+
+
+C2C_SHAPES = [(32, 32, 32), (8, 8, 8), (12, 10, 6), (64, 48, 40), (3, 5, 4), (160, 12, 6),
+              (512, 4, 4), (4, 4, 512), (1, 1, 16), (16, 1, 1)]
+
+
+@pytest.mark.parametrize("shape", C2C_SHAPES)
+@pytest.mark.parametrize("ncomp", [1, 3])
+@pytest.mark.parametrize("direction", [-1, 1])
+def test_c2c(lf2, shape, ncomp, direction):
+    print(f"case c2c {shape} ncomp={ncomp} dir={direction}", flush=True)
+    z = complex_field(shape, seed=4, ncomp=ncomp)
+    plan = lf2.Plan(shape, lf2.LF2_C2C, ncomp=ncomp)
+    zin = torch.from_numpy(z if ncomp > 1 else z[..., 0]).to(dev())
+    out = plan.forward(zin) if direction < 0 else plan.backward(zin)
+    torch.cuda.synchronize()
+    got = out.cpu().numpy()
+    if ncomp == 1:
+        got = got[..., None]
+    for c in range(ncomp):
+        ref = oracle.c2c(z[..., c].astype(np.complex128), direction)
+        e, em = rel_l2(got[..., c], ref), rel_max(got[..., c], ref)
+        report(f"c2c comp{c} dir{direction}", shape, e, em)
+        assert e <= tol(shape)
+
+
+@pytest.mark.parametrize("shape", [(16, 12, 10), (32, 32, 32)])
+@pytest.mark.parametrize("halo", [1, 2])
+def test_halo_matches_dense(lf2, shape, halo):
+    """Halo sites (set to NaN) are never read; the interior result equals the dense one."""
+    print(f"case halo {shape} h={halo}", flush=True)
+    dense, pad = real_field(shape, seed=5, halo=halo)
+    p0 = lf2.Plan(shape, lf2.LF2_R2C)
+    ph = lf2.Plan(shape, lf2.LF2_R2C, halo=halo)
+    F0 = p0.forward(torch.from_numpy(dense[..., 0]).to(dev()))
+    Fh = ph.forward(torch.from_numpy(pad[..., 0]).to(dev()))
+    torch.cuda.synchronize()
+    assert torch.equal(F0, Fh)
+    # backward writes the interior only
+    out = torch.full(ph.x_shape, 7.0, dtype=torch.float32, device=dev())
+    ph.backward(Fh, out=out)
+    ref = p0.backward(F0)
+    torch.cuda.synchronize()
+    h = halo
+    o = out.cpu().numpy()
+    n0, n1, n2 = shape
+    assert np.array_equal(o[h:h + n2, h:h + n1, h:h + n0], ref.cpu().numpy())
+    mask = np.ones(o.shape, bool)
+    mask[h:h + n2, h:h + n1, h:h + n0] = False
+    assert np.all(o[mask] == 7.0)
+
+
+def test_aos_three_components_equal_scalar(lf2):
+    shape = (32, 24, 20)
+    z = complex_field(shape, seed=6, ncomp=3)
+    p3 = lf2.Plan(shape, lf2.LF2_C2C, ncomp=3)
+    p1 = lf2.Plan(shape, lf2.LF2_C2C, ncomp=1)
+    F3 = p3.forward(torch.from_numpy(z).to(dev()))
+    for c in range(3):
+        F1 = p1.forward(torch.from_numpy(np.ascontiguousarray(z[..., c])).to(dev()))
+        torch.cuda.synchronize()
+        assert torch.equal(F3[..., c].contiguous(), F1)
+
+
+def test_deterministic(lf2):
+    shape = (64, 48, 40)
+    dense, _ = real_field(shape, seed=7)
+    plan = lf2.Plan(shape, lf2.LF2_R2C)
+    x = torch.from_numpy(dense[..., 0]).to(dev())
+    a = plan.forward(x)
+    b = plan.forward(x)
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
+
+
+def test_round_trip(lf2):
+    shape = (64, 48, 40)
+    dense, _ = real_field(shape, seed=8)
+    plan = lf2.Plan(shape, lf2.LF2_R2C)
+    x = torch.from_numpy(dense[..., 0]).to(dev())
+    back = plan.backward(plan.forward(x)) / float(np.prod(shape))
+    torch.cuda.synchronize()
+    assert rel_l2(back.cpu().numpy(), dense[..., 0]) <= tol(shape)

@@ -1,0 +1,128 @@
+"""GPU parity of the Poisson solve and the power spectrum against the oracle."""
+import numpy as np
+import pytest
+
+import oracle
+from gpu_helpers import grf_field, real_field, rel_l2, rel_max, tol
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def lf2():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1508_05610_amd as m
+    m.load()
+    return m
+
+
+def dev():
+    return torch.device("cuda:0")
+
+
+SHAPES = [(32, 32, 32), (16, 12, 10), (64, 48, 40), (8, 8, 8), (128, 96, 80), (96, 160, 192)]
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+@pytest.mark.parametrize("discrete", [0, 1])
+@pytest.mark.parametrize("dx", [1.0, 0.37])
+def test_poisson(lf2, shape, discrete, dx):
+    print(f"case poisson {shape} discrete={discrete} dx={dx}", flush=True)
+    dense, _ = real_field(shape, seed=11)
+    f = dense[..., 0]
+    plan = lf2.Plan(shape, lf2.LF2_R2C)
+    phi = plan.poisson(torch.from_numpy(f).to(dev()), dx=dx,
+                       flags=lf2.LF2_POISSON_DISCRETE_K2 if discrete else 0)
+    torch.cuda.synchronize()
+    ref = oracle.poisson(f.astype(np.float64), dx=dx, k2mode=discrete)
+    got = phi.cpu().numpy().astype(np.float64)
+    e = rel_l2(got, ref)
+    print(f"  rel-L2 {e:.3e} max {rel_max(got, ref):.3e}", flush=True)
+    assert e <= tol(shape)
+
+
+@pytest.mark.parametrize("shape,nbins", [((32, 32, 32), 16), ((64, 48, 40), 24), ((16, 12, 10), 5),
+                                         ((128, 96, 80), 64), ((8, 8, 8), 1), ((96, 160, 192), 40)])
+def test_power_spectrum_real_space(lf2, shape, nbins):
+    print(f"case pk {shape} nbins={nbins}", flush=True)
+    dense, _ = real_field(shape, seed=12)
+    f = dense[..., 0]
+    plan = lf2.Plan(shape, lf2.LF2_R2C)
+    xd = torch.from_numpy(f).to(dev())
+    pk, km, ct = plan.power_spectrum(xd, nbins, dx=0.5)
+    torch.cuda.synchronize()
+    opk, okm, oct_ = oracle.power_spectrum(oracle.r2c(f.astype(np.float64)), shape, nbins, dx=0.5)
+    assert np.array_equal(ct.cpu().numpy(), oct_)
+    e = rel_l2(pk.cpu().numpy(), opk)
+    print(f"  pk rel-L2 {e:.3e}  kmean {rel_l2(km.cpu().numpy(), okm):.3e}", flush=True)
+    assert e <= tol(shape)
+    assert rel_l2(km.cpu().numpy(), okm) <= 1e-12
+    # the k-space entry gives the same bins from the spectrum
+    F = plan.forward(xd)
+    pk2, km2, ct2 = plan.power_spectrum(F, nbins, dx=0.5, field_is_kspace=True)
+    torch.cuda.synchronize()
+    assert np.array_equal(ct2.cpu().numpy(), oct_)
+    assert rel_l2(pk2.cpu().numpy(), opk) <= tol(shape)
+
+
+def test_power_spectrum_c2c(lf2):
+    shape = (32, 24, 20)
+    from gpu_helpers import complex_field
+    z = complex_field(shape, seed=13)[..., 0]
+    plan = lf2.Plan(shape, lf2.LF2_C2C)
+    pk, km, ct = plan.power_spectrum(torch.from_numpy(z).to(dev()), 12)
+    torch.cuda.synchronize()
+    opk, okm, oct_ = oracle.power_spectrum(oracle.c2c(z.astype(np.complex128), -1), shape, 12,
+                                           half=False)
+    assert np.array_equal(ct.cpu().numpy(), oct_)
+    assert rel_l2(pk.cpu().numpy(), opk) <= tol(shape)
+
+
+@pytest.mark.parametrize("of_phi", [False, True])
+def test_poisson_with_pk_and_parseval(lf2, of_phi):
+    shape = (64, 48, 40)
+    N = int(np.prod(shape))
+    dense, _ = real_field(shape, seed=14)
+    f = dense[..., 0]
+    f64 = f.astype(np.float64)
+    plan = lf2.Plan(shape, lf2.LF2_R2C)
+    flags = lf2.LF2_PK_OF_PHI if of_phi else 0
+    res = plan.poisson(torch.from_numpy(f).to(dev()), nbins=20, flags=flags, parseval=not of_phi)
+    torch.cuda.synchronize()
+    phi, pk, km, ct = res[:4]
+    ref_phi = oracle.poisson(f64)
+    assert rel_l2(phi.cpu().numpy(), ref_phi) <= tol(shape)
+    src = ref_phi if of_phi else f64
+    opk, okm, oct_ = oracle.power_spectrum(oracle.r2c(src), shape, 20)
+    assert np.array_equal(ct.cpu().numpy(), oct_)
+    assert rel_l2(pk.cpu().numpy(), opk) <= tol(shape)
+    if not of_phi:
+        pv = res[4].cpu().numpy()
+        assert abs(pv[0] - np.sum(f64 * f64)) <= 1e-12 * np.sum(f64 * f64)
+        assert abs(pv[1] - pv[0]) <= tol(shape) * pv[0]
+
+
+def test_grf_spectrum_256(lf2):
+    """256^3 P(k) ~ k^-3 random field: full-size parity of r2c, c2r, Poisson and 128-bin P(k)."""
+    shape = (256, 256, 256)
+    print("case grf 256^3", flush=True)
+    f32, f64, scale = grf_field(shape, 3.0, seed=2)
+    plan = lf2.Plan(shape, lf2.LF2_R2C)
+    x = torch.from_numpy(f32).to(dev())
+    F = plan.forward(x)
+    back = plan.backward(F)
+    phi, pk, km, ct = plan.poisson(x, nbins=128)
+    torch.cuda.synchronize()
+    refF = oracle.r2c(f64)
+    e1 = rel_l2(F.cpu().numpy(), refF)
+    e2 = rel_l2(back.cpu().numpy(), float(np.prod(shape)) * f64)
+    e3 = rel_l2(phi.cpu().numpy(), oracle.poisson(f64))
+    opk, okm, oct_ = oracle.power_spectrum(refF, shape, 128)
+    e4 = rel_l2(pk.cpu().numpy(), opk)
+    print(f"  r2c {e1:.2e} c2r {e2:.2e} poisson {e3:.2e} pk {e4:.2e}", flush=True)
+    assert np.array_equal(ct.cpu().numpy(), oct_)
+    for e in (e1, e2, e3, e4):
+        assert e <= tol(shape)
