@@ -1,0 +1,311 @@
+#!/usr/bin/env python3
+"""Throughput of the lf2 hot path on one MI355X.
+
+One step = one pass of the whole transform path over the 512^3 FP32
+workload:
+  r2c forward + c2r backward of a real N(0,1) field (1 component),
+  c2c forward + backward of a complex64 3-component AoS N(0,1) field,
+  Poisson solve of the real field with a fused 128-bin power spectrum and
+  FP64 Parseval sums.
+value = 3-D FFT GFLOP/s with the conventional 5 N log2 N per transform and
+component (10 transforms per step).  Inputs are resident in HBM before the
+timed region.  Prints one JSON line.
+
+Extra fields: per-op times, algorithmic GB/s, the dominant kernel's HBM
+roofline (its average duration measured with HIP events inside the timed
+region), the FP64 oracle timed on the host cores (CPU baseline), and the
+relative errors of the results against that oracle.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_1508_05610_amd", "csrc")
+    for fn in sorted(os.listdir(csrc)):
+        if fn.endswith((".hip", ".hpp", ".cpp")):
+            with open(os.path.join(csrc, fn), "rb") as f:
+                h.update(fn.encode())
+                h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel: str):
+    """HBM bytes per launch of `kernel` from the committed PMC summary, if it
+    was taken on the current kernel sources; else None."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        t = json.load(f)
+    if t.get("source_hash") != kernel_source_hash():
+        return None
+    k = t.get("kernels", {}).get(kernel)
+    return None if k is None else k.get("hbm_bytes_per_launch")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--size", type=int, default=512)
+    ap.add_argument("--nbins", type=int, default=128)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-errors", action="store_true")
+    ap.add_argument("--only", default=None,
+                    help="time one op alone (r2c_fwd, c2r_bwd, c2c_fwd_3comp, c2c_bwd_3comp, "
+                         "poisson_pk, copy) for profiler runs")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(a single large lattice would shard as z-slabs with one all-to-all; "
+              "not built).", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import synth
+    import paper_1508_05610_amd as lf2
+    from paper_1508_05610_amd import _lib
+
+    lf2.load()
+    dev = torch.device("cuda:0")
+    S = args.size
+    n = (S, S, S)
+    N = S ** 3
+    flops_fft = 5.0 * N * math.log2(N)
+
+    # ---- inputs (seeded, synthetic; resident before timing)
+    f32 = synth.white_field(3, n)[..., 0]
+    z3 = synth.white_field(4, n, ncomp=3, complex_values=True)
+    x = torch.from_numpy(f32).to(dev)
+    z = torch.from_numpy(z3).to(dev).view(torch.complex64).reshape(S, S, S, 3)
+    del z3
+
+    pr = lf2.Plan(n, lf2.LF2_R2C)
+    pc = lf2.Plan(n, lf2.LF2_C2C, ncomp=3)
+    F = torch.empty(pr.k_shape, dtype=torch.complex64, device=dev)
+    back = torch.empty(pr.x_shape, dtype=torch.float32, device=dev)
+    Z = torch.empty(pc.k_shape, dtype=torch.complex64, device=dev)
+    zb = torch.empty(pc.x_shape, dtype=torch.complex64, device=dev)
+    phi = torch.empty(pr.x_shape, dtype=torch.float32, device=dev)
+    nb = args.nbins
+    pk = torch.empty(nb, dtype=torch.float64, device=dev)
+    km = torch.empty(nb, dtype=torch.float64, device=dev)
+    ct = torch.empty(nb, dtype=torch.float64, device=dev)
+    pv = torch.empty(2, dtype=torch.float64, device=dev)
+    stream = torch.cuda.current_stream()
+    sh = int(stream.cuda_stream)
+
+    def op_r2c():
+        _lib.lf2_fft_execute(pr.handle, lf2.LF2_FORWARD, x.data_ptr(), F.data_ptr(), sh)
+
+    def op_c2r():
+        _lib.lf2_fft_execute(pr.handle, lf2.LF2_BACKWARD, F.data_ptr(), back.data_ptr(), sh)
+
+    def op_c2c_f():
+        _lib.lf2_fft_execute(pc.handle, lf2.LF2_FORWARD, z.data_ptr(), Z.data_ptr(), sh)
+
+    def op_c2c_b():
+        _lib.lf2_fft_execute(pc.handle, lf2.LF2_BACKWARD, Z.data_ptr(), zb.data_ptr(), sh)
+
+    def op_poisson():
+        _lib.lf2_poisson_solve(pr.handle, x.data_ptr(), phi.data_ptr(), 1.0, 0, nb, pk.data_ptr(),
+                               km.data_ptr(), ct.data_ptr(), pv.data_ptr(), sh)
+
+    ops = [("r2c_fwd", op_r2c, 1), ("c2r_bwd", op_c2r, 1), ("c2c_fwd_3comp", op_c2c_f, 3),
+           ("c2c_bwd_3comp", op_c2c_b, 3), ("poisson_pk", op_poisson, 2)]
+    n_transforms = sum(w for _, _, w in ops)
+
+    if args.only:
+        # one op alone, for profiler runs; "copy" is a plain 1 GiB device copy
+        # whose counter readings calibrate the HBM byte counters
+        if args.only == "copy":
+            src = torch.empty(1 << 28, dtype=torch.float32, device=dev).fill_(1.0)
+            dst = torch.empty_like(src)
+            fn = lambda: dst.copy_(src)  # noqa: E731
+        else:
+            fn = dict((nm, f) for nm, f, _ in ops)[args.only]
+        for _ in range(args.warmup):
+            fn()
+        torch.cuda.synchronize()
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        for _ in range(args.steps):
+            fn()
+        b.record(stream)
+        torch.cuda.synchronize()
+        print(json.dumps({"only": args.only, "ms": a.elapsed_time(b) / args.steps,
+                          "steps": args.steps}), flush=True)
+        return
+
+    def step():
+        for _, fn, _ in ops:
+            fn()
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+
+    # ---- timed region: K steps, kernel timing on
+    _lib.lf2_profile_enable(True)
+    t_start = torch.cuda.Event(enable_timing=True)
+    t_end = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    wall0 = time.perf_counter()
+    t_start.record(stream)
+    for _ in range(args.steps):
+        step()
+    t_end.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - wall0
+    ms_step = t_start.elapsed_time(t_end) / args.steps
+    table = _lib.profile_table()
+    _lib.lf2_profile_enable(False)
+
+    # ---- per-op times (separate loop, events around each op)
+    per_op = {}
+    reps = max(3, args.steps)
+    for name, fn, _ in ops:
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        a.record(stream)
+        for _ in range(reps):
+            fn()
+        b.record(stream)
+        torch.cuda.synchronize()
+        per_op[name] = a.elapsed_time(b) / reps
+
+    step_bytes = sum(v[2] for v in table.values()) / args.steps
+    # group the per-pass records by kernel symbol (the part before the space)
+    by_symbol = {}
+    for k, (n_, ms_, by_) in table.items():
+        sym = k.split(" ")[0]
+        a0 = by_symbol.setdefault(sym, [0, 0.0, 0.0])
+        a0[0] += n_
+        a0[1] += ms_
+        a0[2] += by_
+    dom = max(by_symbol.items(), key=lambda kv: kv[1][1])
+    dname, (dn, dms, dbytes) = dom
+    achieved = (dbytes / dn) / (dms / dn * 1e-3) / 1e9
+    traffic = measured_traffic(dname)
+    kernels = {k: {"launches": v[0], "avg_us": 1e3 * v[1] / v[0],
+                   "alg_bytes_per_launch": v[2] / v[0],
+                   "gbps": (v[2] / v[0]) / (v[1] / v[0] * 1e-3) / 1e9} for k, v in table.items()}
+
+    value = n_transforms * flops_fft / (ms_step * 1e-3) / 1e9
+    res = {
+        "metric": "3D FFT GFLOP/s (5N*log2N) + HBM GB/s at 512^3 FP32",
+        "value": round(value, 2),
+        "unit": "GFLOP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True,
+        "scaling": "strong",
+        "vs_baseline": None,
+        "dtype": "fp32",
+        "data": "synthetic",
+        "config": {
+            "workload": f"{S}^3 FP32 lattice: r2c fwd + c2r bwd (real N(0,1), seed 3), "
+                        f"c2c fwd + bwd (complex64 3-comp AoS N(0,1), seed 4), "
+                        f"Poisson with fused {nb}-bin P(k) + FP64 Parseval",
+            "lattice": [S, S, S], "transforms_per_step": n_transforms,
+        },
+        "gbps_algorithmic": round(step_bytes / (ms_step * 1e-3) / 1e9, 1),
+        "ops_ms": {k: round(v, 4) for k, v in per_op.items()},
+        "roofline": {
+            "bound": "hbm", "kernel": dname,
+            "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": traffic,
+            "avg_us": round(1e3 * dms / dn, 2),
+            "alg_bytes_per_launch": dbytes / dn,
+        },
+        "kernels": kernels,
+        "wall_s_timed": round(wall, 3),
+    }
+    # r2c forward / c2r backward: 3 passes, 4 + 5 * 8 Nh/N0 bytes per point
+    # (x pass reads reals and writes the half spectrum, y and z read and
+    # write it).
+    r2c_ms = per_op["r2c_fwd"]
+    nh = S // 2 + 1
+    alg_r2c = 4.0 * N + 8.0 * nh * S * S + 2 * (2 * 8.0 * nh * S * S)
+    res["r2c_fwd_gbps"] = round(alg_r2c / (r2c_ms * 1e-3) / 1e9, 1)
+    res["r2c_fwd_roofline_frac"] = round(alg_r2c / (r2c_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
+    res["c2r_bwd_roofline_frac"] = round(alg_r2c / (per_op["c2r_bwd"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
+
+    # ---- CPU baseline: the FP64 oracle on the host cores, bounded sample
+    errors = {}
+    if not args.no_cpu_baseline or not args.no_errors:
+        import oracle
+        f64 = f32.astype(np.float64)
+        t0 = time.perf_counter()
+        Fo = oracle.r2c(f64)
+        t1 = time.perf_counter()
+        bo = oracle.c2r(Fo, S)
+        t2 = time.perf_counter()
+        cpu_s = t2 - t0
+        if not args.no_cpu_baseline:
+            res["cpu_baseline"] = {
+                "value": round(2 * flops_fft / cpu_s / 1e9, 3), "unit": "GFLOP/s",
+                "cores": oracle.num_threads(), "kind": "oracle",
+                "sample": f"one r2c forward + one c2r backward of the {S}^3 field "
+                          f"(2 of the {n_transforms} transforms of a step); "
+                          f"{t1 - t0:.2f} s + {t2 - t1:.2f} s",
+            }
+        if not args.no_errors:
+            def rel_l2(a, b):
+                return float(np.linalg.norm((a - b).ravel()) / np.linalg.norm(b.ravel()))
+
+            def rel_max(a, b):
+                return float(np.abs(a - b).max() / np.abs(b).max())
+
+            op_r2c()
+            op_c2r()
+            op_poisson()
+            op_c2c_f()
+            torch.cuda.synchronize()
+            Fg = F.cpu().numpy()
+            errors["r2c_fwd"] = {"rel_l2": rel_l2(Fg, Fo), "max": rel_max(Fg, Fo)}
+            bg = back.cpu().numpy()
+            errors["c2r_bwd_chain"] = {"rel_l2": rel_l2(bg, bo), "max": rel_max(bg, bo)}
+            opk, okm, oct_ = oracle.power_spectrum(Fo, n, nb)
+            errors["pk"] = {"rel_l2": rel_l2(pk.cpu().numpy(), opk),
+                            "counts_exact": bool(np.array_equal(ct.cpu().numpy(), oct_))}
+            # c2c 3-comp: sampled modes, each evaluated from the definition
+            Zg = Z.cpu().numpy()
+            zz = z.cpu().numpy()
+            worst = 0.0
+            for c in range(3):
+                zc = zz[..., c].astype(np.complex128)
+                for k in ((0, 0, 0), (1, 2, 3), (S // 2, S // 3, S - 1), (S - 5, 7, S // 2)):
+                    v = oracle.dft3d_at(zc, k)
+                    worst = max(worst, float(abs(complex(Zg[k[2], k[1], k[0], c]) - v)) / math.sqrt(N))
+            errors["c2c_fwd_sampled_abs_over_sqrtN"] = worst
+            errors["tolerance_rel_l2"] = 1e-5 * math.log2(N)
+            res["errors"] = errors
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

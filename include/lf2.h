@@ -167,6 +167,24 @@ lf2_status lf2_power_spectrum(lf2_plan p, const void *field, int32_t field_is_ks
 
 lf2_status lf2_plan_destroy(lf2_plan p);
 
+/*
+ * Kernel timing (tracing).  While enabled, every kernel launch made by the
+ * calls above is bracketed by two HIP events recorded on the launch's
+ * stream and tagged with the kernel's name and its algorithmic HBM bytes
+ * (the bytes a single pass over its inputs and outputs must move).
+ * lf2_profile_count synchronises on the recorded events and returns the
+ * number of distinct kernel names; lf2_profile_get(i, ...) returns, for the
+ * i-th name, the launch count, the summed event time in milliseconds and
+ * the summed algorithmic bytes.  name receives at most name_len bytes
+ * (NUL-terminated).  Enabling or resetting drops earlier records.
+ * Recording adds two event records per launch; it is off by default.
+ */
+lf2_status lf2_profile_enable(int32_t on);
+lf2_status lf2_profile_reset(void);
+int32_t lf2_profile_count(void);
+lf2_status lf2_profile_get(int32_t i, char *name, size_t name_len, int64_t *launches, double *ms,
+                           double *bytes);
+
 const char *lf2_status_string(lf2_status s);
 const char *lf2_last_error(void);
 

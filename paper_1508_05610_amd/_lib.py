@@ -55,6 +55,11 @@ _SIGS = {
     "lf2_poisson_solve": (_i32, [_vp, _vp, _vp, _f64, _u32, _i32, _vp, _vp, _vp, _vp, _vp]),
     "lf2_power_spectrum": (_i32, [_vp, _vp, _i32, _i32, _f64, _vp, _vp, _vp, _vp]),
     "lf2_plan_destroy": (_i32, [_vp]),
+    "lf2_profile_enable": (_i32, [_i32]),
+    "lf2_profile_reset": (_i32, []),
+    "lf2_profile_count": (_i32, []),
+    "lf2_profile_get": (_i32, [_i32, ctypes.c_char_p, ctypes.c_size_t, ctypes.POINTER(_i64),
+                                ctypes.POINTER(_f64), ctypes.POINTER(_f64)]),
     "lf2_status_string": (ctypes.c_char_p, [_i32]),
     "lf2_last_error": (ctypes.c_char_p, []),
     "lf2_version": (ctypes.c_char_p, []),
@@ -153,3 +158,32 @@ def lf2_power_spectrum(plan: int, field_ptr: int, field_is_kspace: int, nbins: i
 
 def lf2_plan_destroy(plan: int):
     _check(load().lf2_plan_destroy(plan), "lf2_plan_destroy")
+
+
+def lf2_profile_enable(on: bool = True):
+    _check(load().lf2_profile_enable(int(bool(on))), "lf2_profile_enable")
+
+
+def lf2_profile_reset():
+    _check(load().lf2_profile_reset(), "lf2_profile_reset")
+
+
+def lf2_profile_count() -> int:
+    return int(load().lf2_profile_count())
+
+
+def lf2_profile_get(i: int):
+    """(name, launches, total_ms, total_algorithmic_bytes) of kernel name i."""
+    name = ctypes.create_string_buffer(128)
+    n = _i64()
+    ms = _f64()
+    by = _f64()
+    _check(load().lf2_profile_get(int(i), name, 128, ctypes.byref(n), ctypes.byref(ms),
+                                  ctypes.byref(by)), "lf2_profile_get")
+    return name.value.decode(), int(n.value), float(ms.value), float(by.value)
+
+
+def profile_table():
+    """{kernel name: (launches, total_ms, total_bytes)} of the records so far."""
+    return {nm: (n, ms, by) for nm, n, ms, by in
+            (lf2_profile_get(i) for i in range(lf2_profile_count()))}

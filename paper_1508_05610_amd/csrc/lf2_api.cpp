@@ -91,6 +91,96 @@ bool radix_ok(int64_t n)
 
 size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 
+// ------------------------------------------------------------- kernel timing
+namespace prof {
+struct Rec {
+    int id;
+    hipEvent_t a, b;
+    double bytes;
+};
+struct Agg {
+    int64_t n = 0;
+    double ms = 0.0, bytes = 0.0;
+};
+std::mutex mu;
+bool on = false;
+std::vector<std::string> names;
+std::vector<Agg> agg;
+std::vector<Rec> recs;
+std::vector<hipEvent_t> pool;
+
+hipEvent_t take()
+{
+    if (!pool.empty()) {
+        hipEvent_t e = pool.back();
+        pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+// Returns a record index, or -1 when timing is off.
+int begin(const std::string &name, double bytes, hipStream_t s)
+{
+    std::lock_guard<std::mutex> lk(mu);
+    if (!on) return -1;
+    int id = -1;
+    for (size_t i = 0; i < names.size(); ++i)
+        if (names[i] == name) id = (int)i;
+    if (id < 0) {
+        names.push_back(name);
+        agg.emplace_back();
+        id = (int)names.size() - 1;
+    }
+    Rec r{id, take(), take(), bytes};
+    if (!r.a || !r.b) return -1;
+    (void)hipEventRecord(r.a, s);
+    recs.push_back(r);
+    return (int)recs.size() - 1;
+}
+
+void end(int idx, hipStream_t s)
+{
+    if (idx < 0) return;
+    std::lock_guard<std::mutex> lk(mu);
+    if (idx < (int)recs.size()) (void)hipEventRecord(recs[idx].b, s);
+}
+
+void drain()
+{
+    for (Rec &r : recs) {
+        float ms = 0.f;
+        if (hipEventSynchronize(r.b) == hipSuccess && hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess) {
+            agg[r.id].n += 1;
+            agg[r.id].ms += ms;
+            agg[r.id].bytes += r.bytes;
+        }
+        pool.push_back(r.a);
+        pool.push_back(r.b);
+    }
+    recs.clear();
+}
+
+void reset()
+{
+    drain();
+    names.clear();
+    agg.clear();
+}
+}  // namespace prof
+
+std::string kname(const char *fmt, ...)
+{
+    char buf[128];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    return buf;
+}
+
 }  // namespace
 
 struct K2Entry {
@@ -375,7 +465,15 @@ SArgs s_args(const lf2_plan_s *p, int axis, const void *in, void *out, int epi)
 lf2_status run_strided(const lf2_plan_s *p, int axis, int sign, const SArgs &a, int grid_cap,
                        hipStream_t s, int *grid_used)
 {
+    const double sb = (double)spectrum_bytes(p);
+    const bool epi = (a.epi & (EPI_PK | EPI_PK_AFTER | EPI_POISSON)) != 0;
+    // "<kernel symbol> <pass>": the symbol part matches the profiler's name
+    const int t = prof::begin(kname("k_strided<%d,%d,%d> %s%s%s", p->len[axis], sign, epi ? 1 : 0,
+                                    axis == 1 ? "y" : "z", (a.epi & EPI_POISSON) ? "+poisson" : "",
+                                    (a.epi & (EPI_PK | EPI_PK_AFTER)) ? "+pk" : ""),
+                              (a.epi & EPI_STORE) ? 2 * sb : sb, s);
     hipError_t e = launch_strided(p->len[axis], sign, a, grid_cap, s, grid_used);
+    prof::end(t, s);
     if (e != hipSuccess)
         return fail(LF2_ERR_DEVICE, "strided pass (axis %d, L=%d) launch: %s", axis, p->len[axis],
                     hipGetErrorString(e));
@@ -385,12 +483,20 @@ lf2_status run_strided(const lf2_plan_s *p, int axis, int sign, const SArgs &a, 
 lf2_status run_x(const lf2_plan_s *p, int which, int sign, const XArgs &a, hipStream_t s)
 {
     hipError_t e;
-    if (which == 0)
+    const double rb = (double)p->ntot * p->nc * 4.0;  // real field
+    const double sb = (double)spectrum_bytes(p);
+    int t;
+    if (which == 0) {
+        t = prof::begin(kname("k_x_r2c<%d,%d>", p->len[0], p->nc), rb + sb, s);
         e = launch_x_r2c(p->len[0], p->nc, a, s);
-    else if (which == 1)
+    } else if (which == 1) {
+        t = prof::begin(kname("k_x_c2r<%d,%d>", p->len[0], p->nc), rb + sb, s);
         e = launch_x_c2r(p->len[0], p->nc, a, s);
-    else
+    } else {
+        t = prof::begin(kname("k_x_c2c<%d,%d,%d>", p->len[0], p->nc, sign), 2 * sb, s);
         e = launch_x_c2c(p->len[0], p->nc, sign, a, s);
+    }
+    prof::end(t, s);
     if (e != hipSuccess)
         return fail(LF2_ERR_DEVICE, "x pass (L=%d) launch: %s", p->len[0], hipGetErrorString(e));
     return LF2_OK;
@@ -432,6 +538,44 @@ const char *lf2_status_string(lf2_status s)
 }
 
 const char *lf2_last_error(void) { return g_err.c_str(); }
+
+lf2_status lf2_profile_enable(int32_t on)
+{
+    std::lock_guard<std::mutex> lk(prof::mu);
+    prof::reset();
+    prof::on = on != 0;
+    return LF2_OK;
+}
+
+lf2_status lf2_profile_reset(void)
+{
+    std::lock_guard<std::mutex> lk(prof::mu);
+    prof::reset();
+    return LF2_OK;
+}
+
+int32_t lf2_profile_count(void)
+{
+    std::lock_guard<std::mutex> lk(prof::mu);
+    prof::drain();
+    return (int32_t)prof::names.size();
+}
+
+lf2_status lf2_profile_get(int32_t i, char *name, size_t name_len, int64_t *launches, double *ms,
+                           double *bytes)
+{
+    std::lock_guard<std::mutex> lk(prof::mu);
+    if (i < 0 || i >= (int32_t)prof::names.size())
+        return fail(LF2_ERR_INVALID_ARG, "profile index %d out of range", i);
+    if (name && name_len > 0) {
+        strncpy(name, prof::names[i].c_str(), name_len - 1);
+        name[name_len - 1] = 0;
+    }
+    if (launches) *launches = prof::agg[i].n;
+    if (ms) *ms = prof::agg[i].ms;
+    if (bytes) *bytes = prof::agg[i].bytes;
+    return LF2_OK;
+}
 
 const char *lf2_version(void) { return "lf2 0.1.0 gfx950"; }
 
@@ -705,7 +849,10 @@ lf2_status lf2_power_spectrum(lf2_plan p, const void *field, int32_t field_is_ks
         mt.thresh = sh.thresh;
         mt.nbins = nbins;
         grid = kPkGrid;
-        LF2_HIP(launch_pk_kspace(field, (int)p->n[1], (int)p->n[2], mt, part, grid, s));
+        const int t = prof::begin("k_pk_kspace", (double)spectrum_bytes(p), s);
+        hipError_t e = launch_pk_kspace(field, (int)p->n[1], (int)p->n[2], mt, part, grid, s);
+        prof::end(t, s);
+        LF2_HIP(e);
     } else {
         void *W = ws + L.w;
         if (p->kind == LF2_R2C) {

@@ -266,4 +266,189 @@ __device__ __forceinline__ void stockham(c32 *buf, int nlines, int LS, int PS, c
     }
 }
 
+// ------------------------------------------------------------ column engine
+// NL interleaved lines (columns of a strided pass), element (line l, point p)
+// at buf[l + p * NL].  NT is a multiple of NL, so thread tid always works on
+// line tid % NL and on butterflies j = tid / NL + i * (NT / NL).  The first
+// stage may take its inputs straight from global memory (rows j + r L/R of
+// the thread's column, which for consecutive lanes are adjacent addresses)
+// and the last stage may store its outputs straight to global memory (the
+// last stage of a Stockham DIT writes point j + r L/R).  Stages that read
+// and write LDS wait at a barrier between their reads and their writes.
+
+template <int L, int R, int NS, int S, int NL, int NT, bool SRC_G, bool DST_G>
+__device__ __forceinline__ void col_stage(c32 *buf, const c32 *gin, c32 *gout, int64_t gs,
+                                          bool gv, const c32 *tw, int tid)
+{
+    constexpr int Q = L / R;
+    constexpr int JS = NT / NL;
+    constexpr int NB = (Q + JS - 1) / JS;
+    static_assert(NT % NL == 0, "threads must tile the lines");
+    static_assert(!DST_G || NS * R == L, "only the last stage stores to global memory");
+    const int l = tid % NL;
+    const int j0 = tid / NL;
+    c32 v[NB][R];
+#pragma unroll
+    for (int i = 0; i < NB; ++i) {
+        const int j = j0 + i * JS;
+        if (Q % JS == 0 || j < Q) {
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                if (SRC_G)
+                    v[i][r] = gv ? gin[(int64_t)(j + r * Q) * gs] : c32{0.f, 0.f};
+                else
+                    v[i][r] = buf[l + (j + r * Q) * NL];
+            }
+        }
+    }
+    if (!SRC_G && !DST_G) __syncthreads();
+#pragma unroll
+    for (int i = 0; i < NB; ++i) {
+        const int j = j0 + i * JS;
+        if (Q % JS == 0 || j < Q) {
+            const int k = j % NS;
+            if (NS > 1) {
+#pragma unroll
+                for (int r = 1; r < R; ++r) {
+                    c32 w = tw[r * k * (L / (NS * R))];
+                    if (S > 0) w = conjg(w);
+                    v[i][r] = mul(v[i][r], w);
+                }
+            }
+            Dft<R, S>::run(v[i]);
+            if (DST_G) {
+                if (gv) {
+#pragma unroll
+                    for (int r = 0; r < R; ++r) gout[(int64_t)(j + r * Q) * gs] = v[i][r];
+                }
+            } else {
+                c32 *dst = buf + l + ((j / NS) * NS * R + k) * NL;
+#pragma unroll
+                for (int r = 0; r < R; ++r) dst[r * NS * NL] = v[i][r];
+            }
+        }
+    }
+    if (!DST_G) __syncthreads();
+}
+
+// ------------------------------------------------------------ row engine
+// NLN contiguous lines (rows of the x pass), point p of line l at
+// buf[l * LP + p].  Butterfly b = tid + i NT of a stage maps to line b / Q
+// and j = b % Q, so consecutive lanes take consecutive j: the first stage's
+// global loads (point j + r Q of a row) and the last stage's global stores
+// are contiguous across a wave.  `rowoff[l]` is the element offset of line
+// l in the global arrays.
+
+template <int L, int R, int NS, int S, int NLN, int LP, int NT, bool SRC_G, bool DST_G>
+__device__ __forceinline__ void row_stage(c32 *buf, const c32 *gin, c32 *gout,
+                                          const int64_t *rowoff_in, const int64_t *rowoff_out,
+                                          int nvalid, const c32 *tw, int tid, double *ssq)
+{
+    constexpr int Q = L / R;
+    constexpr int NBF = NLN * Q;
+    constexpr int NB = (NBF + NT - 1) / NT;
+    static_assert(!DST_G || NS * R == L, "only the last stage stores to global memory");
+    c32 v[NB][R];
+#pragma unroll
+    for (int i = 0; i < NB; ++i) {
+        const int b = tid + i * NT;
+        if (NBF % NT == 0 || b < NBF) {
+            const int l = b / Q, j = b % Q;
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                if (SRC_G)
+                    v[i][r] = l < nvalid ? gin[rowoff_in[l] + j + r * Q] : c32{0.f, 0.f};
+                else
+                    v[i][r] = buf[l * LP + j + r * Q];
+            }
+            if (SRC_G && ssq) {
+#pragma unroll
+                for (int r = 0; r < R; ++r)
+                    *ssq += (double)v[i][r].x * v[i][r].x + (double)v[i][r].y * v[i][r].y;
+            }
+        }
+    }
+    if (!SRC_G && !DST_G) __syncthreads();
+#pragma unroll
+    for (int i = 0; i < NB; ++i) {
+        const int b = tid + i * NT;
+        if (NBF % NT == 0 || b < NBF) {
+            const int l = b / Q, j = b % Q;
+            const int k = j % NS;
+            if (NS > 1) {
+#pragma unroll
+                for (int r = 1; r < R; ++r) {
+                    c32 w = tw[r * k * (L / (NS * R))];
+                    if (S > 0) w = conjg(w);
+                    v[i][r] = mul(v[i][r], w);
+                }
+            }
+            Dft<R, S>::run(v[i]);
+            if (DST_G) {
+                if (l < nvalid) {
+#pragma unroll
+                    for (int r = 0; r < R; ++r) gout[rowoff_out[l] + j + r * Q] = v[i][r];
+                }
+            } else {
+                c32 *dst = buf + l * LP + (j / NS) * NS * R + k;
+#pragma unroll
+                for (int r = 0; r < R; ++r) dst[r * NS] = v[i][r];
+            }
+        }
+    }
+    if (!DST_G) __syncthreads();
+}
+
+template <int L, int S, int NLN, int LP, int NT, bool SRC_G, bool DST_G, int ST = 0, int NS = 1>
+__device__ __forceinline__ void row_fft(c32 *buf, const c32 *gin, c32 *gout,
+                                        const int64_t *rowoff_in, const int64_t *rowoff_out,
+                                        int nvalid, const c32 *tw, int tid, double *ssq = nullptr)
+{
+    if constexpr (L == 1) {
+        for (int l = tid; l < NLN; l += NT) {
+            c32 v = SRC_G ? (l < nvalid ? gin[rowoff_in[l]] : c32{0.f, 0.f}) : buf[l * LP];
+            if (SRC_G && ssq) *ssq += (double)v.x * v.x + (double)v.y * v.y;
+            if (DST_G) {
+                if (l < nvalid) gout[rowoff_out[l]] = v;
+            } else {
+                buf[l * LP] = v;
+            }
+        }
+        __syncthreads();
+    } else if constexpr (NS < L) {
+        constexpr int R = radix_at(L, ST);
+        constexpr bool first = ST == 0, last = NS * R == L;
+        row_stage<L, R, NS, S, NLN, LP, NT, first && SRC_G, last && DST_G>(
+            buf, gin, gout, rowoff_in, rowoff_out, nvalid, tw, tid, ssq);
+        row_fft<L, S, NLN, LP, NT, SRC_G, DST_G, ST + 1, NS * R>(buf, gin, gout, rowoff_in,
+                                                                 rowoff_out, nvalid, tw, tid, ssq);
+    }
+}
+
+// Whole transform of the NL columns; SRC_G / DST_G select global input for
+// the first stage and global output for the last stage.  L = 1 is a copy.
+template <int L, int S, int NL, int NT, bool SRC_G, bool DST_G, int ST = 0, int NS = 1>
+__device__ __forceinline__ void col_fft(c32 *buf, const c32 *gin, c32 *gout, int64_t gs, bool gv,
+                                        const c32 *tw, int tid)
+{
+    if constexpr (L == 1) {
+        if (tid < NL) {
+            const int l = tid;
+            c32 v = SRC_G ? (gv ? gin[0] : c32{0.f, 0.f}) : buf[l];
+            if (DST_G) {
+                if (gv) gout[0] = v;
+            } else {
+                buf[l] = v;
+            }
+        }
+        __syncthreads();
+    } else if constexpr (NS < L) {
+        constexpr int R = radix_at(L, ST);
+        constexpr bool first = ST == 0, last = NS * R == L;
+        col_stage<L, R, NS, S, NL, NT, first && SRC_G, last && DST_G>(buf, gin, gout, gs, gv, tw,
+                                                                      tid);
+        col_fft<L, S, NL, NT, SRC_G, DST_G, ST + 1, NS * R>(buf, gin, gout, gs, gv, tw, tid);
+    }
+}
+
 }  // namespace lf2

@@ -22,7 +22,7 @@
 namespace lf2 {
 
 constexpr int kXThreads = 256;
-constexpr int kSThreads = 256;
+constexpr int kSThreads = 512;
 
 // Rows per x-pass block: about 4096 complex values of LDS (32 KiB), at
 // most 256 rows.
@@ -270,6 +270,155 @@ __global__ __launch_bounds__(kXThreads) void k_x_c2c(XArgs a)
     }
 }
 
+// ------------------------------------------------- one-component fast x pass
+// Rows whose element offsets are even (8-byte aligned) are read as complex
+// values: the packed r2c line z[n] = x[2n] + i x[2n+1] comes straight from
+// memory into the first Stockham stage, and the last stage of c2r / c2c
+// stores straight to memory.
+
+template <int RB>
+__device__ __forceinline__ int rows_valid(const XArgs &a, int64_t r0)
+{
+    const int64_t left = a.nrows - r0;
+    return left < RB ? (int)left : RB;
+}
+
+// X[k] = fe + W^k fo and X[M-k] = conj(fe - W^k fo), with
+// fe = (Z[k] + conj Z[M-k]) / 2, fo = (Z[k] - conj Z[M-k]) / (2i).
+template <int M>
+__global__ __launch_bounds__(kXThreads) void k_x_r2c_v(XArgs a)
+{
+    constexpr int NT = kXThreads;
+    constexpr int RB = x_rb(M, 1);
+    constexpr int LP = M;
+    constexpr int NH = M + 1;
+    constexpr int HALF = M / 2 + 1;  // pair items per line
+    __shared__ c32 buf[RB * LP];
+    __shared__ c32 tw[M];
+    __shared__ c32 twp[NH];
+    __shared__ int64_t ib[RB], ob[RB];
+    __shared__ double red[NT / 64];
+    const int tid = threadIdx.x;
+    const c32 *gtw = (const c32 *)a.tw;
+    const c32 *gtp = (const c32 *)a.tw_post;
+    for (int i = tid; i < M; i += NT) tw[i] = gtw[i];
+    for (int i = tid; i < NH; i += NT) twp[i] = gtp[i];
+    const int64_t r0 = (int64_t)blockIdx.x * RB;
+    row_bases<RB>(ib, ob, a, r0, tid);
+    __syncthreads();
+    for (int i = tid; i < RB; i += NT) ib[i] >>= 1;  // float offset -> complex offset
+    __syncthreads();
+    const int nv = rows_valid<RB>(a, r0);
+    double ss = 0.0;
+    row_fft<M, -1, RB, LP, NT, true, false>(buf, (const c32 *)a.in, nullptr, ib, nullptr, nv, tw,
+                                            tid, a.sumsq ? &ss : nullptr);
+    if (a.sumsq) block_sum_f64(ss, a.sumsq, red);
+    c32 *out = (c32 *)a.out;
+    constexpr int NI = RB * HALF;
+#pragma unroll
+    for (int i = 0; i < (NI + NT - 1) / NT; ++i) {
+        const int idx = tid + i * NT;
+        if (idx < NI) {
+            const int l = idx / HALF;
+            const int k = idx - l * HALF;
+            if (l < nv) {
+                const c32 *line = buf + l * LP;
+                const c32 z = line[k];
+                const c32 zc = conjg(line[k == 0 ? 0 : M - k]);
+                const c32 fe = scl(add(z, zc), 0.5f);
+                const c32 d = sub(z, zc);
+                const c32 fo = c32{0.5f * d.y, -0.5f * d.x};
+                const c32 wf = mul(twp[k], fo);
+                c32 *orow = out + ob[l];
+                orow[k] = add(fe, wf);
+                if (2 * k != M) orow[M - k] = conjg(sub(fe, wf));
+            }
+        }
+    }
+}
+
+// Z[k] = (X[k] + conj X[M-k]) + i W^{-k} (X[k] - conj X[M-k]); every thread
+// owns the pair (k, M-k), so the update is in place without a barrier.
+template <int M>
+__global__ __launch_bounds__(kXThreads) void k_x_c2r_v(XArgs a)
+{
+    constexpr int NT = kXThreads;
+    constexpr int RB = x_rb(M, 1);
+    constexpr int LP = M + 1;
+    constexpr int NH = M + 1;
+    constexpr int HALF = M / 2 + 1;
+    __shared__ c32 buf[RB * LP];
+    __shared__ c32 tw[M];
+    __shared__ c32 twp[NH];
+    __shared__ int64_t ib[RB], ob[RB];
+    const int tid = threadIdx.x;
+    const c32 *gtw = (const c32 *)a.tw;
+    const c32 *gtp = (const c32 *)a.tw_post;
+    for (int i = tid; i < M; i += NT) tw[i] = gtw[i];
+    for (int i = tid; i < NH; i += NT) twp[i] = gtp[i];
+    const int64_t r0 = (int64_t)blockIdx.x * RB;
+    row_bases<RB>(ib, ob, a, r0, tid);
+    __syncthreads();
+    for (int i = tid; i < RB; i += NT) ob[i] >>= 1;
+    const int nv = rows_valid<RB>(a, r0);
+    const c32 *in = (const c32 *)a.in;
+    constexpr int NI = RB * NH;
+#pragma unroll 4
+    for (int i = 0; i < (NI + NT - 1) / NT; ++i) {
+        const int idx = tid + i * NT;
+        if (idx < NI) {
+            const int l = idx / NH;
+            const int k = idx - l * NH;
+            buf[l * LP + k] = l < nv ? in[ib[l] + k] : c32{0.f, 0.f};
+        }
+    }
+    __syncthreads();
+    constexpr int NP = RB * HALF;
+#pragma unroll
+    for (int i = 0; i < (NP + NT - 1) / NT; ++i) {
+        const int idx = tid + i * NT;
+        if (idx < NP) {
+            const int l = idx / HALF;
+            const int k = idx - l * HALF;
+            c32 *line = buf + l * LP;
+            c32 xk = line[k], xm = line[M - k];
+            if (k == 0) {
+                xk.y = 0.f;
+                xm.y = 0.f;
+            }
+            const c32 s1 = add(xk, conjg(xm));
+            const c32 d1 = mul(conjg(twp[k]), sub(xk, conjg(xm)));
+            const c32 zk = c32{s1.x - d1.y, s1.y + d1.x};
+            if (k != 0 && 2 * k != M) {
+                const c32 s2 = add(xm, conjg(xk));
+                const c32 d2 = mul(conjg(twp[M - k]), sub(xm, conjg(xk)));
+                line[M - k] = c32{s2.x - d2.y, s2.y + d2.x};
+            }
+            line[k] = zk;
+        }
+    }
+    __syncthreads();
+    row_fft<M, +1, RB, LP, NT, false, true>(buf, nullptr, (c32 *)a.out, nullptr, ob, nv, tw, tid);
+}
+
+template <int L, int S>
+__global__ __launch_bounds__(kXThreads) void k_x_c2c_v(XArgs a)
+{
+    constexpr int NT = kXThreads;
+    constexpr int RB = x_rb(L, 1);
+    __shared__ c32 buf[RB * L];
+    __shared__ c32 tw[L];
+    __shared__ int64_t ib[RB], ob[RB];
+    const int tid = threadIdx.x;
+    const c32 *gtw = (const c32 *)a.tw;
+    for (int i = tid; i < L; i += NT) tw[i] = gtw[i];
+    const int64_t r0 = (int64_t)blockIdx.x * RB;
+    row_bases<RB>(ib, ob, a, r0, tid);
+    __syncthreads();
+    const int nv = rows_valid<RB>(a, r0);
+    row_fft<L, S, RB, L, NT, true, true>(buf, (const c32 *)a.in, (c32 *)a.out, ib, ob, nv, tw, tid);
+}
+
 // ------------------------------------------------------------------ binning
 // Exact bin of integer squared radius q: max{b <= nbins-1 : thresh[b] <= q},
 // thresh[b] = ceil(b^2 qmax / nbins^2).  The FP64 estimate is corrected by
@@ -284,13 +433,14 @@ __device__ __forceinline__ int bin_of(int64_t q, const int64_t *thresh, int nbin
 }
 
 // ------------------------------------------------------------------ strided pass
-template <int L, int S>
-__global__ __launch_bounds__(kSThreads) void k_strided(SArgs a)
+// EPI = false: plain pass (no epilogue code, fewest registers);
+// EPI = true : last-axis pass with the binning / Poisson epilogue.
+template <int L, int S, bool EPI>
+__global__ __launch_bounds__(kSThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_strided(SArgs a)
 {
     constexpr int NT = kSThreads;
     constexpr int B = s_b(L);
-    constexpr int RPT = NT / B;                 // rows covered by one sweep of the block
-    constexpr int NIT = (L + RPT - 1) / RPT;    // sweeps per tile
+    constexpr int RPT = NT / B;                 // row groups in the epilogue
     __shared__ c32 buf[L * B];
     __shared__ c32 tw[L];
     extern __shared__ double dyn[];              // hist[nbins + 1], thresh[nbins + 1]
@@ -300,10 +450,11 @@ __global__ __launch_bounds__(kSThreads) void k_strided(SArgs a)
     const c32 *gtw = (const c32 *)a.tw;
     for (int i = tid; i < L; i += NT) tw[i] = gtw[i];
     const bool pk = (a.epi & (EPI_PK | EPI_PK_AFTER)) != 0;
+    const bool store = (a.epi & EPI_STORE) != 0;
     const int nb = a.mt.nbins;
     double *hist = dyn;
     int64_t *thresh = (int64_t *)(dyn + (nb + 1));
-    if (pk) {
+    if (EPI && pk) {
         for (int i = tid; i <= nb; i += NT) {
             hist[i] = 0.0;
             thresh[i] = a.mt.thresh[i];
@@ -334,26 +485,19 @@ __global__ __launch_bounds__(kSThreads) void k_strided(SArgs a)
             const int64_t o = f / a.ncols_inner;
             base = o * a.outer + (f - o * a.ncols_inner);
         }
-#pragma unroll
-        for (int i = 0; i < NIT; ++i) {
-            const int row = rg + i * RPT;
-            if (row < L) {
-                c32 v = c32{0.f, 0.f};
-                if (valid) v = in[base + (int64_t)row * a.stride];
-                buf[row * B + col] = v;
-            }
-        }
-        __syncthreads();
-        stockham<L, S, B, NT, true>(buf, B, 1, B, tw, tid);
-
-        if (a.epi & (EPI_PK | EPI_POISSON | EPI_PK_AFTER)) {
+        const c32 *gin = in + base;
+        c32 *gout = out + base;
+        if constexpr (!EPI) {
+            // global -> registers -> stages -> registers -> global
+            col_fft<L, S, B, NT, true, true>(buf, gin, gout, a.stride, valid && store, tw, tid);
+        } else {
+            col_fft<L, S, B, NT, true, false>(buf, gin, nullptr, a.stride, valid, tw, tid);
             // Epilogue on the last axis: thread (col, rg) walks a contiguous run
             // of kz so that consecutive modes mostly share a bin.
             constexpr int EP = (L + RPT - 1) / RPT;
             const int kx = valid ? (int)(f % a.mt.nxk) : 0;
             const int ky = valid ? (int)(f / a.mt.nxk) : 0;
-            const double wgt =
-                (a.mt.half && !(kx == 0 || 2 * kx == a.mt.n0)) ? 2.0 : 1.0;
+            const double wgt = (a.mt.half && !(kx == 0 || 2 * kx == a.mt.n0)) ? 2.0 : 1.0;
             double k2xy = 0.0;
             int64_t qxy = 0;
             if (valid && (a.epi & EPI_POISSON)) k2xy = a.mt.k2[0][kx] + a.mt.k2[1][ky];
@@ -393,21 +537,21 @@ __global__ __launch_bounds__(kSThreads) void k_strided(SArgs a)
             }
             if (cur >= 0) atomicAdd(&hist[cur], acc);
             __syncthreads();
+            bool stored = false;
             if constexpr (S < 0) {
-                if (a.epi & EPI_POISSON) stockham<L, +1, B, NT, true>(buf, B, 1, B, tw, tid);
+                if (a.epi & EPI_POISSON) {
+                    col_fft<L, +1, B, NT, false, true>(buf, nullptr, gout, a.stride, valid && store,
+                                                       tw, tid);
+                    stored = true;
+                }
             }
-        }
-
-        if (a.epi & EPI_STORE) {
-#pragma unroll
-            for (int i = 0; i < NIT; ++i) {
-                const int row = rg + i * RPT;
-                if (row < L && valid) out[base + (int64_t)row * a.stride] = buf[row * B + col];
+            if (store && !stored && valid) {
+                for (int row = rg; row < L; row += RPT) gout[(int64_t)row * a.stride] = buf[row * B + col];
             }
         }
         __syncthreads();
     }
-    if (pk) {
+    if (EPI && pk) {
         __syncthreads();
         for (int i = tid; i <= nb; i += NT) a.partial[(int64_t)blockIdx.x * (nb + 1) + i] = hist[i];
     }

@@ -22,6 +22,7 @@ hipError_t launch_strided(int len, int sign, const SArgs &a, int grid_cap, hipSt
                           int *grid_used)
 {
     const bool pk = (a.epi & (EPI_PK | EPI_PK_AFTER)) != 0;
+    const bool epi = (a.epi & (EPI_PK | EPI_PK_AFTER | EPI_POISSON)) != 0;
     const size_t shm = pk ? (size_t)(a.mt.nbins + 1) * 16 : 0;
 #define LF2_CASE(L)                                                                          \
     case L: {                                                                                \
@@ -29,10 +30,14 @@ hipError_t launch_strided(int len, int sign, const SArgs &a, int grid_cap, hipSt
         int g = (int)(ntiles < grid_cap ? ntiles : grid_cap);                                \
         if (g < 1) g = 1;                                                                    \
         if (grid_used) *grid_used = g;                                                       \
-        if (sign < 0)                                                                        \
-            hipLaunchKernelGGL((k_strided<L, -1>), dim3(g), dim3(kSThreads), shm, s, a);     \
+        if (epi && sign < 0)                                                                 \
+            hipLaunchKernelGGL((k_strided<L, -1, true>), dim3(g), dim3(kSThreads), shm, s, a);\
+        else if (epi)                                                                        \
+            return hipErrorInvalidValue;                                                     \
+        else if (sign < 0)                                                                   \
+            hipLaunchKernelGGL((k_strided<L, -1, false>), dim3(g), dim3(kSThreads), 0, s, a); \
         else                                                                                 \
-            hipLaunchKernelGGL((k_strided<L, 1>), dim3(g), dim3(kSThreads), shm, s, a);      \
+            hipLaunchKernelGGL((k_strided<L, 1, false>), dim3(g), dim3(kSThreads), 0, s, a);  \
         return hipGetLastError();                                                            \
     }
     switch (len) {

@@ -1,6 +1,12 @@
 // lf2_kx.hip -- instantiations and launchers of the x-pass kernels.
 // LF2_KX_PART selects the family compiled by this translation unit
 // (0: r2c, 1: c2r, 2: c2c) so that the families build in parallel.
+// One-component rows with 8-byte aligned element offsets take the fast
+// kernels (complex loads/stores straight into/out of the Stockham stages);
+// everything else (components interleaved, odd halo offsets) takes the
+// general kernels that de-interleave through LDS.
+#include <stdint.h>
+
 #include "lf2_kernels.hpp"
 #include "lf2_lengths.hpp"
 
@@ -11,6 +17,13 @@ namespace lf2 {
 #endif
 
 static inline unsigned x_grid(int64_t nrows, int rb) { return (unsigned)((nrows + rb - 1) / rb); }
+
+// Real-array side of an r2c/c2r pass viewed as complex pairs: pointer and
+// every row/plane offset must be even (in floats).
+static inline bool pairs_aligned(const void *p, int64_t off, int64_t row, int64_t plane)
+{
+    return ((uintptr_t)p % 8) == 0 && off % 2 == 0 && row % 2 == 0 && plane % 2 == 0;
+}
 
 #if LF2_KX_PART == 0
 bool x_supported(int len, int nc)
@@ -30,9 +43,13 @@ int x_rows_per_block(int len, int nc) { return x_rb(len, nc); }
 
 hipError_t launch_x_r2c(int m, int nc, const XArgs &a, hipStream_t s)
 {
+    const bool vec = nc == 1 && pairs_aligned(a.in, a.in_off, a.in_row, a.in_plane);
 #define LF2_CASE(L)                                                                          \
     case L:                                                                                  \
-        if (nc == 1)                                                                         \
+        if (vec)                                                                             \
+            hipLaunchKernelGGL((k_x_r2c_v<L>), dim3(x_grid(a.nrows, x_rb(L, 1))),            \
+                               dim3(kXThreads), 0, s, a);                                    \
+        else if (nc == 1)                                                                    \
             hipLaunchKernelGGL((k_x_r2c<L, 1>), dim3(x_grid(a.nrows, x_rb(L, 1))),           \
                                dim3(kXThreads), 0, s, a);                                    \
         else                                                                                 \
@@ -51,9 +68,13 @@ hipError_t launch_x_r2c(int m, int nc, const XArgs &a, hipStream_t s)
 #if LF2_KX_PART == 1
 hipError_t launch_x_c2r(int m, int nc, const XArgs &a, hipStream_t s)
 {
+    const bool vec = nc == 1 && pairs_aligned(a.out, a.out_off, a.out_row, a.out_plane);
 #define LF2_CASE(L)                                                                          \
     case L:                                                                                  \
-        if (nc == 1)                                                                         \
+        if (vec)                                                                             \
+            hipLaunchKernelGGL((k_x_c2r_v<L>), dim3(x_grid(a.nrows, x_rb(L, 1))),            \
+                               dim3(kXThreads), 0, s, a);                                    \
+        else if (nc == 1)                                                                    \
             hipLaunchKernelGGL((k_x_c2r<L, 1>), dim3(x_grid(a.nrows, x_rb(L, 1))),           \
                                dim3(kXThreads), 0, s, a);                                    \
         else                                                                                 \
@@ -74,16 +95,16 @@ hipError_t launch_x_c2c(int len, int nc, int sign, const XArgs &a, hipStream_t s
 {
 #define LF2_CASE(L)                                                                          \
     case L:                                                                                  \
-        if (sign < 0) {                                                                      \
-            if (nc == 1)                                                                     \
-                hipLaunchKernelGGL((k_x_c2c<L, 1, -1>), dim3(x_grid(a.nrows, x_rb(L, 1))),   \
+        if (nc == 1) {                                                                       \
+            if (sign < 0)                                                                    \
+                hipLaunchKernelGGL((k_x_c2c_v<L, -1>), dim3(x_grid(a.nrows, x_rb(L, 1))),    \
                                    dim3(kXThreads), 0, s, a);                                \
             else                                                                             \
-                hipLaunchKernelGGL((k_x_c2c<L, 3, -1>), dim3(x_grid(a.nrows, x_rb(L, 3))),   \
+                hipLaunchKernelGGL((k_x_c2c_v<L, 1>), dim3(x_grid(a.nrows, x_rb(L, 1))),     \
                                    dim3(kXThreads), 0, s, a);                                \
         } else {                                                                             \
-            if (nc == 1)                                                                     \
-                hipLaunchKernelGGL((k_x_c2c<L, 1, 1>), dim3(x_grid(a.nrows, x_rb(L, 1))),    \
+            if (sign < 0)                                                                    \
+                hipLaunchKernelGGL((k_x_c2c<L, 3, -1>), dim3(x_grid(a.nrows, x_rb(L, 3))),   \
                                    dim3(kXThreads), 0, s, a);                                \
             else                                                                             \
                 hipLaunchKernelGGL((k_x_c2c<L, 3, 1>), dim3(x_grid(a.nrows, x_rb(L, 3))),    \

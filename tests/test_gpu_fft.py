@@ -119,7 +119,8 @@ def test_halo_matches_dense(lf2, shape, halo):
     F0 = p0.forward(torch.from_numpy(dense[..., 0]).to(dev()))
     Fh = ph.forward(torch.from_numpy(pad[..., 0]).to(dev()))
     torch.cuda.synchronize()
-    assert torch.equal(F0, Fh)
+    # odd halos take the general kernel, even ones the paired fast kernel
+    assert rel_l2(Fh.cpu().numpy(), F0.cpu().numpy()) <= 1e-6
     # backward writes the interior only
     out = torch.full(ph.x_shape, 7.0, dtype=torch.float32, device=dev())
     ph.backward(Fh, out=out)
@@ -128,7 +129,7 @@ def test_halo_matches_dense(lf2, shape, halo):
     h = halo
     o = out.cpu().numpy()
     n0, n1, n2 = shape
-    assert np.array_equal(o[h:h + n2, h:h + n1, h:h + n0], ref.cpu().numpy())
+    assert rel_l2(o[h:h + n2, h:h + n1, h:h + n0], ref.cpu().numpy()) <= 1e-6
     mask = np.ones(o.shape, bool)
     mask[h:h + n2, h:h + n1, h:h + n0] = False
     assert np.all(o[mask] == 7.0)
@@ -143,7 +144,7 @@ def test_aos_three_components_equal_scalar(lf2):
     for c in range(3):
         F1 = p1.forward(torch.from_numpy(np.ascontiguousarray(z[..., c])).to(dev()))
         torch.cuda.synchronize()
-        assert torch.equal(F3[..., c].contiguous(), F1)
+        assert rel_l2(F3[..., c].cpu().numpy(), F1.cpu().numpy()) <= 1e-6
 
 
 def test_deterministic(lf2):
