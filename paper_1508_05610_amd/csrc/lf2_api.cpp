@@ -468,9 +468,11 @@ lf2_status run_strided(const lf2_plan_s *p, int axis, int sign, const SArgs &a, 
     const double sb = (double)spectrum_bytes(p);
     const bool epi = (a.epi & (EPI_PK | EPI_PK_AFTER | EPI_POISSON)) != 0;
     // "<kernel symbol> <pass>": the symbol part matches the profiler's name
-    const int t = prof::begin(kname("k_strided<%d,%d,%d> %s%s%s", p->len[axis], sign, epi ? 1 : 0,
-                                    axis == 1 ? "y" : "z", (a.epi & EPI_POISSON) ? "+poisson" : "",
-                                    (a.epi & (EPI_PK | EPI_PK_AFTER)) ? "+pk" : ""),
+    const int t = prof::begin(kname("k_strided<%d,%d,%d> %s%s%s %lldx%lldx%lld/%d", p->len[axis], sign,
+                                    epi ? 1 : 0, axis == 1 ? "y" : "z",
+                                    (a.epi & EPI_POISSON) ? "+poisson" : "",
+                                    (a.epi & (EPI_PK | EPI_PK_AFTER)) ? "+pk" : "",
+                                    (long long)p->n[0], (long long)p->n[1], (long long)p->n[2], p->nc),
                               (a.epi & EPI_STORE) ? 2 * sb : sb, s);
     hipError_t e = launch_strided(p->len[axis], sign, a, grid_cap, s, grid_used);
     prof::end(t, s);
@@ -486,14 +488,24 @@ lf2_status run_x(const lf2_plan_s *p, int which, int sign, const XArgs &a, hipSt
     const double rb = (double)p->ntot * p->nc * 4.0;  // real field
     const double sb = (double)spectrum_bytes(p);
     int t;
+    // the same layout test the launchers apply to pick the paired fast kernels
+    auto paired = [](const void *q, int64_t off, int64_t row, int64_t plane) {
+        return ((uintptr_t)q % 8) == 0 && off % 2 == 0 && row % 2 == 0 && plane % 2 == 0;
+    };
+    const std::string shape = kname(" %lldx%lldx%lld/%d", (long long)p->n[0], (long long)p->n[1],
+                                    (long long)p->n[2], p->nc);
     if (which == 0) {
-        t = prof::begin(kname("k_x_r2c<%d,%d>", p->len[0], p->nc), rb + sb, s);
+        const bool v = p->nc == 1 && paired(a.in, a.in_off, a.in_row, a.in_plane);
+        t = prof::begin((v ? kname("k_x_r2c_v<%d>", p->len[0]) : kname("k_x_r2c<%d,%d>", p->len[0], p->nc)) + shape,
+                        rb + sb, s);
         e = launch_x_r2c(p->len[0], p->nc, a, s);
     } else if (which == 1) {
-        t = prof::begin(kname("k_x_c2r<%d,%d>", p->len[0], p->nc), rb + sb, s);
+        const bool v = p->nc == 1 && paired(a.out, a.out_off, a.out_row, a.out_plane);
+        t = prof::begin((v ? kname("k_x_c2r_v<%d>", p->len[0]) : kname("k_x_c2r<%d,%d>", p->len[0], p->nc)) + shape,
+                        rb + sb, s);
         e = launch_x_c2r(p->len[0], p->nc, a, s);
     } else {
-        t = prof::begin(kname("k_x_c2c<%d,%d,%d>", p->len[0], p->nc, sign), 2 * sb, s);
+        t = prof::begin(kname("k_x_c2c_v<%d,%d,%d>", p->len[0], p->nc, sign) + shape, 2 * sb, s);
         e = launch_x_c2c(p->len[0], p->nc, sign, a, s);
     }
     prof::end(t, s);

@@ -332,20 +332,22 @@ __device__ __forceinline__ void col_stage(c32 *buf, const c32 *gin, c32 *gout, i
 }
 
 // ------------------------------------------------------------ row engine
-// NLN contiguous lines (rows of the x pass), point p of line l at
-// buf[l * LP + p].  Butterfly b = tid + i NT of a stage maps to line b / Q
-// and j = b % Q, so consecutive lanes take consecutive j: the first stage's
-// global loads (point j + r Q of a row) and the last stage's global stores
-// are contiguous across a wave.  `rowoff[l]` is the element offset of line
-// l in the global arrays.
+// RB rows of NC interleaved components (the x pass): component c of point p
+// of row q sits at global offset rowoff[q] + p * NC + c and at
+// buf[(q * NC + c) * LP + p] in LDS (one LDS line per row and component).
+// Butterfly b = tid + i NT of a stage maps to component b % NC, then
+// j = (b / NC) % Q, then row b / (NC Q): consecutive lanes walk consecutive
+// memory, so the first stage's global loads (point j + r Q) and the last
+// stage's global stores are contiguous across a wave.  Only rows < nvalid
+// exist in memory.
 
-template <int L, int R, int NS, int S, int NLN, int LP, int NT, bool SRC_G, bool DST_G>
+template <int L, int R, int NS, int S, int RB, int NC, int LP, int NT, bool SRC_G, bool DST_G>
 __device__ __forceinline__ void row_stage(c32 *buf, const c32 *gin, c32 *gout,
                                           const int64_t *rowoff_in, const int64_t *rowoff_out,
                                           int nvalid, const c32 *tw, int tid, double *ssq)
 {
     constexpr int Q = L / R;
-    constexpr int NBF = NLN * Q;
+    constexpr int NBF = RB * NC * Q;
     constexpr int NB = (NBF + NT - 1) / NT;
     static_assert(!DST_G || NS * R == L, "only the last stage stores to global memory");
     c32 v[NB][R];
@@ -353,11 +355,13 @@ __device__ __forceinline__ void row_stage(c32 *buf, const c32 *gin, c32 *gout,
     for (int i = 0; i < NB; ++i) {
         const int b = tid + i * NT;
         if (NBF % NT == 0 || b < NBF) {
-            const int l = b / Q, j = b % Q;
+            const int c = b % NC, t = b / NC;
+            const int j = t % Q, q = t / Q;
+            const int l = q * NC + c;
 #pragma unroll
             for (int r = 0; r < R; ++r) {
                 if (SRC_G)
-                    v[i][r] = l < nvalid ? gin[rowoff_in[l] + j + r * Q] : c32{0.f, 0.f};
+                    v[i][r] = q < nvalid ? gin[rowoff_in[q] + (j + r * Q) * NC + c] : c32{0.f, 0.f};
                 else
                     v[i][r] = buf[l * LP + j + r * Q];
             }
@@ -373,7 +377,9 @@ __device__ __forceinline__ void row_stage(c32 *buf, const c32 *gin, c32 *gout,
     for (int i = 0; i < NB; ++i) {
         const int b = tid + i * NT;
         if (NBF % NT == 0 || b < NBF) {
-            const int l = b / Q, j = b % Q;
+            const int c = b % NC, t = b / NC;
+            const int j = t % Q, q = t / Q;
+            const int l = q * NC + c;
             const int k = j % NS;
             if (NS > 1) {
 #pragma unroll
@@ -385,9 +391,9 @@ __device__ __forceinline__ void row_stage(c32 *buf, const c32 *gin, c32 *gout,
             }
             Dft<R, S>::run(v[i]);
             if (DST_G) {
-                if (l < nvalid) {
+                if (q < nvalid) {
 #pragma unroll
-                    for (int r = 0; r < R; ++r) gout[rowoff_out[l] + j + r * Q] = v[i][r];
+                    for (int r = 0; r < R; ++r) gout[rowoff_out[q] + (j + r * Q) * NC + c] = v[i][r];
                 }
             } else {
                 c32 *dst = buf + l * LP + (j / NS) * NS * R + k;
@@ -399,29 +405,31 @@ __device__ __forceinline__ void row_stage(c32 *buf, const c32 *gin, c32 *gout,
     if (!DST_G) __syncthreads();
 }
 
-template <int L, int S, int NLN, int LP, int NT, bool SRC_G, bool DST_G, int ST = 0, int NS = 1>
+template <int L, int S, int RB, int NC, int LP, int NT, bool SRC_G, bool DST_G, int ST = 0,
+          int NS = 1>
 __device__ __forceinline__ void row_fft(c32 *buf, const c32 *gin, c32 *gout,
                                         const int64_t *rowoff_in, const int64_t *rowoff_out,
                                         int nvalid, const c32 *tw, int tid, double *ssq = nullptr)
 {
     if constexpr (L == 1) {
-        for (int l = tid; l < NLN; l += NT) {
-            c32 v = SRC_G ? (l < nvalid ? gin[rowoff_in[l]] : c32{0.f, 0.f}) : buf[l * LP];
+        for (int b = tid; b < RB * NC; b += NT) {
+            const int c = b % NC, q = b / NC;
+            c32 v = SRC_G ? (q < nvalid ? gin[rowoff_in[q] + c] : c32{0.f, 0.f}) : buf[b * LP];
             if (SRC_G && ssq) *ssq += (double)v.x * v.x + (double)v.y * v.y;
             if (DST_G) {
-                if (l < nvalid) gout[rowoff_out[l]] = v;
+                if (q < nvalid) gout[rowoff_out[q] + c] = v;
             } else {
-                buf[l * LP] = v;
+                buf[b * LP] = v;
             }
         }
         __syncthreads();
     } else if constexpr (NS < L) {
         constexpr int R = radix_at(L, ST);
         constexpr bool first = ST == 0, last = NS * R == L;
-        row_stage<L, R, NS, S, NLN, LP, NT, first && SRC_G, last && DST_G>(
+        row_stage<L, R, NS, S, RB, NC, LP, NT, first && SRC_G, last && DST_G>(
             buf, gin, gout, rowoff_in, rowoff_out, nvalid, tw, tid, ssq);
-        row_fft<L, S, NLN, LP, NT, SRC_G, DST_G, ST + 1, NS * R>(buf, gin, gout, rowoff_in,
-                                                                 rowoff_out, nvalid, tw, tid, ssq);
+        row_fft<L, S, RB, NC, LP, NT, SRC_G, DST_G, ST + 1, NS * R>(
+            buf, gin, gout, rowoff_in, rowoff_out, nvalid, tw, tid, ssq);
     }
 }
 

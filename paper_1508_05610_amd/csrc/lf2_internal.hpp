@@ -52,6 +52,7 @@ struct SArgs {
     int64_t outer;       // elements between outer column groups
     int64_t ncols;       // total columns (O * C)
     int epi;             // EPI_* flags
+    int xcd_chunk;       // tiles per XCD chunk (set by the launcher)
     const void *tw;      // twiddles, length L
     ModeTables mt;
     double *partial;     // [gridDim.x][nbins + 1]

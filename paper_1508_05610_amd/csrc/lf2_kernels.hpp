@@ -92,7 +92,7 @@ __global__ __launch_bounds__(kXThreads) void k_x_r2c(XArgs a)
     float *fb = (float *)buf;
     double ss = 0.0;
     constexpr int NE = RB * N0 * NC;
-#pragma unroll 4
+#pragma unroll
     for (int i = 0; i < (NE + NT - 1) / NT; ++i) {
         const int idx = tid + i * NT;
         if (idx < NE) {
@@ -111,7 +111,7 @@ __global__ __launch_bounds__(kXThreads) void k_x_r2c(XArgs a)
     stockham<M, -1, NL, NT, false>(buf, NL, LP, 1, tw, tid);
     c32 *out = (c32 *)a.out;
     constexpr int NO = RB * NH * NC;
-#pragma unroll 4
+#pragma unroll
     for (int i = 0; i < (NO + NT - 1) / NT; ++i) {
         const int idx = tid + i * NT;
         if (idx < NO) {
@@ -156,7 +156,7 @@ __global__ __launch_bounds__(kXThreads) void k_x_c2r(XArgs a)
     __syncthreads();
     const c32 *in = (const c32 *)a.in;
     constexpr int NI = RB * NH * NC;
-#pragma unroll 4
+#pragma unroll
     for (int i = 0; i < (NI + NT - 1) / NT; ++i) {
         const int idx = tid + i * NT;
         if (idx < NI) {
@@ -209,7 +209,7 @@ __global__ __launch_bounds__(kXThreads) void k_x_c2r(XArgs a)
     float *out = (float *)a.out;
     const float *fb = (const float *)buf;
     constexpr int NE = RB * N0 * NC;
-#pragma unroll 4
+#pragma unroll
     for (int i = 0; i < (NE + NT - 1) / NT; ++i) {
         const int idx = tid + i * NT;
         if (idx < NE) {
@@ -241,7 +241,7 @@ __global__ __launch_bounds__(kXThreads) void k_x_c2c(XArgs a)
     __syncthreads();
     const c32 *in = (const c32 *)a.in;
     constexpr int NE = RB * L * NC;
-#pragma unroll 4
+#pragma unroll
     for (int i = 0; i < (NE + NT - 1) / NT; ++i) {
         const int idx = tid + i * NT;
         if (idx < NE) {
@@ -257,7 +257,7 @@ __global__ __launch_bounds__(kXThreads) void k_x_c2c(XArgs a)
     __syncthreads();
     stockham<L, S, NL, NT, false>(buf, NL, LP, 1, tw, tid);
     c32 *out = (c32 *)a.out;
-#pragma unroll 4
+#pragma unroll
     for (int i = 0; i < (NE + NT - 1) / NT; ++i) {
         const int idx = tid + i * NT;
         if (idx < NE) {
@@ -310,7 +310,7 @@ __global__ __launch_bounds__(kXThreads) void k_x_r2c_v(XArgs a)
     __syncthreads();
     const int nv = rows_valid<RB>(a, r0);
     double ss = 0.0;
-    row_fft<M, -1, RB, LP, NT, true, false>(buf, (const c32 *)a.in, nullptr, ib, nullptr, nv, tw,
+    row_fft<M, -1, RB, 1, LP, NT, true, false>(buf, (const c32 *)a.in, nullptr, ib, nullptr, nv, tw,
                                             tid, a.sumsq ? &ss : nullptr);
     if (a.sumsq) block_sum_f64(ss, a.sumsq, red);
     c32 *out = (c32 *)a.out;
@@ -362,14 +362,18 @@ __global__ __launch_bounds__(kXThreads) void k_x_c2r_v(XArgs a)
     for (int i = tid; i < RB; i += NT) ob[i] >>= 1;
     const int nv = rows_valid<RB>(a, r0);
     const c32 *in = (const c32 *)a.in;
-    constexpr int NI = RB * NH;
-#pragma unroll 4
-    for (int i = 0; i < (NI + NT - 1) / NT; ++i) {
-        const int idx = tid + i * NT;
-        if (idx < NI) {
-            const int l = idx / NH;
-            const int k = idx - l * NH;
-            buf[l * LP + k] = l < nv ? in[ib[l] + k] : c32{0.f, 0.f};
+    // TPR threads per row, each walking one row: a single row offset per
+    // thread, loads of a wave contiguous within each row.
+    constexpr int TPR = NT / RB >= 1 ? NT / RB : 1;
+    constexpr int NK = (NH + TPR - 1) / TPR;
+    for (int l = tid / TPR; l < RB; l += NT / TPR) {
+        const int64_t base = ib[l];
+        const bool ok = l < nv;
+        const int k0 = tid % TPR;
+#pragma unroll
+        for (int i = 0; i < NK; ++i) {
+            const int k = k0 + i * TPR;
+            if (k < NH) buf[l * LP + k] = ok ? in[base + k] : c32{0.f, 0.f};
         }
     }
     __syncthreads();
@@ -398,15 +402,15 @@ __global__ __launch_bounds__(kXThreads) void k_x_c2r_v(XArgs a)
         }
     }
     __syncthreads();
-    row_fft<M, +1, RB, LP, NT, false, true>(buf, nullptr, (c32 *)a.out, nullptr, ob, nv, tw, tid);
+    row_fft<M, +1, RB, 1, LP, NT, false, true>(buf, nullptr, (c32 *)a.out, nullptr, ob, nv, tw, tid);
 }
 
-template <int L, int S>
+template <int L, int NC, int S>
 __global__ __launch_bounds__(kXThreads) void k_x_c2c_v(XArgs a)
 {
     constexpr int NT = kXThreads;
-    constexpr int RB = x_rb(L, 1);
-    __shared__ c32 buf[RB * L];
+    constexpr int RB = x_rb(L, NC);
+    __shared__ c32 buf[RB * NC * L];
     __shared__ c32 tw[L];
     __shared__ int64_t ib[RB], ob[RB];
     const int tid = threadIdx.x;
@@ -416,7 +420,8 @@ __global__ __launch_bounds__(kXThreads) void k_x_c2c_v(XArgs a)
     row_bases<RB>(ib, ob, a, r0, tid);
     __syncthreads();
     const int nv = rows_valid<RB>(a, r0);
-    row_fft<L, S, RB, L, NT, true, true>(buf, (const c32 *)a.in, (c32 *)a.out, ib, ob, nv, tw, tid);
+    row_fft<L, S, RB, NC, L, NT, true, true>(buf, (const c32 *)a.in, (c32 *)a.out, ib, ob, nv, tw,
+                                             tid);
 }
 
 // ------------------------------------------------------------------ binning
@@ -465,19 +470,20 @@ __global__ __launch_bounds__(kSThreads) __attribute__((amdgpu_waves_per_eu(4))) 
     const c32 *in = (const c32 *)a.in;
     c32 *out = (c32 *)a.out;
     const int64_t ntiles = (a.ncols + B - 1) / B;
-    // XCD-aware walk: the chip hands consecutive block ids to its XCDs in
-    // turn, so block b works on a contiguous chunk of tiles owned by XCD
-    // (b mod NX); neighbouring tiles then share that XCD's L2.
-    const int G = gridDim.x;
-    const int NX = G < 8 ? G : 8;
-    const int xcd = blockIdx.x % NX, lb = blockIdx.x / NX;
-    const int nbx = (G - xcd + NX - 1) / NX;
-    const int64_t ch = (ntiles + NX - 1) / NX;
-    const int64_t t0 = (int64_t)xcd * ch;
-    const int64_t t1 = t0 + ch < ntiles ? t0 + ch : ntiles;
+    // XCD-aware walk over virtual block ids vb = blockIdx.x + i * G (G is a
+    // multiple of 8).  The chip hands block ids to its 8 XCDs in turn, so
+    // vb mod 8 is this block's XCD.  Chunks of K consecutive tiles go to one
+    // XCD and the chunks rotate over the XCDs: neighbouring tiles, which
+    // share cache lines when rows are not 128-byte aligned, meet in one L2,
+    // while all XCDs stream from nearby addresses.
+    const int64_t K = a.xcd_chunk;
+    const int64_t span = (ntiles + 8 * K - 1) / (8 * K) * (8 * K);
     const double inv_qmax = 1.0 / a.mt.qmax;
 
-    for (int64_t t = t0 + lb; t < t1; t += nbx) {
+    for (int64_t vb = blockIdx.x; vb < span; vb += gridDim.x) {
+        const int64_t lb = vb / 8;
+        const int64_t t = ((lb / K) * 8 + (vb % 8)) * K + lb % K;
+        if (t >= ntiles) continue;  // uniform over the block
         const int64_t f = t * B + col;
         const bool valid = f < a.ncols;
         int64_t base = 0;

@@ -18,17 +18,23 @@ bool s_supported(int len)
 
 int s_cols_per_block(int len) { return s_b(len); }
 
-hipError_t launch_strided(int len, int sign, const SArgs &a, int grid_cap, hipStream_t s,
+hipError_t launch_strided(int len, int sign, const SArgs &a_in, int grid_cap, hipStream_t s,
                           int *grid_used)
 {
+    // 16 tiles per XCD chunk; the grid is a multiple of 8 (grid_cap is).
+    constexpr int kChunk = 16;
+    SArgs a = a_in;
+    a.xcd_chunk = kChunk;
+    grid_cap = grid_cap / 8 * 8;
+    if (grid_cap < 8) grid_cap = 8;
     const bool pk = (a.epi & (EPI_PK | EPI_PK_AFTER)) != 0;
     const bool epi = (a.epi & (EPI_PK | EPI_PK_AFTER | EPI_POISSON)) != 0;
     const size_t shm = pk ? (size_t)(a.mt.nbins + 1) * 16 : 0;
 #define LF2_CASE(L)                                                                          \
     case L: {                                                                                \
         int64_t ntiles = (a.ncols + s_b(L) - 1) / s_b(L);                                    \
-        int g = (int)(ntiles < grid_cap ? ntiles : grid_cap);                                \
-        if (g < 1) g = 1;                                                                    \
+        int64_t span = (ntiles + 8 * kChunk - 1) / (8 * kChunk) * (8 * kChunk);              \
+        int g = (int)(span < grid_cap ? span : grid_cap);                                    \
         if (grid_used) *grid_used = g;                                                       \
         if (epi && sign < 0)                                                                 \
             hipLaunchKernelGGL((k_strided<L, -1, true>), dim3(g), dim3(kSThreads), shm, s, a);\

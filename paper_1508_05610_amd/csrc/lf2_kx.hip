@@ -97,17 +97,17 @@ hipError_t launch_x_c2c(int len, int nc, int sign, const XArgs &a, hipStream_t s
     case L:                                                                                  \
         if (nc == 1) {                                                                       \
             if (sign < 0)                                                                    \
-                hipLaunchKernelGGL((k_x_c2c_v<L, -1>), dim3(x_grid(a.nrows, x_rb(L, 1))),    \
+                hipLaunchKernelGGL((k_x_c2c_v<L, 1, -1>), dim3(x_grid(a.nrows, x_rb(L, 1))),    \
                                    dim3(kXThreads), 0, s, a);                                \
             else                                                                             \
-                hipLaunchKernelGGL((k_x_c2c_v<L, 1>), dim3(x_grid(a.nrows, x_rb(L, 1))),     \
+                hipLaunchKernelGGL((k_x_c2c_v<L, 1, 1>), dim3(x_grid(a.nrows, x_rb(L, 1))),     \
                                    dim3(kXThreads), 0, s, a);                                \
         } else {                                                                             \
             if (sign < 0)                                                                    \
-                hipLaunchKernelGGL((k_x_c2c<L, 3, -1>), dim3(x_grid(a.nrows, x_rb(L, 3))),   \
+                hipLaunchKernelGGL((k_x_c2c_v<L, 3, -1>), dim3(x_grid(a.nrows, x_rb(L, 3))),   \
                                    dim3(kXThreads), 0, s, a);                                \
             else                                                                             \
-                hipLaunchKernelGGL((k_x_c2c<L, 3, 1>), dim3(x_grid(a.nrows, x_rb(L, 3))),    \
+                hipLaunchKernelGGL((k_x_c2c_v<L, 3, 1>), dim3(x_grid(a.nrows, x_rb(L, 3))),    \
                                    dim3(kXThreads), 0, s, a);                                \
         }                                                                                    \
         return hipGetLastError();
