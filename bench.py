@@ -57,6 +57,73 @@ def measured_traffic(kernel: str):
     return None if k is None else k.get("hbm_bytes_per_launch")
 
 
+def bench_batch(args, torch, np, lf2, stream):
+    """48 Poisson solves with fused 32-bin P(k) on uneven lattices (extents per
+    axis from {64, 96, 128, 160, 192, 256}, field 0 = 128x192x256): one
+    persistent launch in a hipGraph against 48 plain lf2_poisson_solve calls.
+    Inputs are seeded N(0,1) fields (run time does not depend on values; the
+    random-field parity of the same workload is in the tests)."""
+    import synth
+    from paper_1508_05610_amd import _lib
+    S = [64, 96, 128, 160, 192, 256]
+    draws = synth.choice(5, 48 * 3, len(S)).reshape(48, 3)
+    sizes = [(128, 192, 256)] + [tuple(S[j] for j in d) for d in draws[1:]]
+    nb = 32
+    dev = torch.device("cuda:0")
+    rhos = [torch.from_numpy(synth.normal(5, a * b * c, stream=i, dtype=np.float32)
+                             .reshape(c, b, a)).to(dev) for i, (a, b, c) in enumerate(sizes)]
+    phis = [torch.empty_like(r) for r in rhos]
+    pks = [torch.empty(nb, dtype=torch.float64, device=dev) for _ in sizes]
+    kms = [torch.empty(nb, dtype=torch.float64, device=dev) for _ in sizes]
+    cts = [torch.empty(nb, dtype=torch.float64, device=dev) for _ in sizes]
+    batch = lf2.Batch(sizes, nbins=nb)
+    plans = {}
+    for s in sizes:
+        if s not in plans:
+            plans[s] = lf2.Plan(s, lf2.LF2_R2C)
+    sh = int(stream.cuda_stream)
+
+    def run_batch():
+        batch.run(rhos, phis, pks, kms, cts, stream=stream)
+
+    def run_plain():
+        for s, r, p, a, b, c in zip(sizes, rhos, phis, pks, kms, cts):
+            _lib.lf2_poisson_solve(plans[s].handle, r.data_ptr(), p.data_ptr(), 1.0, 0, nb,
+                                   a.data_ptr(), b.data_ptr(), c.data_ptr(), 0, sh)
+
+    def timed(fn, reps):
+        for _ in range(2):
+            fn()
+        torch.cuda.synchronize()
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        for _ in range(reps):
+            fn()
+        b.record(stream)
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / reps
+
+    reps = max(3, args.steps)
+    t_batch = timed(run_batch, reps)
+    err = batch.error()
+    t_plain = timed(run_plain, reps)
+    points = sum(a * b * c for a, b, c in sizes)
+    alg = sum(8.0 * a * b * c + 64.0 * (a // 2 + 1) * b * c for a, b, c in sizes)
+    nitems, launches, wsb = batch.nitems, batch.launches, batch.workspace_bytes
+    batch.close()
+    return {
+        "workload": "48 Poisson + 32-bin P(k) solves, extents per axis from {64..256}, "
+                    "field 0 = 128x192x256",
+        "points": points, "batch_ms": round(t_batch, 4), "plain_ms": round(t_plain, 4),
+        "speedup_vs_plain": round(t_plain / t_batch, 3),
+        "batch_gbps_algorithmic": round(alg / (t_batch * 1e-3) / 1e9, 1),
+        "plain_gbps_algorithmic": round(alg / (t_plain * 1e-3) / 1e9, 1),
+        "work_items": nitems, "launches_per_run": launches, "plain_launches_per_run": 48 * 7,
+        "error_bits": err,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -66,6 +133,7 @@ def main():
     ap.add_argument("--nbins", type=int, default=128)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-errors", action="store_true")
+    ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--only", default=None,
                     help="time one op alone (r2c_fwd, c2r_bwd, c2c_fwd_3comp, c2c_bwd_3comp, "
                          "poisson_pk, copy) for profiler runs")
@@ -253,6 +321,9 @@ def main():
     res["r2c_fwd_gbps"] = round(alg_r2c / (r2c_ms * 1e-3) / 1e9, 1)
     res["r2c_fwd_roofline_frac"] = round(alg_r2c / (r2c_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
     res["c2r_bwd_roofline_frac"] = round(alg_r2c / (per_op["c2r_bwd"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
+
+    if not args.no_batch:
+        res["batch"] = bench_batch(args, torch, np, lf2, stream)
 
     # ---- CPU baseline: the FP64 oracle on the host cores, bounded sample
     errors = {}

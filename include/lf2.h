@@ -168,6 +168,53 @@ lf2_status lf2_power_spectrum(lf2_plan p, const void *field, int32_t field_is_ks
 lf2_status lf2_plan_destroy(lf2_plan p);
 
 /*
+ * Batched Poisson solves on many lattices of different sizes.  The work of
+ * all fields is grouped by pass and line length: one launch per group, in
+ * pass order (x r2c, y, z Poisson [+ binning], y backward, x c2r), each
+ * block taking one (field, tile) item, then one launch that finalizes every
+ * field's power spectrum; the sequence is captured once in a hipGraph and
+ * replayed by lf2_batch_execute.  Each field gives the same result as
+ * lf2_poisson_solve on it alone (power spectra within FP64 summation
+ * order).
+ *
+ * lats: nfields dense lattices (halo 0) whose N0/2, N1 and N2 are each one
+ *   of 16, 32, 48, 64, 80, 96, 128, 160, 192, 256, 384.
+ * ops: LF2_BATCH_POISSON, optionally | LF2_BATCH_PK for the fused
+ *   power spectrum of each rho with nbins bins (1..511).
+ * poisson_flags: 0 or LF2_POISSON_DISCRETE_K2.
+ * The batch owns the spectra of all fields (lf2_batch_info).  Plan creation
+ * synchronises the device.
+ */
+#define LF2_BATCH_POISSON 1u
+#define LF2_BATCH_PK 2u
+typedef struct lf2_batch_s *lf2_batch;
+
+lf2_status lf2_batch_plan(lf2_batch *out, int32_t nfields, const lf2_lattice *lats, uint32_t ops,
+                          int32_t nbins, double dx, uint32_t poisson_flags);
+
+/*
+ * Run the batch on `stream`.  rho and phi are host arrays of nfields device
+ * pointers (float fields of each lattice, 8-byte aligned, rho[f] != phi[f]);
+ * d_pk, d_kmean, d_count are NULL or host arrays of nfields device pointers
+ * to nbins doubles (an entry may be NULL).  When the pointer set differs
+ * from the previous call the stream is synchronised once and the field
+ * descriptors are uploaded before the graph launch.
+ */
+lf2_status lf2_batch_execute(lf2_batch b, const float *const *rho, float *const *phi,
+                             double *const *d_pk, double *const *d_kmean, double *const *d_count,
+                             void *stream);
+
+/* Synchronise the device; *err = 0, or LF2_ERR_DEVICE if a HIP error is
+ * pending from the batch's launches. */
+lf2_status lf2_batch_error(lf2_batch b, uint32_t *err);
+
+/* Work items, kernel launches per execution and workspace bytes. */
+lf2_status lf2_batch_info(lf2_batch b, int64_t *nitems, int32_t *launches,
+                          size_t *workspace_bytes);
+
+lf2_status lf2_batch_destroy(lf2_batch b);
+
+/*
  * Kernel timing (tracing).  While enabled, every kernel launch made by the
  * calls above is bracketed by two HIP events recorded on the launch's
  * stream and tagged with the kernel's name and its algorithmic HBM bytes

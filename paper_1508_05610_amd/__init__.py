@@ -14,15 +14,19 @@ Layouts (N0 fastest, paper section 3.4; components innermost, 3.5):
 from __future__ import annotations
 
 from . import _lib
-from ._lib import (LF2_BACKWARD, LF2_C2C, LF2_FORWARD, LF2_PK_OF_PHI, LF2_POISSON_DISCRETE_K2,
-                   LF2_R2C, LF2Error, lf2_fft_execute, lf2_fft_kspace, lf2_fft_plan,
-                   lf2_plan_destroy, lf2_plan_set_workspace, lf2_plan_workspace_bytes,
-                   lf2_poisson_solve, lf2_power_spectrum, lf2_version)
+from ._lib import (LF2_BACKWARD, LF2_BATCH_PK, LF2_BATCH_POISSON, LF2_C2C, LF2_FORWARD,
+                   LF2_PK_OF_PHI, LF2_POISSON_DISCRETE_K2, LF2_R2C, LF2Error, lf2_batch_destroy,
+                   lf2_batch_error, lf2_batch_execute, lf2_batch_info, lf2_batch_plan,
+                   lf2_fft_execute, lf2_fft_kspace, lf2_fft_plan, lf2_plan_destroy,
+                   lf2_plan_set_workspace, lf2_plan_workspace_bytes, lf2_poisson_solve,
+                   lf2_power_spectrum, lf2_version)
 
-__all__ = ["Plan", "LF2Error", "LF2_R2C", "LF2_C2C", "LF2_FORWARD", "LF2_BACKWARD",
-           "LF2_POISSON_DISCRETE_K2", "LF2_PK_OF_PHI", "lf2_fft_plan", "lf2_fft_execute",
-           "lf2_fft_kspace", "lf2_poisson_solve", "lf2_power_spectrum", "lf2_plan_destroy",
-           "lf2_plan_workspace_bytes", "lf2_plan_set_workspace", "lf2_version", "load"]
+__all__ = ["Plan", "Batch", "LF2Error", "LF2_R2C", "LF2_C2C", "LF2_FORWARD", "LF2_BACKWARD",
+           "LF2_POISSON_DISCRETE_K2", "LF2_PK_OF_PHI", "LF2_BATCH_POISSON", "LF2_BATCH_PK",
+           "lf2_fft_plan", "lf2_fft_execute", "lf2_fft_kspace", "lf2_poisson_solve",
+           "lf2_power_spectrum", "lf2_plan_destroy", "lf2_plan_workspace_bytes",
+           "lf2_plan_set_workspace", "lf2_batch_plan", "lf2_batch_execute", "lf2_batch_error",
+           "lf2_batch_info", "lf2_batch_destroy", "lf2_version", "load"]
 
 
 def load():
@@ -129,6 +133,20 @@ class Plan:
         res = (phi, pk, kmean, count)
         return res + (pv,) if parseval else res
 
+    def power_spectrum_into(self, field, nbins, pk, kmean, count, dx=1.0, field_is_kspace=False,
+                            stream=None):
+        """Like power_spectrum, into caller-owned float64 device tensors."""
+        import torch
+        if field_is_kspace:
+            fp = _ptr(field, "field", torch.complex64, self.k_shape)
+        else:
+            xdt = torch.float32 if self.kind == LF2_R2C else torch.complex64
+            fp = _ptr(field, "field", xdt, self.x_shape)
+        lf2_power_spectrum(self.handle, fp, int(bool(field_is_kspace)), nbins, dx,
+                           pk.data_ptr() if pk is not None else 0,
+                           kmean.data_ptr() if kmean is not None else 0,
+                           count.data_ptr() if count is not None else 0, _stream_handle(stream))
+
     def power_spectrum(self, field, nbins, dx=1.0, field_is_kspace=False, stream=None):
         """Returns (pk, kmean, count) as float64 device tensors."""
         import torch
@@ -144,3 +162,44 @@ class Plan:
         lf2_power_spectrum(self.handle, fp, int(bool(field_is_kspace)), nbins, dx, pk.data_ptr(),
                            kmean.data_ptr(), count.data_ptr(), _stream_handle(stream))
         return pk, kmean, count
+
+
+class Batch:
+    """Batched Poisson solves (optionally with fused power spectra) on many
+    lattices: grouped launches replayed from one hipGraph (see lf2_batch_plan
+    in include/lf2.h)."""
+
+    def __init__(self, sizes_list, nbins=0, dx=1.0, poisson_flags=0):
+        self.sizes = [tuple(int(v) for v in s) for s in sizes_list]
+        self.nbins = int(nbins)
+        ops = LF2_BATCH_POISSON | (LF2_BATCH_PK if nbins > 0 else 0)
+        self.handle = lf2_batch_plan(self.sizes, ops, nbins, dx, poisson_flags)
+        self.nitems, self.launches, self.workspace_bytes = lf2_batch_info(self.handle)
+
+    def close(self):
+        if self.handle:
+            lf2_batch_destroy(self.handle)
+            self.handle = 0
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def run(self, rhos, phis, pks=None, kmeans=None, counts=None, stream=None):
+        """rhos, phis: lists of float32 device tensors (N2, N1, N0) per field;
+        pks/kmeans/counts: optional lists of float64 device tensors (nbins)."""
+        import torch
+        n = len(self.sizes)
+        assert len(rhos) == n and len(phis) == n
+        for s, r, p in zip(self.sizes, rhos, phis):
+            shape = (s[2], s[1], s[0])
+            _ptr(r, "rho", torch.float32, shape)
+            _ptr(p, "phi", torch.float32, shape)
+        ptrs = lambda ts: None if ts is None else [t.data_ptr() if t is not None else 0 for t in ts]  # noqa: E731
+        lf2_batch_execute(self.handle, ptrs(rhos), ptrs(phis), ptrs(pks), ptrs(kmeans),
+                          ptrs(counts), _stream_handle(stream))
+
+    def error(self) -> int:
+        return lf2_batch_error(self.handle)

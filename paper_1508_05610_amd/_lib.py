@@ -55,6 +55,15 @@ _SIGS = {
     "lf2_poisson_solve": (_i32, [_vp, _vp, _vp, _f64, _u32, _i32, _vp, _vp, _vp, _vp, _vp]),
     "lf2_power_spectrum": (_i32, [_vp, _vp, _i32, _i32, _f64, _vp, _vp, _vp, _vp]),
     "lf2_plan_destroy": (_i32, [_vp]),
+    "lf2_batch_plan": (_i32, [ctypes.POINTER(_vp), _i32, ctypes.POINTER(lf2_lattice), _u32, _i32,
+                              _f64, _u32]),
+    "lf2_batch_execute": (_i32, [_vp, ctypes.POINTER(_vp), ctypes.POINTER(_vp),
+                                 ctypes.POINTER(_vp), ctypes.POINTER(_vp), ctypes.POINTER(_vp),
+                                 _vp]),
+    "lf2_batch_error": (_i32, [_vp, ctypes.POINTER(_u32)]),
+    "lf2_batch_info": (_i32, [_vp, ctypes.POINTER(_i64), ctypes.POINTER(_i32),
+                              ctypes.POINTER(ctypes.c_size_t)]),
+    "lf2_batch_destroy": (_i32, [_vp]),
     "lf2_profile_enable": (_i32, [_i32]),
     "lf2_profile_reset": (_i32, []),
     "lf2_profile_count": (_i32, []),
@@ -158,6 +167,72 @@ def lf2_power_spectrum(plan: int, field_ptr: int, field_is_kspace: int, nbins: i
 
 def lf2_plan_destroy(plan: int):
     _check(load().lf2_plan_destroy(plan), "lf2_plan_destroy")
+
+
+LF2_BATCH_POISSON = 1
+LF2_BATCH_PK = 2
+
+
+def _lattices(sizes_list):
+    arr = (lf2_lattice * len(sizes_list))()
+    for i, s in enumerate(sizes_list):
+        arr[i] = lf2_lattice(3, 0, (ctypes.c_int64 * 3)(*[int(v) for v in s]))
+    return arr
+
+
+def lf2_batch_plan(sizes_list, ops: int, nbins: int = 0, dx: float = 1.0,
+                   poisson_flags: int = 0) -> int:
+    out = _vp()
+    lats = _lattices(sizes_list)
+    _check(load().lf2_batch_plan(ctypes.byref(out), len(sizes_list), lats, int(ops), int(nbins),
+                                 float(dx), int(poisson_flags)), "lf2_batch_plan")
+    return out.value
+
+
+def lf2_batch_plan_status(sizes_list, ops: int, nbins: int = 0, dx: float = 1.0,
+                          poisson_flags: int = 0, halo: int = 0) -> int:
+    """Raw status of lf2_batch_plan (argument-validation tests); destroys any batch made."""
+    out = _vp()
+    lats = _lattices(sizes_list)
+    for i in range(len(sizes_list)):
+        lats[i].halo = int(halo)
+    st = load().lf2_batch_plan(ctypes.byref(out), len(sizes_list), lats, int(ops), int(nbins),
+                               float(dx), int(poisson_flags))
+    if st == LF2_OK and out.value:
+        load().lf2_batch_destroy(out)
+    return st
+
+
+def _ptr_array(ptrs):
+    if ptrs is None:
+        return None
+    return (_vp * len(ptrs))(*[p or None for p in ptrs])
+
+
+def lf2_batch_execute(batch: int, rho_ptrs, phi_ptrs, pk_ptrs=None, kmean_ptrs=None,
+                      count_ptrs=None, stream: int = 0):
+    _check(load().lf2_batch_execute(batch, _ptr_array(rho_ptrs), _ptr_array(phi_ptrs),
+                                    _ptr_array(pk_ptrs), _ptr_array(kmean_ptrs),
+                                    _ptr_array(count_ptrs), stream or None), "lf2_batch_execute")
+
+
+def lf2_batch_error(batch: int) -> int:
+    e = _u32()
+    _check(load().lf2_batch_error(batch, ctypes.byref(e)), "lf2_batch_error")
+    return int(e.value)
+
+
+def lf2_batch_info(batch: int):
+    n = _i64()
+    g = _i32()
+    w = ctypes.c_size_t()
+    _check(load().lf2_batch_info(batch, ctypes.byref(n), ctypes.byref(g), ctypes.byref(w)),
+           "lf2_batch_info")
+    return int(n.value), int(g.value), int(w.value)
+
+
+def lf2_batch_destroy(batch: int):
+    _check(load().lf2_batch_destroy(batch), "lf2_batch_destroy")
 
 
 def lf2_profile_enable(on: bool = True):

@@ -36,7 +36,9 @@ UNITS = [
     ("lf2_kx.hip", ["-DLF2_KX_PART=2"], "kx_c2c.o"),
     ("lf2_ks.hip", [], "ks.o"),
     ("lf2_kmisc.hip", [], "kmisc.o"),
+    ("lf2_kbatch.hip", [], "kbatch.o"),
     ("lf2_api.cpp", ["-x", "hip"], "api.o"),
+    ("lf2_batch.cpp", ["-x", "hip"], "batch.o"),
 ]
 
 

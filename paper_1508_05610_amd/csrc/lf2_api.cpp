@@ -23,10 +23,12 @@
 #include <vector>
 
 #include "lf2_internal.hpp"
+#include "lf2_plan.hpp"
 
 using namespace lf2;
 
-namespace {
+namespace lf2 {
+namespace host {
 
 thread_local std::string g_err;
 
@@ -41,18 +43,7 @@ lf2_status fail(lf2_status st, const char *fmt, ...)
     return st;
 }
 
-#define LF2_HIP(call)                                                                       \
-    do {                                                                                    \
-        hipError_t e_ = (call);                                                             \
-        if (e_ != hipSuccess) {                                                             \
-            return fail(e_ == hipErrorOutOfMemory ? LF2_ERR_OUT_OF_MEMORY : LF2_ERR_DEVICE, \
-                        "%s failed: %s", #call, hipGetErrorString(e_));                     \
-        }                                                                                   \
-    } while (0)
-
 constexpr int kMaxDevices = 64;
-constexpr int kPkGrid = 1024;          // blocks of a binning pass (partials rows)
-constexpr int kStridedGridCap = 1 << 30;
 
 // Shared workspace per device (the paper's temporary memory shared by plans).
 struct SharedWs {
@@ -180,45 +171,6 @@ std::string kname(const char *fmt, ...)
     va_end(ap);
     return buf;
 }
-
-}  // namespace
-
-struct K2Entry {
-    double dx;
-    int discrete;
-    double *tab[3];
-};
-
-struct ShellEntry {
-    int nbins;
-    int64_t *thresh;  // nbins + 1
-    double *count;    // nbins
-    double *sumk;     // nbins (sum w sqrt(q))
-};
-
-struct lf2_plan_s {
-    int device = 0;
-    lf2_fft_kind kind = LF2_R2C;
-    int nc = 1;
-    int halo = 0;
-    uint32_t flags = 0;
-    int64_t n[3] = {0, 0, 0};
-    int64_t nh = 0;    // N0/2 + 1
-    int64_t nxk = 0;   // k-space extent of dimension 0
-    int64_t ntot = 0;  // N0 N1 N2
-    int len[3] = {0, 0, 0};
-    void *tw[3] = {nullptr, nullptr, nullptr};
-    void *tw_post = nullptr;
-    int64_t *q[3] = {nullptr, nullptr, nullptr};
-    int64_t lcm = 1, qmax = 0;
-    std::vector<K2Entry> k2;
-    std::vector<ShellEntry> shells;
-    void *own_ws = nullptr;
-    size_t own_ws_bytes = 0;
-    std::vector<void *> allocs;
-};
-
-namespace {
 
 lf2_status plan_alloc(lf2_plan p, void **dst, size_t bytes)
 {
@@ -528,7 +480,22 @@ lf2_status pk_tail(lf2_plan p, const ShellEntry &sh, double *part, int grid, dou
     return LF2_OK;
 }
 
-}  // namespace
+lf2_status check_bins(const lf2_plan_s *p, int32_t nbins)
+{
+    if (nbins < 0) return fail(LF2_ERR_INVALID_ARG, "nbins %d < 0", nbins);
+    if (nbins > kMaxBins) return fail(LF2_ERR_UNSUPPORTED, "nbins %d > %d", nbins, kMaxBins);
+    if (nbins > 0) {
+        // nbins^2 * qmax must fit the exact integer bin rule
+        long double lim = (long double)nbins * nbins * (long double)p->qmax;
+        if (lim > 4.0e18L) return fail(LF2_ERR_UNSUPPORTED, "nbins^2 * qmax overflows the integer bin rule");
+    }
+    return LF2_OK;
+}
+
+}  // namespace host
+}  // namespace lf2
+
+using namespace lf2::host;
 
 // ===================================================================== C ABI
 
@@ -760,18 +727,6 @@ lf2_status lf2_fft_execute(lf2_plan p, lf2_direction dir, const void *in, void *
     if ((st = run_strided(p, 2, sg, s_args(p, 2, in, W, EPI_STORE), kStridedGridCap, s, nullptr))) return st;
     if ((st = run_strided(p, 1, sg, s_args(p, 1, W, W, EPI_STORE), kStridedGridCap, s, nullptr))) return st;
     return run_x(p, 2, sg, x_args(p, W, out, false, true, false), s);
-}
-
-static lf2_status check_bins(const lf2_plan_s *p, int32_t nbins)
-{
-    if (nbins < 0) return fail(LF2_ERR_INVALID_ARG, "nbins %d < 0", nbins);
-    if (nbins > kMaxBins) return fail(LF2_ERR_UNSUPPORTED, "nbins %d > %d", nbins, kMaxBins);
-    if (nbins > 0) {
-        // nbins^2 * qmax must fit the exact integer bin rule
-        long double lim = (long double)nbins * nbins * (long double)p->qmax;
-        if (lim > 4.0e18L) return fail(LF2_ERR_UNSUPPORTED, "nbins^2 * qmax overflows the integer bin rule");
-    }
-    return LF2_OK;
 }
 
 lf2_status lf2_poisson_solve(lf2_plan p, const float *rho, float *phi, double dx, uint32_t flags,

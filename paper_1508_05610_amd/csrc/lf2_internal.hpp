@@ -89,4 +89,41 @@ hipError_t launch_pk_finalize(const double *S, int nbins, const double *count, c
 int x_rows_per_block(int len, int nc);
 int s_cols_per_block(int len);
 
+// ---------------------------------------------------------------- batches
+// Passes of one field in a batched Poisson solve.
+enum : int {
+    BP_XF = 0,   // x r2c: rho -> W
+    BP_YF = 1,   // y forward on W
+    BP_Z = 2,    // z forward * -1/(N k^2) (+ binning) * z backward on W
+    BP_YI = 3,   // y backward on W
+    BP_XI = 4,   // x c2r: W -> phi
+    BP_FIN = 5,  // power-spectrum finalize (one item)
+    BP_COUNT = 6
+};
+
+struct BatchField {
+    XArgs xf, xi;
+    SArgs yf, z, yi;
+    int m, l1, l2;           // x, y, z line lengths
+    int ntiles[BP_COUNT];
+    int nbins;               // 0: no binning
+    double *partial;         // [ntiles[BP_Z]][nbins + 1]
+    const double *count;     // shell table of the lattice
+    const double *sumk;
+    double norm, kscale;     // dx^3 / N, 2 pi / (L dx)
+    double *pk, *kmean, *count_out;  // caller's device arrays (nullable)
+};
+
+struct BatchItem {
+    int field, tile;
+};
+
+constexpr int kBatchMaxBins = 511;
+bool batch_len_supported(int len);
+int batch_x_rows(int m);
+// One grouped launch: items of pass `pass` whose line length is `len`.
+hipError_t batch_group_launch(int pass, int len, const BatchField *fields,
+                              const BatchItem *items, int nitems, int nbins, hipStream_t s);
+hipError_t batch_finalize_launch(const BatchField *fields, int nfields, hipStream_t s);
+
 }  // namespace lf2

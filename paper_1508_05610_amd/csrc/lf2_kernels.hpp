@@ -1,20 +1,26 @@
 // lf2_kernels.hpp -- pass kernels of the 3-D FFT (gfx950).
 //
-// x pass  : lines along dimension 0 are contiguous in memory.  A block loads
-//           RB rows (all components of each row) with coalesced loads,
-//           de-interleaves the components into LDS lines, runs the Stockham
-//           stages in LDS and stores coalesced.  r2c packs N0 reals into N0/2
-//           complex values, transforms and splits the result into Nh bins;
-//           c2r does the reverse.
+// Every pass is written as a per-tile device function that works in an LDS
+// area handed to it by the caller.  The standalone kernels below run one
+// pass over one field; the batch kernel (lf2_kbatch.hip) runs the same tile
+// functions for many fields and passes inside one persistent launch.
+//
+// x pass  : lines along dimension 0 are contiguous in memory.  A tile is RB
+//           rows (all components of each row).  One-component rows with
+//           even element offsets are read as complex values straight into
+//           the first Stockham stage (r2c packs N0 reals as N0/2 complex
+//           values, transforms and splits the result into Nh bins; c2r does
+//           the reverse).  Other layouts (interleaved components of real
+//           fields, odd halo offsets) de-interleave through LDS.
 // strided : lines along dimension 1 or 2 have a large stride; consecutive
-//           columns are adjacent in memory.  A block takes a tile of B
-//           adjacent columns x L points, loads it row by row (B * 8 bytes
-//           contiguous per row), transforms the B columns in LDS (lanes walk
-//           adjacent columns, so LDS accesses are consecutive words) and
-//           stores the tile back.  This replaces the paper's rod transposes
-//           (the data never leaves its place; the tile is the transpose).
-//           Epilogues on the last axis: power-spectrum binning, the Poisson
-//           scale followed by the backward transform.
+//           columns are adjacent in memory.  A tile is B adjacent columns x
+//           L points: loaded row by row (B * 8 bytes contiguous per row)
+//           straight into the first stage, transformed in LDS with lanes
+//           walking adjacent columns, stored from the last stage.  This
+//           replaces the paper's rod transposes (the data never leaves its
+//           place; the tile is the transpose).  Epilogues on the last axis:
+//           power-spectrum binning and the Poisson scale followed by the
+//           backward transform.
 #pragma once
 #include "lf2_device.hpp"
 #include "lf2_internal.hpp"
@@ -24,11 +30,13 @@ namespace lf2 {
 constexpr int kXThreads = 256;
 constexpr int kSThreads = 512;
 
-// Rows per x-pass block: about 4096 complex values of LDS (32 KiB), at
+// Rows per x-pass tile: about 4096 * (NT / 256) complex values of LDS, at
 // most 256 rows.
-__host__ __device__ constexpr int x_rb(int L, int NC)
+__host__ __device__ constexpr int x_rb(int L, int NC, int NT = kXThreads)
 {
-    return ((4096 / L) / NC) < 1 ? 1 : (((4096 / L) / NC) > 256 ? 256 : ((4096 / L) / NC));
+    return ((4096 / L) / NC * (NT / 256)) < 1
+               ? 1
+               : (((4096 / L) / NC * (NT / 256)) > 256 ? 256 : ((4096 / L) / NC * (NT / 256)));
 }
 // Columns per strided tile: 64 KiB of LDS at most, >= 128-byte row segments
 // up to L = 512.
@@ -37,12 +45,14 @@ __host__ __device__ constexpr int s_b(int L)
     return L <= 128 ? 64 : L <= 256 ? 32 : L <= 512 ? 16 : L <= 1024 ? 8 : 4;
 }
 
-// Row base offsets of the RB rows of this block, in LDS.
-template <int RB>
+__host__ __device__ constexpr size_t al16(size_t b) { return (b + 15) & ~(size_t)15; }
+
+// Row base offsets of the RB rows of tile `blk`, in LDS.
+template <int RB, int NT>
 __device__ __forceinline__ void row_bases(int64_t *ib, int64_t *ob, const XArgs &a, int64_t r0,
                                           int tid)
 {
-    for (int i = tid; i < RB; i += kXThreads) {
+    for (int i = tid; i < RB; i += NT) {
         int64_t r = r0 + i;
         if (r >= a.nrows) r = a.nrows - 1;
         int64_t z = r / a.n1, y = r - z * a.n1;
@@ -51,7 +61,15 @@ __device__ __forceinline__ void row_bases(int64_t *ib, int64_t *ob, const XArgs 
     }
 }
 
-// FP64 block sum, one value per block into dst[blockIdx.x].
+template <int RB>
+__device__ __forceinline__ int rows_valid(const XArgs &a, int64_t r0)
+{
+    const int64_t left = a.nrows - r0;
+    return left < RB ? (int)left : RB;
+}
+
+// FP64 block sum of v into *dst (thread 0 writes).
+template <int NT>
 __device__ __forceinline__ void block_sum_f64(double v, double *dst, double *scratch)
 {
     for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
@@ -60,371 +78,334 @@ __device__ __forceinline__ void block_sum_f64(double v, double *dst, double *scr
     __syncthreads();
     if (threadIdx.x == 0) {
         double t = 0;
-        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += scratch[w];
-        dst[blockIdx.x] = t;
+        for (int w = 0; w < NT / 64; ++w) t += scratch[w];
+        *dst = t;
     }
 }
 
-// ------------------------------------------------------------------ r2c x pass
-template <int M, int NC>
-__global__ __launch_bounds__(kXThreads) void k_x_r2c(XArgs a)
+// Twiddle tables into LDS (callers wait at a barrier before use).
+__device__ __forceinline__ void load_table(c32 *dst, const void *src, int n, int tid, int nt)
 {
-    constexpr int NT = kXThreads;
-    constexpr int RB = x_rb(M, NC);
-    constexpr int NL = RB * NC;
-    constexpr int N0 = 2 * M;
-    constexpr int LP = M;
-    constexpr int NH = M + 1;
-    __shared__ c32 buf[NL * LP];
-    __shared__ c32 tw[M];
-    __shared__ c32 twp[NH];
-    __shared__ int64_t ib[RB], ob[RB];
-    __shared__ double red[NT / 64];
-    const int tid = threadIdx.x;
-    const c32 *gtw = (const c32 *)a.tw;
-    const c32 *gtp = (const c32 *)a.tw_post;
-    for (int i = tid; i < M; i += NT) tw[i] = gtw[i];
-    for (int i = tid; i < NH; i += NT) twp[i] = gtp[i];
-    const int64_t r0 = (int64_t)blockIdx.x * RB;
-    row_bases<RB>(ib, ob, a, r0, tid);
-    __syncthreads();
-    const float *in = (const float *)a.in;
-    float *fb = (float *)buf;
-    double ss = 0.0;
-    constexpr int NE = RB * N0 * NC;
-#pragma unroll
-    for (int i = 0; i < (NE + NT - 1) / NT; ++i) {
-        const int idx = tid + i * NT;
-        if (idx < NE) {
-            const int row = idx / (N0 * NC);
-            const int rem = idx - row * (N0 * NC);
-            const int x = rem / NC;
-            const int c = rem - x * NC;
-            float v = 0.f;
-            if (r0 + row < a.nrows) v = in[ib[row] + rem];
-            fb[(row * NC + c) * LP * 2 + x] = v;
-            ss += (double)v * (double)v;
-        }
+    const c32 *g = (const c32 *)src;
+    for (int i = tid; i < n; i += nt) dst[i] = g[i];
+}
+
+// =================================================================== x tiles
+
+// ---- general r2c: components de-interleaved through LDS
+template <int M, int NC, int NT>
+struct XR2CGen {
+    static constexpr int RB = x_rb(M, NC, NT), NL = RB * NC, N0 = 2 * M, LP = M, NH = M + 1;
+    static constexpr size_t O_BUF = 0, O_TW = al16(O_BUF + sizeof(c32) * NL * LP),
+                            O_TWP = al16(O_TW + sizeof(c32) * M),
+                            O_IB = al16(O_TWP + sizeof(c32) * NH), O_OB = O_IB + 8 * RB,
+                            O_RED = O_OB + 8 * RB, BYTES = al16(O_RED + 8 * (NT / 64));
+    static __device__ void tables(const XArgs &a, char *sm, int tid)
+    {
+        load_table((c32 *)(sm + O_TW), a.tw, M, tid, NT);
+        load_table((c32 *)(sm + O_TWP), a.tw_post, NH, tid, NT);
     }
-    if (a.sumsq) block_sum_f64(ss, a.sumsq, red);
-    __syncthreads();
-    stockham<M, -1, NL, NT, false>(buf, NL, LP, 1, tw, tid);
-    c32 *out = (c32 *)a.out;
-    constexpr int NO = RB * NH * NC;
+    // sumsq: where to put this tile's FP64 sum of squares (nullptr: skip)
+    static __device__ void tile(const XArgs &a, int64_t blk, char *sm, int tid, double *sumsq)
+    {
+        c32 *buf = (c32 *)(sm + O_BUF);
+        const c32 *tw = (const c32 *)(sm + O_TW), *twp = (const c32 *)(sm + O_TWP);
+        int64_t *ib = (int64_t *)(sm + O_IB), *ob = (int64_t *)(sm + O_OB);
+        const int64_t r0 = blk * RB;
+        row_bases<RB, NT>(ib, ob, a, r0, tid);
+        __syncthreads();
+        const float *in = (const float *)a.in;
+        float *fb = (float *)buf;
+        double ss = 0.0;
+        constexpr int NE = RB * N0 * NC;
 #pragma unroll
-    for (int i = 0; i < (NO + NT - 1) / NT; ++i) {
-        const int idx = tid + i * NT;
-        if (idx < NO) {
-            const int row = idx / (NH * NC);
-            const int rem = idx - row * (NH * NC);
-            const int k = rem / NC;
-            const int c = rem - k * NC;
-            if (r0 + row < a.nrows) {
-                const c32 *line = buf + (row * NC + c) * LP;
-                const c32 z = line[k == M ? 0 : k];
-                const c32 zc = conjg(line[k == 0 ? 0 : M - k]);
-                const c32 fe = scl(add(z, zc), 0.5f);
-                const c32 d = sub(z, zc);
-                const c32 fo = c32{0.5f * d.y, -0.5f * d.x};  // (z - zc) / (2i)
-                out[ob[row] + rem] = add(fe, mul(twp[k], fo));
+        for (int i = 0; i < (NE + NT - 1) / NT; ++i) {
+            const int idx = tid + i * NT;
+            if (idx < NE) {
+                const int row = idx / (N0 * NC);
+                const int rem = idx - row * (N0 * NC);
+                const int x = rem / NC;
+                const int c = rem - x * NC;
+                float v = 0.f;
+                if (r0 + row < a.nrows) v = in[ib[row] + rem];
+                fb[(row * NC + c) * LP * 2 + x] = v;
+                ss += (double)v * (double)v;
             }
         }
-    }
-}
-
-// ------------------------------------------------------------------ c2r x pass
-template <int M, int NC>
-__global__ __launch_bounds__(kXThreads) void k_x_c2r(XArgs a)
-{
-    constexpr int NT = kXThreads;
-    constexpr int RB = x_rb(M, NC);
-    constexpr int NL = RB * NC;
-    constexpr int N0 = 2 * M;
-    constexpr int LP = M + 1;
-    constexpr int NH = M + 1;
-    __shared__ c32 buf[NL * LP];
-    __shared__ c32 tw[M];
-    __shared__ c32 twp[NH];
-    __shared__ int64_t ib[RB], ob[RB];
-    const int tid = threadIdx.x;
-    const c32 *gtw = (const c32 *)a.tw;
-    const c32 *gtp = (const c32 *)a.tw_post;
-    for (int i = tid; i < M; i += NT) tw[i] = gtw[i];
-    for (int i = tid; i < NH; i += NT) twp[i] = gtp[i];
-    const int64_t r0 = (int64_t)blockIdx.x * RB;
-    row_bases<RB>(ib, ob, a, r0, tid);
-    __syncthreads();
-    const c32 *in = (const c32 *)a.in;
-    constexpr int NI = RB * NH * NC;
+        if (sumsq) block_sum_f64<NT>(ss, sumsq, (double *)(sm + O_RED));
+        __syncthreads();
+        stockham<M, -1, NL, NT, false>(buf, NL, LP, 1, tw, tid);
+        c32 *out = (c32 *)a.out;
+        constexpr int NO = RB * NH * NC;
 #pragma unroll
-    for (int i = 0; i < (NI + NT - 1) / NT; ++i) {
-        const int idx = tid + i * NT;
-        if (idx < NI) {
-            const int row = idx / (NH * NC);
-            const int rem = idx - row * (NH * NC);
-            const int k = rem / NC;
-            const int c = rem - k * NC;
-            c32 v = c32{0.f, 0.f};
-            if (r0 + row < a.nrows) v = in[ib[row] + rem];
-            buf[(row * NC + c) * LP + k] = v;
-        }
-    }
-    __syncthreads();
-    // Z[k] = (X[k] + conj X[M-k]) + i W^{-k} (X[k] - conj X[M-k]), k < M,
-    // with the imaginary parts of X[0] and X[M] dropped.
-    constexpr int NZ = NL * M;
-    constexpr int NZT = (NZ + NT - 1) / NT;
-    c32 zv[NZT];
-#pragma unroll
-    for (int i = 0; i < NZT; ++i) {
-        const int idx = tid + i * NT;
-        if (idx < NZ) {
-            const int l = idx / M;
-            const int k = idx - l * M;
-            const c32 *line = buf + l * LP;
-            c32 xk = line[k];
-            c32 xm = line[M - k];
-            if (k == 0) {
-                xk.y = 0.f;
-                xm.y = 0.f;
+        for (int i = 0; i < (NO + NT - 1) / NT; ++i) {
+            const int idx = tid + i * NT;
+            if (idx < NO) {
+                const int row = idx / (NH * NC);
+                const int rem = idx - row * (NH * NC);
+                const int k = rem / NC;
+                const int c = rem - k * NC;
+                if (r0 + row < a.nrows) {
+                    const c32 *line = buf + (row * NC + c) * LP;
+                    const c32 z = line[k == M ? 0 : k];
+                    const c32 zc = conjg(line[k == 0 ? 0 : M - k]);
+                    const c32 fe = scl(add(z, zc), 0.5f);
+                    const c32 d = sub(z, zc);
+                    const c32 fo = c32{0.5f * d.y, -0.5f * d.x};  // (z - zc) / (2i)
+                    out[ob[row] + rem] = add(fe, mul(twp[k], fo));
+                }
             }
-            const c32 xmc = conjg(xm);
-            const c32 s = add(xk, xmc);
-            const c32 d = mul(conjg(twp[k]), sub(xk, xmc));
-            zv[i] = c32{s.x - d.y, s.y + d.x};  // s + i d
         }
+        __syncthreads();
     }
-    __syncthreads();
-#pragma unroll
-    for (int i = 0; i < NZT; ++i) {
-        const int idx = tid + i * NT;
-        if (idx < NZ) {
-            const int l = idx / M;
-            const int k = idx - l * M;
-            buf[l * LP + k] = zv[i];
-        }
-    }
-    __syncthreads();
-    stockham<M, +1, NL, NT, false>(buf, NL, LP, 1, tw, tid);
-    float *out = (float *)a.out;
-    const float *fb = (const float *)buf;
-    constexpr int NE = RB * N0 * NC;
-#pragma unroll
-    for (int i = 0; i < (NE + NT - 1) / NT; ++i) {
-        const int idx = tid + i * NT;
-        if (idx < NE) {
-            const int row = idx / (N0 * NC);
-            const int rem = idx - row * (N0 * NC);
-            const int x = rem / NC;
-            const int c = rem - x * NC;
-            if (r0 + row < a.nrows) out[ob[row] + rem] = fb[(row * NC + c) * LP * 2 + x];
-        }
-    }
-}
+};
 
-// ------------------------------------------------------------------ c2c x pass
-template <int L, int NC, int S>
-__global__ __launch_bounds__(kXThreads) void k_x_c2c(XArgs a)
-{
-    constexpr int NT = kXThreads;
-    constexpr int RB = x_rb(L, NC);
-    constexpr int NL = RB * NC;
-    constexpr int LP = L;
-    __shared__ c32 buf[NL * LP];
-    __shared__ c32 tw[L];
-    __shared__ int64_t ib[RB], ob[RB];
-    const int tid = threadIdx.x;
-    const c32 *gtw = (const c32 *)a.tw;
-    for (int i = tid; i < L; i += NT) tw[i] = gtw[i];
-    const int64_t r0 = (int64_t)blockIdx.x * RB;
-    row_bases<RB>(ib, ob, a, r0, tid);
-    __syncthreads();
-    const c32 *in = (const c32 *)a.in;
-    constexpr int NE = RB * L * NC;
-#pragma unroll
-    for (int i = 0; i < (NE + NT - 1) / NT; ++i) {
-        const int idx = tid + i * NT;
-        if (idx < NE) {
-            const int row = idx / (L * NC);
-            const int rem = idx - row * (L * NC);
-            const int x = rem / NC;
-            const int c = rem - x * NC;
-            c32 v = c32{0.f, 0.f};
-            if (r0 + row < a.nrows) v = in[ib[row] + rem];
-            buf[(row * NC + c) * LP + x] = v;
-        }
+// ---- general c2r
+template <int M, int NC, int NT>
+struct XC2RGen {
+    static constexpr int RB = x_rb(M, NC, NT), NL = RB * NC, N0 = 2 * M, LP = M + 1, NH = M + 1;
+    static constexpr size_t O_BUF = 0, O_TW = al16(O_BUF + sizeof(c32) * NL * LP),
+                            O_TWP = al16(O_TW + sizeof(c32) * M),
+                            O_IB = al16(O_TWP + sizeof(c32) * NH), O_OB = O_IB + 8 * RB,
+                            BYTES = al16(O_OB + 8 * RB);
+    static __device__ void tables(const XArgs &a, char *sm, int tid)
+    {
+        load_table((c32 *)(sm + O_TW), a.tw, M, tid, NT);
+        load_table((c32 *)(sm + O_TWP), a.tw_post, NH, tid, NT);
     }
-    __syncthreads();
-    stockham<L, S, NL, NT, false>(buf, NL, LP, 1, tw, tid);
-    c32 *out = (c32 *)a.out;
+    static __device__ void tile(const XArgs &a, int64_t blk, char *sm, int tid)
+    {
+        c32 *buf = (c32 *)(sm + O_BUF);
+        const c32 *tw = (const c32 *)(sm + O_TW), *twp = (const c32 *)(sm + O_TWP);
+        int64_t *ib = (int64_t *)(sm + O_IB), *ob = (int64_t *)(sm + O_OB);
+        const int64_t r0 = blk * RB;
+        row_bases<RB, NT>(ib, ob, a, r0, tid);
+        __syncthreads();
+        const c32 *in = (const c32 *)a.in;
+        constexpr int NI = RB * NH * NC;
 #pragma unroll
-    for (int i = 0; i < (NE + NT - 1) / NT; ++i) {
-        const int idx = tid + i * NT;
-        if (idx < NE) {
-            const int row = idx / (L * NC);
-            const int rem = idx - row * (L * NC);
-            const int x = rem / NC;
-            const int c = rem - x * NC;
-            if (r0 + row < a.nrows) out[ob[row] + rem] = buf[(row * NC + c) * LP + x];
+        for (int i = 0; i < (NI + NT - 1) / NT; ++i) {
+            const int idx = tid + i * NT;
+            if (idx < NI) {
+                const int row = idx / (NH * NC);
+                const int rem = idx - row * (NH * NC);
+                const int k = rem / NC;
+                const int c = rem - k * NC;
+                c32 v = c32{0.f, 0.f};
+                if (r0 + row < a.nrows) v = in[ib[row] + rem];
+                buf[(row * NC + c) * LP + k] = v;
+            }
         }
+        __syncthreads();
+        // Z[k] = (X[k] + conj X[M-k]) + i W^{-k} (X[k] - conj X[M-k]), k < M,
+        // with the imaginary parts of X[0] and X[M] dropped.
+        constexpr int NZ = NL * M;
+        constexpr int NZT = (NZ + NT - 1) / NT;
+        c32 zv[NZT];
+#pragma unroll
+        for (int i = 0; i < NZT; ++i) {
+            const int idx = tid + i * NT;
+            if (idx < NZ) {
+                const int l = idx / M;
+                const int k = idx - l * M;
+                const c32 *line = buf + l * LP;
+                c32 xk = line[k];
+                c32 xm = line[M - k];
+                if (k == 0) {
+                    xk.y = 0.f;
+                    xm.y = 0.f;
+                }
+                const c32 xmc = conjg(xm);
+                const c32 s = add(xk, xmc);
+                const c32 d = mul(conjg(twp[k]), sub(xk, xmc));
+                zv[i] = c32{s.x - d.y, s.y + d.x};  // s + i d
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < NZT; ++i) {
+            const int idx = tid + i * NT;
+            if (idx < NZ) {
+                const int l = idx / M;
+                const int k = idx - l * M;
+                buf[l * LP + k] = zv[i];
+            }
+        }
+        __syncthreads();
+        stockham<M, +1, NL, NT, false>(buf, NL, LP, 1, tw, tid);
+        float *out = (float *)a.out;
+        const float *fb = (const float *)buf;
+        constexpr int NE = RB * N0 * NC;
+#pragma unroll
+        for (int i = 0; i < (NE + NT - 1) / NT; ++i) {
+            const int idx = tid + i * NT;
+            if (idx < NE) {
+                const int row = idx / (N0 * NC);
+                const int rem = idx - row * (N0 * NC);
+                const int x = rem / NC;
+                const int c = rem - x * NC;
+                if (r0 + row < a.nrows) out[ob[row] + rem] = fb[(row * NC + c) * LP * 2 + x];
+            }
+        }
+        __syncthreads();
     }
-}
+};
 
-// ------------------------------------------------- one-component fast x pass
-// Rows whose element offsets are even (8-byte aligned) are read as complex
-// values: the packed r2c line z[n] = x[2n] + i x[2n+1] comes straight from
-// memory into the first Stockham stage, and the last stage of c2r / c2c
-// stores straight to memory.
-
-template <int RB>
-__device__ __forceinline__ int rows_valid(const XArgs &a, int64_t r0)
-{
-    const int64_t left = a.nrows - r0;
-    return left < RB ? (int)left : RB;
-}
-
+// ---- one-component fast r2c.
 // X[k] = fe + W^k fo and X[M-k] = conj(fe - W^k fo), with
 // fe = (Z[k] + conj Z[M-k]) / 2, fo = (Z[k] - conj Z[M-k]) / (2i).
-template <int M>
-__global__ __launch_bounds__(kXThreads) void k_x_r2c_v(XArgs a)
-{
-    constexpr int NT = kXThreads;
-    constexpr int RB = x_rb(M, 1);
-    constexpr int LP = M;
-    constexpr int NH = M + 1;
-    constexpr int HALF = M / 2 + 1;  // pair items per line
-    __shared__ c32 buf[RB * LP];
-    __shared__ c32 tw[M];
-    __shared__ c32 twp[NH];
-    __shared__ int64_t ib[RB], ob[RB];
-    __shared__ double red[NT / 64];
-    const int tid = threadIdx.x;
-    const c32 *gtw = (const c32 *)a.tw;
-    const c32 *gtp = (const c32 *)a.tw_post;
-    for (int i = tid; i < M; i += NT) tw[i] = gtw[i];
-    for (int i = tid; i < NH; i += NT) twp[i] = gtp[i];
-    const int64_t r0 = (int64_t)blockIdx.x * RB;
-    row_bases<RB>(ib, ob, a, r0, tid);
-    __syncthreads();
-    for (int i = tid; i < RB; i += NT) ib[i] >>= 1;  // float offset -> complex offset
-    __syncthreads();
-    const int nv = rows_valid<RB>(a, r0);
-    double ss = 0.0;
-    row_fft<M, -1, RB, 1, LP, NT, true, false>(buf, (const c32 *)a.in, nullptr, ib, nullptr, nv, tw,
-                                            tid, a.sumsq ? &ss : nullptr);
-    if (a.sumsq) block_sum_f64(ss, a.sumsq, red);
-    c32 *out = (c32 *)a.out;
-    constexpr int NI = RB * HALF;
+template <int M, int NT>
+struct XR2CV {
+    static constexpr int RB = x_rb(M, 1, NT), LP = M, NH = M + 1, HALF = M / 2 + 1;
+    static constexpr size_t O_BUF = 0, O_TW = al16(O_BUF + sizeof(c32) * RB * LP),
+                            O_TWP = al16(O_TW + sizeof(c32) * M),
+                            O_IB = al16(O_TWP + sizeof(c32) * NH), O_OB = O_IB + 8 * RB,
+                            O_RED = O_OB + 8 * RB, BYTES = al16(O_RED + 8 * (NT / 64));
+    static __device__ void tables(const XArgs &a, char *sm, int tid)
+    {
+        load_table((c32 *)(sm + O_TW), a.tw, M, tid, NT);
+        load_table((c32 *)(sm + O_TWP), a.tw_post, NH, tid, NT);
+    }
+    static __device__ void tile(const XArgs &a, int64_t blk, char *sm, int tid, double *sumsq)
+    {
+        c32 *buf = (c32 *)(sm + O_BUF);
+        const c32 *tw = (const c32 *)(sm + O_TW), *twp = (const c32 *)(sm + O_TWP);
+        int64_t *ib = (int64_t *)(sm + O_IB), *ob = (int64_t *)(sm + O_OB);
+        const int64_t r0 = blk * RB;
+        row_bases<RB, NT>(ib, ob, a, r0, tid);
+        __syncthreads();
+        for (int i = tid; i < RB; i += NT) ib[i] >>= 1;  // float offset -> complex offset
+        __syncthreads();
+        const int nv = rows_valid<RB>(a, r0);
+        double ss = 0.0;
+        row_fft<M, -1, RB, 1, LP, NT, true, false>(buf, (const c32 *)a.in, nullptr, ib, nullptr,
+                                                   nv, tw, tid, sumsq ? &ss : nullptr);
+        if (sumsq) block_sum_f64<NT>(ss, sumsq, (double *)(sm + O_RED));
+        c32 *out = (c32 *)a.out;
+        constexpr int NI = RB * HALF;
 #pragma unroll
-    for (int i = 0; i < (NI + NT - 1) / NT; ++i) {
-        const int idx = tid + i * NT;
-        if (idx < NI) {
-            const int l = idx / HALF;
-            const int k = idx - l * HALF;
-            if (l < nv) {
-                const c32 *line = buf + l * LP;
-                const c32 z = line[k];
-                const c32 zc = conjg(line[k == 0 ? 0 : M - k]);
-                const c32 fe = scl(add(z, zc), 0.5f);
-                const c32 d = sub(z, zc);
-                const c32 fo = c32{0.5f * d.y, -0.5f * d.x};
-                const c32 wf = mul(twp[k], fo);
-                c32 *orow = out + ob[l];
-                orow[k] = add(fe, wf);
-                if (2 * k != M) orow[M - k] = conjg(sub(fe, wf));
+        for (int i = 0; i < (NI + NT - 1) / NT; ++i) {
+            const int idx = tid + i * NT;
+            if (idx < NI) {
+                const int l = idx / HALF;
+                const int k = idx - l * HALF;
+                if (l < nv) {
+                    const c32 *line = buf + l * LP;
+                    const c32 z = line[k];
+                    const c32 zc = conjg(line[k == 0 ? 0 : M - k]);
+                    const c32 fe = scl(add(z, zc), 0.5f);
+                    const c32 d = sub(z, zc);
+                    const c32 fo = c32{0.5f * d.y, -0.5f * d.x};
+                    const c32 wf = mul(twp[k], fo);
+                    c32 *orow = out + ob[l];
+                    orow[k] = add(fe, wf);
+                    if (2 * k != M) orow[M - k] = conjg(sub(fe, wf));
+                }
             }
         }
+        __syncthreads();
     }
-}
+};
 
+// ---- one-component fast c2r.
 // Z[k] = (X[k] + conj X[M-k]) + i W^{-k} (X[k] - conj X[M-k]); every thread
 // owns the pair (k, M-k), so the update is in place without a barrier.
-template <int M>
-__global__ __launch_bounds__(kXThreads) void k_x_c2r_v(XArgs a)
-{
-    constexpr int NT = kXThreads;
-    constexpr int RB = x_rb(M, 1);
-    constexpr int LP = M + 1;
-    constexpr int NH = M + 1;
-    constexpr int HALF = M / 2 + 1;
-    __shared__ c32 buf[RB * LP];
-    __shared__ c32 tw[M];
-    __shared__ c32 twp[NH];
-    __shared__ int64_t ib[RB], ob[RB];
-    const int tid = threadIdx.x;
-    const c32 *gtw = (const c32 *)a.tw;
-    const c32 *gtp = (const c32 *)a.tw_post;
-    for (int i = tid; i < M; i += NT) tw[i] = gtw[i];
-    for (int i = tid; i < NH; i += NT) twp[i] = gtp[i];
-    const int64_t r0 = (int64_t)blockIdx.x * RB;
-    row_bases<RB>(ib, ob, a, r0, tid);
-    __syncthreads();
-    for (int i = tid; i < RB; i += NT) ob[i] >>= 1;
-    const int nv = rows_valid<RB>(a, r0);
-    const c32 *in = (const c32 *)a.in;
-    // TPR threads per row, each walking one row: a single row offset per
-    // thread, loads of a wave contiguous within each row.
-    constexpr int TPR = NT / RB >= 1 ? NT / RB : 1;
-    constexpr int NK = (NH + TPR - 1) / TPR;
-    for (int l = tid / TPR; l < RB; l += NT / TPR) {
-        const int64_t base = ib[l];
-        const bool ok = l < nv;
-        const int k0 = tid % TPR;
-#pragma unroll
-        for (int i = 0; i < NK; ++i) {
-            const int k = k0 + i * TPR;
-            if (k < NH) buf[l * LP + k] = ok ? in[base + k] : c32{0.f, 0.f};
-        }
+template <int M, int NT>
+struct XC2RV {
+    static constexpr int RB = x_rb(M, 1, NT), LP = M + 1, NH = M + 1, HALF = M / 2 + 1;
+    static constexpr size_t O_BUF = 0, O_TW = al16(O_BUF + sizeof(c32) * RB * LP),
+                            O_TWP = al16(O_TW + sizeof(c32) * M),
+                            O_IB = al16(O_TWP + sizeof(c32) * NH), O_OB = O_IB + 8 * RB,
+                            BYTES = al16(O_OB + 8 * RB);
+    static __device__ void tables(const XArgs &a, char *sm, int tid)
+    {
+        load_table((c32 *)(sm + O_TW), a.tw, M, tid, NT);
+        load_table((c32 *)(sm + O_TWP), a.tw_post, NH, tid, NT);
     }
-    __syncthreads();
-    constexpr int NP = RB * HALF;
+    static __device__ void tile(const XArgs &a, int64_t blk, char *sm, int tid)
+    {
+        c32 *buf = (c32 *)(sm + O_BUF);
+        const c32 *tw = (const c32 *)(sm + O_TW), *twp = (const c32 *)(sm + O_TWP);
+        int64_t *ib = (int64_t *)(sm + O_IB), *ob = (int64_t *)(sm + O_OB);
+        const int64_t r0 = blk * RB;
+        row_bases<RB, NT>(ib, ob, a, r0, tid);
+        __syncthreads();
+        for (int i = tid; i < RB; i += NT) ob[i] >>= 1;
+        const int nv = rows_valid<RB>(a, r0);
+        const c32 *in = (const c32 *)a.in;
+        // TPR threads per row, each walking one row: a single row offset per
+        // thread, loads of a wave contiguous within each row.
+        constexpr int TPR = NT / RB >= 1 ? NT / RB : 1;
+        constexpr int NK = (NH + TPR - 1) / TPR;
+        for (int l = tid / TPR; l < RB; l += NT / TPR) {
+            const int64_t base = ib[l];
+            const bool ok = l < nv;
+            const int k0 = tid % TPR;
 #pragma unroll
-    for (int i = 0; i < (NP + NT - 1) / NT; ++i) {
-        const int idx = tid + i * NT;
-        if (idx < NP) {
-            const int l = idx / HALF;
-            const int k = idx - l * HALF;
-            c32 *line = buf + l * LP;
-            c32 xk = line[k], xm = line[M - k];
-            if (k == 0) {
-                xk.y = 0.f;
-                xm.y = 0.f;
+            for (int i = 0; i < NK; ++i) {
+                const int k = k0 + i * TPR;
+                if (k < NH) buf[l * LP + k] = ok ? in[base + k] : c32{0.f, 0.f};
             }
-            const c32 s1 = add(xk, conjg(xm));
-            const c32 d1 = mul(conjg(twp[k]), sub(xk, conjg(xm)));
-            const c32 zk = c32{s1.x - d1.y, s1.y + d1.x};
-            if (k != 0 && 2 * k != M) {
-                const c32 s2 = add(xm, conjg(xk));
-                const c32 d2 = mul(conjg(twp[M - k]), sub(xm, conjg(xk)));
-                line[M - k] = c32{s2.x - d2.y, s2.y + d2.x};
-            }
-            line[k] = zk;
         }
+        __syncthreads();
+        constexpr int NP = RB * HALF;
+#pragma unroll
+        for (int i = 0; i < (NP + NT - 1) / NT; ++i) {
+            const int idx = tid + i * NT;
+            if (idx < NP) {
+                const int l = idx / HALF;
+                const int k = idx - l * HALF;
+                c32 *line = buf + l * LP;
+                c32 xk = line[k], xm = line[M - k];
+                if (k == 0) {
+                    xk.y = 0.f;
+                    xm.y = 0.f;
+                }
+                const c32 s1 = add(xk, conjg(xm));
+                const c32 d1 = mul(conjg(twp[k]), sub(xk, conjg(xm)));
+                const c32 zk = c32{s1.x - d1.y, s1.y + d1.x};
+                if (k != 0 && 2 * k != M) {
+                    const c32 s2 = add(xm, conjg(xk));
+                    const c32 d2 = mul(conjg(twp[M - k]), sub(xm, conjg(xk)));
+                    line[M - k] = c32{s2.x - d2.y, s2.y + d2.x};
+                }
+                line[k] = zk;
+            }
+        }
+        __syncthreads();
+        row_fft<M, +1, RB, 1, LP, NT, false, true>(buf, nullptr, (c32 *)a.out, nullptr, ob, nv, tw,
+                                                   tid);
+        __syncthreads();
     }
-    __syncthreads();
-    row_fft<M, +1, RB, 1, LP, NT, false, true>(buf, nullptr, (c32 *)a.out, nullptr, ob, nv, tw, tid);
-}
+};
 
-template <int L, int NC, int S>
-__global__ __launch_bounds__(kXThreads) void k_x_c2c_v(XArgs a)
-{
-    constexpr int NT = kXThreads;
-    constexpr int RB = x_rb(L, NC);
-    __shared__ c32 buf[RB * NC * L];
-    __shared__ c32 tw[L];
-    __shared__ int64_t ib[RB], ob[RB];
-    const int tid = threadIdx.x;
-    const c32 *gtw = (const c32 *)a.tw;
-    for (int i = tid; i < L; i += NT) tw[i] = gtw[i];
-    const int64_t r0 = (int64_t)blockIdx.x * RB;
-    row_bases<RB>(ib, ob, a, r0, tid);
-    __syncthreads();
-    const int nv = rows_valid<RB>(a, r0);
-    row_fft<L, S, RB, NC, L, NT, true, true>(buf, (const c32 *)a.in, (c32 *)a.out, ib, ob, nv, tw,
-                                             tid);
-}
+// ---- c2c with NC interleaved components, register-direct both ends
+template <int L, int NC, int S, int NT>
+struct XC2CV {
+    static constexpr int RB = x_rb(L, NC, NT);
+    static constexpr size_t O_BUF = 0, O_TW = al16(O_BUF + sizeof(c32) * RB * NC * L),
+                            O_IB = al16(O_TW + sizeof(c32) * L), O_OB = O_IB + 8 * RB,
+                            BYTES = al16(O_OB + 8 * RB);
+    static __device__ void tables(const XArgs &a, char *sm, int tid)
+    {
+        load_table((c32 *)(sm + O_TW), a.tw, L, tid, NT);
+    }
+    static __device__ void tile(const XArgs &a, int64_t blk, char *sm, int tid)
+    {
+        c32 *buf = (c32 *)(sm + O_BUF);
+        const c32 *tw = (const c32 *)(sm + O_TW);
+        int64_t *ib = (int64_t *)(sm + O_IB), *ob = (int64_t *)(sm + O_OB);
+        const int64_t r0 = blk * RB;
+        row_bases<RB, NT>(ib, ob, a, r0, tid);
+        __syncthreads();
+        const int nv = rows_valid<RB>(a, r0);
+        row_fft<L, S, RB, NC, L, NT, true, true>(buf, (const c32 *)a.in, (c32 *)a.out, ib, ob, nv,
+                                                 tw, tid);
+        __syncthreads();
+    }
+};
 
-// ------------------------------------------------------------------ binning
+// ================================================================ binning
 // Exact bin of integer squared radius q: max{b <= nbins-1 : thresh[b] <= q},
 // thresh[b] = ceil(b^2 qmax / nbins^2).  The FP64 estimate is corrected by
 // integer comparisons, so the result never depends on rounding.
@@ -437,53 +418,29 @@ __device__ __forceinline__ int bin_of(int64_t q, const int64_t *thresh, int nbin
     return b;
 }
 
-// ------------------------------------------------------------------ strided pass
+// ============================================================ strided tiles
 // EPI = false: plain pass (no epilogue code, fewest registers);
 // EPI = true : last-axis pass with the binning / Poisson epilogue.
-template <int L, int S, bool EPI>
-__global__ __launch_bounds__(kSThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_strided(SArgs a)
-{
-    constexpr int NT = kSThreads;
-    constexpr int B = s_b(L);
-    constexpr int RPT = NT / B;                 // row groups in the epilogue
-    __shared__ c32 buf[L * B];
-    __shared__ c32 tw[L];
-    extern __shared__ double dyn[];              // hist[nbins + 1], thresh[nbins + 1]
-    const int tid = threadIdx.x;
-    const int col = tid % B;
-    const int rg = tid / B;
-    const c32 *gtw = (const c32 *)a.tw;
-    for (int i = tid; i < L; i += NT) tw[i] = gtw[i];
-    const bool pk = (a.epi & (EPI_PK | EPI_PK_AFTER)) != 0;
-    const bool store = (a.epi & EPI_STORE) != 0;
-    const int nb = a.mt.nbins;
-    double *hist = dyn;
-    int64_t *thresh = (int64_t *)(dyn + (nb + 1));
-    if (EPI && pk) {
-        for (int i = tid; i <= nb; i += NT) {
-            hist[i] = 0.0;
-            thresh[i] = a.mt.thresh[i];
-        }
+// hist / thresh: LDS arrays of nbins + 1 entries (EPI with binning only);
+// the tile adds its w|F|^2 sums into hist.
+template <int L, int S, bool EPI, int NT>
+struct STile {
+    static constexpr int B = s_b(L);
+    static constexpr int RPT = NT / B;  // row groups in the epilogue
+    static constexpr size_t O_BUF = 0, O_TW = al16(sizeof(c32) * L * B),
+                            BYTES = al16(O_TW + sizeof(c32) * L);
+    static __device__ void tables(const SArgs &a, char *sm, int tid)
+    {
+        load_table((c32 *)(sm + O_TW), a.tw, L, tid, NT);
     }
-    __syncthreads();
-
-    const c32 *in = (const c32 *)a.in;
-    c32 *out = (c32 *)a.out;
-    const int64_t ntiles = (a.ncols + B - 1) / B;
-    // XCD-aware walk over virtual block ids vb = blockIdx.x + i * G (G is a
-    // multiple of 8).  The chip hands block ids to its 8 XCDs in turn, so
-    // vb mod 8 is this block's XCD.  Chunks of K consecutive tiles go to one
-    // XCD and the chunks rotate over the XCDs: neighbouring tiles, which
-    // share cache lines when rows are not 128-byte aligned, meet in one L2,
-    // while all XCDs stream from nearby addresses.
-    const int64_t K = a.xcd_chunk;
-    const int64_t span = (ntiles + 8 * K - 1) / (8 * K) * (8 * K);
-    const double inv_qmax = 1.0 / a.mt.qmax;
-
-    for (int64_t vb = blockIdx.x; vb < span; vb += gridDim.x) {
-        const int64_t lb = vb / 8;
-        const int64_t t = ((lb / K) * 8 + (vb % 8)) * K + lb % K;
-        if (t >= ntiles) continue;  // uniform over the block
+    static __device__ void tile(const SArgs &a, int64_t t, char *sm, int tid, double *hist,
+                                const int64_t *thresh)
+    {
+        c32 *buf = (c32 *)(sm + O_BUF);
+        const c32 *tw = (const c32 *)(sm + O_TW);
+        const int col = tid % B;
+        const int rg = tid / B;
+        const bool store = (a.epi & EPI_STORE) != 0;
         const int64_t f = t * B + col;
         const bool valid = f < a.ncols;
         int64_t base = 0;
@@ -491,12 +448,15 @@ __global__ __launch_bounds__(kSThreads) __attribute__((amdgpu_waves_per_eu(4))) 
             const int64_t o = f / a.ncols_inner;
             base = o * a.outer + (f - o * a.ncols_inner);
         }
-        const c32 *gin = in + base;
-        c32 *gout = out + base;
+        const c32 *gin = (const c32 *)a.in + base;
+        c32 *gout = (c32 *)a.out + base;
         if constexpr (!EPI) {
             // global -> registers -> stages -> registers -> global
             col_fft<L, S, B, NT, true, true>(buf, gin, gout, a.stride, valid && store, tw, tid);
         } else {
+            const bool pk = (a.epi & (EPI_PK | EPI_PK_AFTER)) != 0;
+            const int nb = a.mt.nbins;
+            const double inv_qmax = 1.0 / a.mt.qmax;
             col_fft<L, S, B, NT, true, false>(buf, gin, nullptr, a.stride, valid, tw, tid);
             // Epilogue on the last axis: thread (col, rg) walks a contiguous run
             // of kz so that consecutive modes mostly share a bin.
@@ -546,18 +506,106 @@ __global__ __launch_bounds__(kSThreads) __attribute__((amdgpu_waves_per_eu(4))) 
             bool stored = false;
             if constexpr (S < 0) {
                 if (a.epi & EPI_POISSON) {
-                    col_fft<L, +1, B, NT, false, true>(buf, nullptr, gout, a.stride, valid && store,
-                                                       tw, tid);
+                    col_fft<L, +1, B, NT, false, true>(buf, nullptr, gout, a.stride,
+                                                       valid && store, tw, tid);
                     stored = true;
                 }
             }
             if (store && !stored && valid) {
-                for (int row = rg; row < L; row += RPT) gout[(int64_t)row * a.stride] = buf[row * B + col];
+                for (int row = rg; row < L; row += RPT)
+                    gout[(int64_t)row * a.stride] = buf[row * B + col];
             }
         }
         __syncthreads();
     }
-    if (EPI && pk) {
+};
+
+// ======================================================= standalone kernels
+// One x tile per block (tile index = blockIdx.x).
+
+template <int M, int NC>
+__global__ __launch_bounds__(kXThreads) void k_x_r2c(XArgs a)
+{
+    using T = XR2CGen<M, NC, kXThreads>;
+    __shared__ __align__(16) char sm[T::BYTES];
+    T::tables(a, sm, threadIdx.x);
+    T::tile(a, blockIdx.x, sm, threadIdx.x, a.sumsq ? a.sumsq + blockIdx.x : nullptr);
+}
+
+template <int M, int NC>
+__global__ __launch_bounds__(kXThreads) void k_x_c2r(XArgs a)
+{
+    using T = XC2RGen<M, NC, kXThreads>;
+    __shared__ __align__(16) char sm[T::BYTES];
+    T::tables(a, sm, threadIdx.x);
+    T::tile(a, blockIdx.x, sm, threadIdx.x);
+}
+
+template <int M>
+__global__ __launch_bounds__(kXThreads) void k_x_r2c_v(XArgs a)
+{
+    using T = XR2CV<M, kXThreads>;
+    __shared__ __align__(16) char sm[T::BYTES];
+    T::tables(a, sm, threadIdx.x);
+    T::tile(a, blockIdx.x, sm, threadIdx.x, a.sumsq ? a.sumsq + blockIdx.x : nullptr);
+}
+
+template <int M>
+__global__ __launch_bounds__(kXThreads) void k_x_c2r_v(XArgs a)
+{
+    using T = XC2RV<M, kXThreads>;
+    __shared__ __align__(16) char sm[T::BYTES];
+    T::tables(a, sm, threadIdx.x);
+    T::tile(a, blockIdx.x, sm, threadIdx.x);
+}
+
+template <int L, int NC, int S>
+__global__ __launch_bounds__(kXThreads) void k_x_c2c_v(XArgs a)
+{
+    using T = XC2CV<L, NC, S, kXThreads>;
+    __shared__ __align__(16) char sm[T::BYTES];
+    T::tables(a, sm, threadIdx.x);
+    T::tile(a, blockIdx.x, sm, threadIdx.x);
+}
+
+// Strided pass: persistent-style walk over tiles.
+template <int L, int S, bool EPI>
+__global__ __launch_bounds__(kSThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_strided(SArgs a)
+{
+    using T = STile<L, S, EPI, kSThreads>;
+    constexpr int NT = kSThreads;
+    constexpr int B = T::B;
+    __shared__ __align__(16) char sm[T::BYTES];
+    extern __shared__ double dyn[];  // hist[nbins + 1], thresh[nbins + 1]
+    const int tid = threadIdx.x;
+    T::tables(a, sm, tid);
+    const bool pk = EPI && (a.epi & (EPI_PK | EPI_PK_AFTER)) != 0;
+    const int nb = a.mt.nbins;
+    double *hist = dyn;
+    int64_t *thresh = (int64_t *)(dyn + (nb + 1));
+    if (pk) {
+        for (int i = tid; i <= nb; i += NT) {
+            hist[i] = 0.0;
+            thresh[i] = a.mt.thresh[i];
+        }
+    }
+    __syncthreads();
+    const int64_t ntiles = (a.ncols + B - 1) / B;
+    // XCD-aware walk over virtual block ids vb = blockIdx.x + i * G (G is a
+    // multiple of 8).  The chip hands block ids to its 8 XCDs in turn, so
+    // vb mod 8 is this block's XCD.  Chunks of K consecutive tiles go to one
+    // XCD and the chunks rotate over the XCDs: neighbouring tiles, which
+    // share cache lines when rows are not 128-byte aligned, meet in one L2,
+    // while all XCDs stream from nearby addresses.
+    const int64_t K = a.xcd_chunk;
+    const int64_t span = (ntiles + 8 * K - 1) / (8 * K) * (8 * K);
+    for (int64_t vb = blockIdx.x; vb < span; vb += gridDim.x) {
+        const int64_t lb = vb / 8;
+        const int64_t t = ((lb / K) * 8 + (vb % 8)) * K + lb % K;
+        if (t >= ntiles) continue;  // uniform over the block
+        T::tile(a, t, sm, tid, hist, thresh);
+    }
+    if (pk) {
         __syncthreads();
         for (int i = tid; i <= nb; i += NT) a.partial[(int64_t)blockIdx.x * (nb + 1) + i] = hist[i];
     }

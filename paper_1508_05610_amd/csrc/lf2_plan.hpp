@@ -1,0 +1,85 @@
+// lf2_plan.hpp -- host-side plan object and helpers shared by the C ABI
+// sources (lf2_api.cpp: transforms; lf2_batch.cpp: batched launches).
+#pragma once
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/lf2.h"
+#include "lf2_internal.hpp"
+
+struct K2Entry {
+    double dx;
+    int discrete;
+    double *tab[3];
+};
+
+struct ShellEntry {
+    int nbins;
+    int64_t *thresh;  // nbins + 1
+    double *count;    // nbins
+    double *sumk;     // nbins (sum w sqrt(q))
+};
+
+struct lf2_plan_s {
+    int device = 0;
+    lf2_fft_kind kind = LF2_R2C;
+    int nc = 1;
+    int halo = 0;
+    uint32_t flags = 0;
+    int64_t n[3] = {0, 0, 0};
+    int64_t nh = 0;    // N0/2 + 1
+    int64_t nxk = 0;   // k-space extent of dimension 0
+    int64_t ntot = 0;  // N0 N1 N2
+    int len[3] = {0, 0, 0};
+    void *tw[3] = {nullptr, nullptr, nullptr};
+    void *tw_post = nullptr;
+    int64_t *q[3] = {nullptr, nullptr, nullptr};
+    int64_t lcm = 1, qmax = 0;
+    std::vector<K2Entry> k2;
+    std::vector<ShellEntry> shells;
+    void *own_ws = nullptr;
+    size_t own_ws_bytes = 0;
+    std::vector<void *> allocs;
+};
+
+namespace lf2 {
+namespace host {
+
+constexpr int kPkGrid = 1024;  // blocks of a binning pass (partials rows)
+constexpr int kStridedGridCap = 1 << 30;
+
+lf2_status fail(lf2_status st, const char *fmt, ...);
+
+#define LF2_HIP(call)                                                                       \
+    do {                                                                                    \
+        hipError_t e_ = (call);                                                             \
+        if (e_ != hipSuccess) {                                                             \
+            return ::lf2::host::fail(                                                       \
+                e_ == hipErrorOutOfMemory ? LF2_ERR_OUT_OF_MEMORY : LF2_ERR_DEVICE,         \
+                "%s failed: %s", #call, hipGetErrorString(e_));                             \
+        }                                                                                   \
+    } while (0)
+
+size_t align256(size_t b);
+std::string kname(const char *fmt, ...);
+namespace prof {
+int begin(const std::string &name, double bytes, hipStream_t s);
+void end(int idx, hipStream_t s);
+}  // namespace prof
+
+lf2_status plan_alloc(lf2_plan p, void **dst, size_t bytes);
+size_t spectrum_bytes(const lf2_plan_s *p);
+ModeTables base_tables(const lf2_plan_s *p);
+lf2_status get_k2(lf2_plan p, double dx, int discrete, hipStream_t s, const double *out[3]);
+lf2_status get_shell(lf2_plan p, int nbins, hipStream_t s, ShellEntry *out);
+lf2_status check_device(const lf2_plan_s *p);
+lf2_status check_ptr(const void *ptr, const char *what, size_t align);
+XArgs x_args(const lf2_plan_s *p, const void *in, void *out, bool in_is_x, bool out_is_x,
+             bool real_x);
+SArgs s_args(const lf2_plan_s *p, int axis, const void *in, void *out, int epi);
+lf2_status check_bins(const lf2_plan_s *p, int32_t nbins);
+
+}  // namespace host
+}  // namespace lf2
