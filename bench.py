@@ -60,7 +60,8 @@ def measured_traffic(kernel: str):
 def bench_batch(args, torch, np, lf2, stream):
     """48 Poisson solves with fused 32-bin P(k) on uneven lattices (extents per
     axis from {64, 96, 128, 160, 192, 256}, field 0 = 128x192x256): one
-    persistent launch in a hipGraph against 48 plain lf2_poisson_solve calls.
+    set of grouped launches replayed from a hipGraph against 48 plain
+    lf2_poisson_solve calls.
     Inputs are seeded N(0,1) fields (run time does not depend on values; the
     random-field parity of the same workload is in the tests)."""
     import synth
@@ -124,6 +125,167 @@ def bench_batch(args, torch, np, lf2, stream):
     }
 
 
+def bench_serving(args, torch, np, lf2):
+    """Request serving: Poisson + 64-bin P(k) solves on cubic lattices with
+    N uniform over {32, 64, 128, 256, 384}, Poisson arrivals at 200 req/s
+    (seed 6), 8 GiB HBM admission budget, plans resident.  Latency is
+    t_done - t_arrival.  Compared with a plain loop that launches each
+    request with lf2_poisson_solve on one stream and waits for it, on the
+    same arrival schedule; then both at saturation (every request arriving at
+    once)."""
+    import collections
+
+    import synth
+    from paper_1508_05610_amd import _lib
+    NS = [32, 64, 128, 256, 384]
+    nb = 64
+    rate = 200.0
+    nreq = args.serve_requests
+    dev = torch.device("cuda:0")
+    draws = synth.choice(6, nreq, len(NS))
+    req_n = [NS[int(d)] for d in draws]
+    u = synth.uniform(6, nreq, stream=1)
+    gaps = -np.log1p(-u) / rate
+    pool = 20  # buffer sets per lattice size (caller-owned request memory)
+    bufs = {}
+    for j, n in enumerate(NS):
+        f = torch.from_numpy(synth.normal(6, n ** 3, stream=10 + j, dtype=np.float32)
+                             .reshape(n, n, n)).to(dev)
+        rho = [f.clone() for _ in range(pool)]
+        phi = [torch.empty_like(f) for _ in range(pool)]
+        pks = [torch.empty((3, nb), dtype=torch.float64, device=dev) for _ in range(pool)]
+        bufs[n] = (rho, phi, pks)
+    torch.cuda.synchronize()
+    plans = {n: lf2.Plan((n, n, n), lf2.LF2_R2C) for n in NS}
+    budget = 8 << 30
+    srv = lf2.Server(budget, max_slots=16, nstreams=4, max_queue=1 << 16)
+    srv.prepare([(n, n, n) for n in NS], nbins=nb)
+    now = _lib.lf2_server_now
+
+    def args_of(n, k):
+        rho, phi, pks = bufs[n]
+        p = pks[k]
+        return (rho[k].data_ptr(), phi[k].data_ptr(), p[0].data_ptr(), p[1].data_ptr(),
+                p[2].data_ptr())
+
+    def served(arrivals):
+        free = {n: list(range(pool)) for n in NS}
+        out = collections.OrderedDict()   # ticket -> (n, slot)
+        lat, last = [], {}
+        t_first = now()
+
+        def reap(block):
+            done = []
+            for t, (n, k) in out.items():
+                r = srv.poll(t, wait=block)
+                if r is None:
+                    if block:
+                        raise RuntimeError("blocking poll returned no result")
+                    continue
+                if r[0] != lf2.LF2_OK:
+                    raise RuntimeError(f"request {t} failed: {_lib.status_string(r[0])}")
+                lat.append(r[3] - r[1])
+                free[n].append(k)
+                done.append(t)
+                if block:
+                    break
+            for t in done:
+                del out[t]
+
+        for i, n in enumerate(req_n):
+            ta = arrivals[i]
+            while now() < ta:
+                reap(False)
+                if ta - now() > 5e-4:
+                    time.sleep(2e-4)
+            while not free[n]:
+                reap(True)
+            k = free[n].pop()
+            rp, pp, a, b, c = args_of(n, k)
+            while True:
+                st, t = srv.submit_raw((n, n, n), rp, pp, 1.0, 0, nb, a, b, c, t_arrival=ta)
+                if st == lf2.LF2_OK:
+                    break
+                if st != lf2.LF2_ERR_BUSY:
+                    raise RuntimeError(f"submit: {_lib.status_string(st)}")
+                reap(True)
+            out[t] = (n, k)
+            last[n] = k
+        while out:
+            reap(True)
+        return lat, now() - t_first, last
+
+    stream = torch.cuda.current_stream()
+    sh = int(stream.cuda_stream)
+
+    def plain(arrivals, sync_each=True):
+        lat = []
+        slot = {n: 0 for n in NS}
+        t_first = now()
+        for i, n in enumerate(req_n):
+            ta = arrivals[i]
+            while now() < ta:
+                if ta - now() > 5e-4:
+                    time.sleep(2e-4)
+            k = slot[n]
+            slot[n] = (k + 1) % pool
+            rp, pp, a, b, c = args_of(n, k)
+            _lib.lf2_poisson_solve(plans[n].handle, rp, pp, 1.0, 0, nb, a, b, c, 0, sh)
+            if sync_each:
+                stream.synchronize()
+                lat.append(now() - ta)
+        stream.synchronize()
+        return lat, now() - t_first
+
+    # warm every path once
+    served([0.0] * nreq)
+    plain([0.0] * nreq)
+    torch.cuda.synchronize()
+
+    t0 = now() + 0.05
+    arr = list(t0 + np.cumsum(gaps))
+    lat_s, wall_s, _ = served(arr)
+    t0 = now() + 0.05
+    arr = list(t0 + np.cumsum(gaps))
+    lat_p, wall_p = plain(arr)
+    sat = [0.0] * nreq
+    _, sat_s, last = served(sat)
+    stats = srv.stats()
+    # served results against solo solves of the same inputs
+    worst = 0.0
+    for n, k in last.items():
+        rho, phi, pks = bufs[n]
+        solo, spk, _, _ = plans[n].poisson(rho[k], nbins=nb)
+        torch.cuda.synchronize()
+        worst = max(worst, float(torch.linalg.vector_norm((phi[k] - solo).double())
+                                 / torch.linalg.vector_norm(solo.double())),
+                    float(torch.linalg.vector_norm(pks[k][0] - spk) / torch.linalg.vector_norm(spk)))
+    _, sat_p = plain(sat)
+    _, sat_q = plain(sat, sync_each=False)
+    srv.close()
+    p50s, p99s = lf2.latency_percentiles(lat_s)
+    p50p, p99p = lf2.latency_percentiles(lat_p)
+    mean_pts = float(np.mean([n ** 3 for n in req_n]))
+    return {
+        "workload": f"{nreq} Poisson + {nb}-bin P(k) requests, cubic N uniform over "
+                    f"{{32,64,128,256,384}} (seed 6), Poisson arrivals {rate:.0f}/s, "
+                    f"budget 8 GiB, 16 slots, 4 streams",
+        "p50_ms": round(1e3 * p50s, 4), "p99_ms": round(1e3 * p99s, 4),
+        "throughput_req_s": round(nreq / wall_s, 1),
+        "saturation_req_s": round(nreq / sat_s, 1),
+        "saturation_mpoints_s": round(nreq * mean_pts / sat_s / 1e6, 1),
+        "plain_p50_ms": round(1e3 * p50p, 4), "plain_p99_ms": round(1e3 * p99p, 4),
+        "plain_throughput_req_s": round(nreq / wall_p, 1),
+        "plain_saturation_req_s": round(nreq / sat_p, 1),
+        "plain_enqueue_only_saturation_req_s": round(nreq / sat_q, 1),
+        "saturation_speedup_vs_plain": round(sat_p / sat_s, 3),
+        "saturation_speedup_vs_plain_enqueue_only": round(sat_q / sat_s, 3),
+        "served_vs_solo_rel_l2_max": worst,
+        "peak_bytes_in_flight": stats["peak_bytes_in_flight"],
+        "plan_misses": stats["plan_misses"],
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -134,6 +296,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-errors", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=1000)
     ap.add_argument("--only", default=None,
                     help="time one op alone (r2c_fwd, c2r_bwd, c2c_fwd_3comp, c2c_bwd_3comp, "
                          "poisson_pk, copy) for profiler runs")
@@ -324,6 +488,8 @@ def main():
 
     if not args.no_batch:
         res["batch"] = bench_batch(args, torch, np, lf2, stream)
+    if not args.no_serve:
+        res["serving"] = bench_serving(args, torch, np, lf2)
 
     # ---- CPU baseline: the FP64 oracle on the host cores, bounded sample
     errors = {}

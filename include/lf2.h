@@ -215,6 +215,93 @@ lf2_status lf2_batch_info(lf2_batch b, int64_t *nitems, int32_t *launches,
 lf2_status lf2_batch_destroy(lf2_batch b);
 
 /*
+ * Serving: a request loop for Poisson solves with optional power spectra on
+ * lattices of mixed sizes (continuous batching).  A scheduler thread admits
+ * queued requests in arrival order while their footprint (rho + phi +
+ * spectrum workspace + bin partials) fits the HBM budget and a slot is
+ * free, and launches each admitted request at once on one of `nstreams`
+ * streams, so requests that arrive while others run join the device work
+ * as capacity frees up.  Plans (twiddles, wavevector and shell tables) stay
+ * resident in a cache keyed by lattice; workspaces are pooled.  A
+ * completion thread timestamps each request when its work has finished and
+ * returns its capacity.  Requests are independent: each gives the same
+ * result as lf2_poisson_solve on its own.
+ *
+ * The caller owns rho, phi and the bin arrays of a request and keeps them
+ * valid until lf2_server_poll reports it done.  The server's streams do not
+ * wait for other streams: rho must hold its values on the device when the
+ * request is submitted.  Up to 32 plans stay resident; a new lattice evicts
+ * the least recently used plan that no running request holds.  Timestamps
+ * are seconds on the host's monotonic clock (lf2_server_now).
+ */
+typedef struct lf2_server_s *lf2_server;
+
+typedef struct {
+    lf2_lattice lat;      /* dense (halo 0) lattice, r2c-compatible (even N0) */
+    const float *rho;     /* device, float[N2][N1][N0] */
+    float *phi;           /* device, float[N2][N1][N0], must not alias rho */
+    double dx;            /* lattice spacing > 0 */
+    uint32_t flags;       /* LF2_POISSON_DISCRETE_K2 | LF2_PK_OF_PHI */
+    int32_t nbins;        /* 0: no power spectrum */
+    double *d_pk, *d_kmean, *d_count;  /* device arrays of nbins doubles (nullable) */
+    double t_arrival;     /* arrival time for latency accounting; 0: submit time */
+} lf2_request;
+
+typedef struct {
+    lf2_status status;    /* LF2_OK, or the request's failure */
+    double t_arrival, t_admit, t_done;  /* seconds, monotonic host clock */
+} lf2_result;
+
+typedef struct {
+    int64_t submitted, completed, failed, rejected_busy, rejected_budget;
+    int64_t in_flight, queued;
+    size_t bytes_in_flight, peak_bytes_in_flight;
+    int64_t plans_cached, plan_hits, plan_misses;
+} lf2_server_stats;
+
+/* Create a GPU server on the current device.  hbm_budget_bytes bounds the
+ * summed footprint of admitted requests; max_slots bounds requests in
+ * flight; nstreams (>= 1) streams of default priority; max_queue bounds
+ * requests waiting for admission. */
+lf2_status lf2_server_create(lf2_server *out, size_t hbm_budget_bytes, int32_t max_slots,
+                             int32_t nstreams, int32_t max_queue);
+
+/* A server whose executor launches nothing: each request completes
+ * delay_us microseconds after admission, the request with ticket
+ * fail_ticket (0: none) completes with LF2_ERR_DEVICE.  Admission, budget,
+ * queue and failure handling are those of the GPU server; for host-side
+ * tests without a GPU.  Bin arrays are not written. */
+lf2_status lf2_server_create_fake(lf2_server *out, size_t hbm_budget_bytes, int32_t max_slots,
+                                  int32_t max_queue, uint32_t delay_us, uint64_t fail_ticket);
+
+/* Make plans resident for these lattices (and bin counts / spacing), so the
+ * first request of each does not pay plan setup.  Synchronises the device. */
+lf2_status lf2_server_prepare(lf2_server s, int32_t n, const lf2_lattice *lats, int32_t nbins,
+                              double dx, uint32_t flags);
+
+/* Queue a request without blocking.  *ticket (>= 1) identifies it.
+ * LF2_ERR_BUDGET: its footprint alone exceeds the budget;
+ * LF2_ERR_BUSY: the queue is full (retry later);
+ * LF2_ERR_INVALID_ARG / LF2_ERR_UNSUPPORTED: bad request. */
+lf2_status lf2_server_submit(lf2_server s, const lf2_request *r, uint64_t *ticket);
+
+/* Result of a ticket.  wait = 0: LF2_ERR_NOT_READY while it runs; wait != 0:
+ * block until done.  A finished ticket is reported once and then forgotten
+ * (LF2_ERR_INVALID_ARG afterwards). */
+lf2_status lf2_server_poll(lf2_server s, uint64_t ticket, lf2_result *res, int32_t wait);
+
+/* Footprint in bytes that admission charges for a request. */
+lf2_status lf2_server_footprint(const lf2_request *r, size_t *bytes);
+
+lf2_status lf2_server_get_stats(lf2_server s, lf2_server_stats *st);
+
+/* Drain: wait for every queued and running request, then free the server. */
+lf2_status lf2_server_destroy(lf2_server s);
+
+/* Monotonic host clock in seconds (the server's timestamps). */
+double lf2_server_now(void);
+
+/*
  * Kernel timing (tracing).  While enabled, every kernel launch made by the
  * calls above is bracketed by two HIP events recorded on the launch's
  * stream and tagged with the kernel's name and its algorithmic HBM bytes

@@ -20,13 +20,16 @@ from ._lib import (LF2_BACKWARD, LF2_BATCH_PK, LF2_BATCH_POISSON, LF2_C2C, LF2_F
                    lf2_fft_execute, lf2_fft_kspace, lf2_fft_plan, lf2_plan_destroy,
                    lf2_plan_set_workspace, lf2_plan_workspace_bytes, lf2_poisson_solve,
                    lf2_power_spectrum, lf2_version)
+from ._lib import (LF2_ERR_BUDGET, LF2_ERR_BUSY, LF2_ERR_DEVICE, LF2_ERR_INVALID_ARG,  # noqa: F401
+                   LF2_ERR_NOT_READY, LF2_ERR_UNSUPPORTED, LF2_OK)
 
 __all__ = ["Plan", "Batch", "LF2Error", "LF2_R2C", "LF2_C2C", "LF2_FORWARD", "LF2_BACKWARD",
            "LF2_POISSON_DISCRETE_K2", "LF2_PK_OF_PHI", "LF2_BATCH_POISSON", "LF2_BATCH_PK",
            "lf2_fft_plan", "lf2_fft_execute", "lf2_fft_kspace", "lf2_poisson_solve",
            "lf2_power_spectrum", "lf2_plan_destroy", "lf2_plan_workspace_bytes",
            "lf2_plan_set_workspace", "lf2_batch_plan", "lf2_batch_execute", "lf2_batch_error",
-           "lf2_batch_info", "lf2_batch_destroy", "lf2_version", "load"]
+           "lf2_batch_info", "lf2_batch_destroy", "lf2_version", "load", "Server",
+           "latency_percentiles"]
 
 
 def load():
@@ -203,3 +206,84 @@ class Batch:
 
     def error(self) -> int:
         return lf2_batch_error(self.handle)
+
+
+class Server:
+    """Continuous-batching request loop for Poisson solves with power spectra
+    (lf2_server_* in include/lf2.h).  Tensors of a request are held until its
+    result has been polled.  Inputs must be ready on the device when submitted:
+    the server's streams do not wait for torch's stream."""
+
+    def __init__(self, budget_bytes, max_slots=16, nstreams=4, max_queue=4096, fake=False,
+                 delay_us=0, fail_ticket=0):
+        if fake:
+            self.handle = _lib.lf2_server_create_fake(budget_bytes, max_slots, max_queue,
+                                                      delay_us, fail_ticket)
+        else:
+            self.handle = _lib.lf2_server_create(budget_bytes, max_slots, nstreams, max_queue)
+        self._held = {}
+
+    def prepare(self, sizes_list, nbins=0, dx=1.0, flags=0):
+        _lib.lf2_server_prepare(self.handle, [tuple(s) for s in sizes_list], nbins, dx, flags)
+
+    def submit_raw(self, sizes, rho_ptr, phi_ptr, dx=1.0, flags=0, nbins=0, pk_ptr=0,
+                   kmean_ptr=0, count_ptr=0, t_arrival=0.0, hold=None):
+        """(status, ticket); status LF2_ERR_BUSY / LF2_ERR_BUDGET are rejections."""
+        req = _lib.make_request(sizes, rho_ptr, phi_ptr, dx, flags, nbins, pk_ptr, kmean_ptr,
+                                count_ptr, t_arrival)
+        st, ticket = _lib.lf2_server_submit_status(self.handle, req)
+        if st == LF2_OK and hold is not None:
+            self._held[ticket] = hold
+        return st, ticket
+
+    def submit(self, rho, phi, dx=1.0, flags=0, nbins=0, pk=None, kmean=None, count=None,
+               t_arrival=0.0):
+        import torch
+        n2, n1, n0 = rho.shape
+        _ptr(rho, "rho", torch.float32, (n2, n1, n0))
+        _ptr(phi, "phi", torch.float32, (n2, n1, n0))
+        bins = []
+        for t, nm in ((pk, "pk"), (kmean, "kmean"), (count, "count")):
+            bins.append(0 if t is None else _ptr(t, nm, torch.float64, (nbins,)))
+        return self.submit_raw((n0, n1, n2), rho.data_ptr(), phi.data_ptr(), dx, flags, nbins,
+                               *bins, t_arrival=t_arrival, hold=(rho, phi, pk, kmean, count))
+
+    def poll(self, ticket, wait=True):
+        """None while running (wait=False), else (status, t_arrival, t_admit, t_done)."""
+        r = _lib.lf2_server_poll(self.handle, ticket, wait)
+        if r is not None:
+            self._held.pop(ticket, None)
+        return r
+
+    def footprint(self, sizes, nbins=0) -> int:
+        return _lib.lf2_server_footprint(_lib.make_request(sizes, 0, 0, 1.0, 0, nbins))
+
+    def stats(self) -> dict:
+        return _lib.lf2_server_get_stats(self.handle)
+
+    def close(self):
+        if self.handle:
+            _lib.lf2_server_destroy(self.handle)
+            self.handle = 0
+            self._held.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def latency_percentiles(values, qs=(50, 99)):
+    """Nearest-rank percentiles: the q-th is the ceil(q n / 100)-th smallest
+    value (1-based), so it is always one of the observed latencies."""
+    import math
+    v = sorted(float(x) for x in values)
+    if not v:
+        raise ValueError("no latencies")
+    out = []
+    for q in qs:
+        if not 0 < q <= 100:
+            raise ValueError("percentile must be in (0, 100]")
+        out.append(v[max(1, math.ceil(q * len(v) / 100.0)) - 1])
+    return tuple(out)

@@ -42,6 +42,27 @@ class LF2Error(RuntimeError):
         super().__init__(f"{func}: {status_string(status)} ({detail})")
 
 
+class lf2_request(ctypes.Structure):
+    _fields_ = [("lat", lf2_lattice), ("rho", ctypes.c_void_p), ("phi", ctypes.c_void_p),
+                ("dx", ctypes.c_double), ("flags", ctypes.c_uint32), ("nbins", ctypes.c_int32),
+                ("d_pk", ctypes.c_void_p), ("d_kmean", ctypes.c_void_p),
+                ("d_count", ctypes.c_void_p), ("t_arrival", ctypes.c_double)]
+
+
+class lf2_result(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("t_arrival", ctypes.c_double),
+                ("t_admit", ctypes.c_double), ("t_done", ctypes.c_double)]
+
+
+class lf2_server_stats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_int64), ("completed", ctypes.c_int64),
+                ("failed", ctypes.c_int64), ("rejected_busy", ctypes.c_int64),
+                ("rejected_budget", ctypes.c_int64), ("in_flight", ctypes.c_int64),
+                ("queued", ctypes.c_int64), ("bytes_in_flight", ctypes.c_size_t),
+                ("peak_bytes_in_flight", ctypes.c_size_t), ("plans_cached", ctypes.c_int64),
+                ("plan_hits", ctypes.c_int64), ("plan_misses", ctypes.c_int64)]
+
+
 _lib = None
 
 # C signatures: name -> (restype, argtypes)
@@ -64,6 +85,16 @@ _SIGS = {
     "lf2_batch_info": (_i32, [_vp, ctypes.POINTER(_i64), ctypes.POINTER(_i32),
                               ctypes.POINTER(ctypes.c_size_t)]),
     "lf2_batch_destroy": (_i32, [_vp]),
+    "lf2_server_create": (_i32, [ctypes.POINTER(_vp), ctypes.c_size_t, _i32, _i32, _i32]),
+    "lf2_server_create_fake": (_i32, [ctypes.POINTER(_vp), ctypes.c_size_t, _i32, _i32, _u32,
+                                      ctypes.c_uint64]),
+    "lf2_server_prepare": (_i32, [_vp, _i32, ctypes.POINTER(lf2_lattice), _i32, _f64, _u32]),
+    "lf2_server_submit": (_i32, [_vp, ctypes.POINTER(lf2_request), ctypes.POINTER(ctypes.c_uint64)]),
+    "lf2_server_poll": (_i32, [_vp, ctypes.c_uint64, ctypes.POINTER(lf2_result), _i32]),
+    "lf2_server_footprint": (_i32, [ctypes.POINTER(lf2_request), ctypes.POINTER(ctypes.c_size_t)]),
+    "lf2_server_get_stats": (_i32, [_vp, ctypes.POINTER(lf2_server_stats)]),
+    "lf2_server_destroy": (_i32, [_vp]),
+    "lf2_server_now": (_f64, []),
     "lf2_profile_enable": (_i32, [_i32]),
     "lf2_profile_reset": (_i32, []),
     "lf2_profile_count": (_i32, []),
@@ -233,6 +264,72 @@ def lf2_batch_info(batch: int):
 
 def lf2_batch_destroy(batch: int):
     _check(load().lf2_batch_destroy(batch), "lf2_batch_destroy")
+
+
+def make_request(sizes, rho_ptr: int, phi_ptr: int, dx: float = 1.0, flags: int = 0,
+                 nbins: int = 0, pk_ptr: int = 0, kmean_ptr: int = 0, count_ptr: int = 0,
+                 t_arrival: float = 0.0) -> lf2_request:
+    lat = lf2_lattice(3, 0, (ctypes.c_int64 * 3)(*[int(v) for v in sizes]))
+    return lf2_request(lat, rho_ptr or None, phi_ptr or None, float(dx), int(flags), int(nbins),
+                       pk_ptr or None, kmean_ptr or None, count_ptr or None, float(t_arrival))
+
+
+def lf2_server_create(budget_bytes: int, max_slots: int, nstreams: int, max_queue: int) -> int:
+    out = _vp()
+    _check(load().lf2_server_create(ctypes.byref(out), int(budget_bytes), int(max_slots),
+                                    int(nstreams), int(max_queue)), "lf2_server_create")
+    return out.value
+
+
+def lf2_server_create_fake(budget_bytes: int, max_slots: int, max_queue: int, delay_us: int,
+                           fail_ticket: int = 0) -> int:
+    out = _vp()
+    _check(load().lf2_server_create_fake(ctypes.byref(out), int(budget_bytes), int(max_slots),
+                                         int(max_queue), int(delay_us), int(fail_ticket)),
+           "lf2_server_create_fake")
+    return out.value
+
+
+def lf2_server_prepare(server: int, sizes_list, nbins: int = 0, dx: float = 1.0, flags: int = 0):
+    _check(load().lf2_server_prepare(server, len(sizes_list), _lattices(sizes_list), int(nbins),
+                                     float(dx), int(flags)), "lf2_server_prepare")
+
+
+def lf2_server_submit_status(server: int, req: lf2_request):
+    """(status, ticket) of lf2_server_submit without raising (BUSY / BUDGET are normal)."""
+    t = ctypes.c_uint64()
+    st = load().lf2_server_submit(server, ctypes.byref(req), ctypes.byref(t))
+    return st, int(t.value)
+
+
+def lf2_server_poll(server: int, ticket: int, wait: bool = True):
+    """None while the request runs (wait=False), else (status, t_arrival, t_admit, t_done)."""
+    r = lf2_result()
+    st = load().lf2_server_poll(server, int(ticket), ctypes.byref(r), int(bool(wait)))
+    if st == LF2_ERR_NOT_READY:
+        return None
+    _check(st, "lf2_server_poll")
+    return int(r.status), float(r.t_arrival), float(r.t_admit), float(r.t_done)
+
+
+def lf2_server_footprint(req: lf2_request) -> int:
+    b = ctypes.c_size_t()
+    _check(load().lf2_server_footprint(ctypes.byref(req), ctypes.byref(b)), "lf2_server_footprint")
+    return int(b.value)
+
+
+def lf2_server_get_stats(server: int) -> dict:
+    st = lf2_server_stats()
+    _check(load().lf2_server_get_stats(server, ctypes.byref(st)), "lf2_server_get_stats")
+    return {name: int(getattr(st, name)) for name, _ in lf2_server_stats._fields_}
+
+
+def lf2_server_destroy(server: int):
+    _check(load().lf2_server_destroy(server), "lf2_server_destroy")
+
+
+def lf2_server_now() -> float:
+    return float(load().lf2_server_now())
 
 
 def lf2_profile_enable(on: bool = True):

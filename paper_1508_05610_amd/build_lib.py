@@ -39,6 +39,7 @@ UNITS = [
     ("lf2_kbatch.hip", [], "kbatch.o"),
     ("lf2_api.cpp", ["-x", "hip"], "api.o"),
     ("lf2_batch.cpp", ["-x", "hip"], "batch.o"),
+    ("lf2_server.cpp", ["-x", "hip"], "server.o"),
 ]
 
 

@@ -729,9 +729,23 @@ lf2_status lf2_fft_execute(lf2_plan p, lf2_direction dir, const void *in, void *
     return run_x(p, 2, sg, x_args(p, W, out, false, true, false), s);
 }
 
-lf2_status lf2_poisson_solve(lf2_plan p, const float *rho, float *phi, double dx, uint32_t flags,
-                             int32_t nbins, double *d_pk, double *d_kmean, double *d_count,
-                             double *d_parseval, void *stream)
+}  // extern "C"
+
+namespace lf2 {
+namespace host {
+
+size_t poisson_ws_bytes(const lf2_plan_s *p, int32_t nbins, bool parseval)
+{
+    const int nb = nbins > 0 ? nbins : (parseval ? 1 : 0);
+    return ws_layout(p, true, nb, parseval).total;
+}
+
+// Poisson solve on `stream`; ws_given (nullable) is a workspace of at least
+// poisson_ws_bytes bytes reserved for this call, else the plan's workspace.
+lf2_status poisson_impl(lf2_plan p, const float *rho, float *phi, double dx, uint32_t flags,
+                        int32_t nbins, double *d_pk, double *d_kmean, double *d_count,
+                        double *d_parseval, hipStream_t stream, char *ws_given,
+                        size_t ws_given_bytes)
 {
     if (!p) return fail(LF2_ERR_INVALID_ARG, "plan is NULL");
     if (p->kind != LF2_R2C || p->nc != 1)
@@ -751,7 +765,14 @@ lf2_status lf2_poisson_solve(lf2_plan p, const float *rho, float *phi, double dx
     const int nb = nbins > 0 ? nbins : (parseval ? 1 : 0);
     WsLayout L = ws_layout(p, true, nb, parseval);
     char *ws;
-    if ((st = get_workspace(p, L.total, &ws))) return st;
+    if (ws_given) {
+        if (ws_given_bytes < L.total)
+            return fail(LF2_ERR_INVALID_ARG, "workspace of %zu bytes < %zu needed", ws_given_bytes,
+                        L.total);
+        ws = ws_given;
+    } else if ((st = get_workspace(p, L.total, &ws))) {
+        return st;
+    }
     void *W = ws + L.w;
     const double *k2[3];
     if ((st = get_k2(p, dx, (flags & LF2_POISSON_DISCRETE_K2) ? 1 : 0, s, k2))) return st;
@@ -789,6 +810,19 @@ lf2_status lf2_poisson_solve(lf2_plan p, const float *rho, float *phi, double dx
             return st;
     }
     return LF2_OK;
+}
+
+}  // namespace host
+}  // namespace lf2
+
+extern "C" {
+
+lf2_status lf2_poisson_solve(lf2_plan p, const float *rho, float *phi, double dx, uint32_t flags,
+                             int32_t nbins, double *d_pk, double *d_kmean, double *d_count,
+                             double *d_parseval, void *stream)
+{
+    return poisson_impl(p, rho, phi, dx, flags, nbins, d_pk, d_kmean, d_count, d_parseval,
+                        (hipStream_t)stream, nullptr, 0);
 }
 
 lf2_status lf2_power_spectrum(lf2_plan p, const void *field, int32_t field_is_kspace, int32_t nbins,

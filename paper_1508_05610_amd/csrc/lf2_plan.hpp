@@ -81,5 +81,11 @@ XArgs x_args(const lf2_plan_s *p, const void *in, void *out, bool in_is_x, bool 
 SArgs s_args(const lf2_plan_s *p, int axis, const void *in, void *out, int epi);
 lf2_status check_bins(const lf2_plan_s *p, int32_t nbins);
 
+size_t poisson_ws_bytes(const lf2_plan_s *p, int32_t nbins, bool parseval);
+lf2_status poisson_impl(lf2_plan p, const float *rho, float *phi, double dx, uint32_t flags,
+                        int32_t nbins, double *d_pk, double *d_kmean, double *d_count,
+                        double *d_parseval, hipStream_t stream, char *ws_given,
+                        size_t ws_given_bytes);
+
 }  // namespace host
 }  // namespace lf2
