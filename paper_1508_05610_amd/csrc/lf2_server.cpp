@@ -13,6 +13,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <chrono>
 #include <condition_variable>
@@ -116,7 +117,7 @@ struct lf2_server_s {
     size_t budget = 0;
     int max_slots = 1, nstreams = 1, max_queue = 1;
     std::vector<hipStream_t> streams;
-    int rr = 0;
+    std::atomic<unsigned> rr{0};
 
     std::mutex mu;
     std::condition_variable cv_sched, cv_done, cv_compl;
@@ -228,11 +229,11 @@ void ev_put(lf2_server s, hipEvent_t e)
     s->ev_free.push_back(e);
 }
 
-// Launch one admitted request (scheduler thread, no server lock held).  On
-// failure nothing of the request is left running on the device.
+// Launch one admitted request (no server lock held; the scheduler thread or
+// a submitting thread).  On failure nothing of the request is left running
+// on the device.
 void launch(lf2_server s, Req *q)
 {
-    q->t_adm = now_s();
     lf2_plan plan = nullptr;
     lf2_status st = get_plan(s, q->key, q->r.lat, &plan);
     if (st) {
@@ -241,7 +242,6 @@ void launch(lf2_server s, Req *q)
     }
     q->has_plan = true;
     if (s->fake) {
-        q->due = q->t_adm + 1e-6 * s->delay_us;
         q->st = (q->ticket == s->fail_ticket) ? LF2_ERR_DEVICE : LF2_OK;
         return;
     }
@@ -251,7 +251,7 @@ void launch(lf2_server s, Req *q)
         q->st = LF2_ERR_OUT_OF_MEMORY;
         return;
     }
-    hipStream_t strm = s->streams[s->rr++ % s->nstreams];
+    hipStream_t strm = s->streams[s->rr.fetch_add(1) % (unsigned)s->nstreams];
     {
         // Tables a plan builds on first use are written on this stream;
         // later requests may run on other streams, so wait for them once.
@@ -286,6 +286,44 @@ void release(lf2_server s, Req *q)
     q->ev = nullptr;
 }
 
+// Admit from the head of the queue while a slot and budget are free (FIFO:
+// a request that does not fit holds back the ones behind it).  Server lock
+// held.
+void admit_locked(lf2_server s, std::vector<Req *> &adm)
+{
+    while (!s->queue.empty()) {
+        Req *q = s->queue.front();
+        if ((int)s->inflight.size() + s->launching >= s->max_slots) break;
+        if (s->bytes_inflight + q->bytes > s->budget) break;
+        s->queue.pop_front();
+        s->bytes_inflight += q->bytes;
+        s->peak = std::max(s->peak, s->bytes_inflight);
+        s->launching += 1;
+        q->t_adm = now_s();
+        adm.push_back(q);
+    }
+}
+
+// Launch admitted requests and hand them to the completion thread; called
+// and returns with the server lock held.
+void launch_admitted(lf2_server s, std::unique_lock<std::mutex> &lk, std::vector<Req *> &adm)
+{
+    if (adm.empty()) return;
+    lk.unlock();
+    int prev = -1;
+    if (!s->fake && hipGetDevice(&prev) == hipSuccess && prev != s->device)
+        (void)hipSetDevice(s->device);  // a submitting thread may have another device current
+    for (Req *q : adm) {
+        launch(s, q);
+        if (s->fake) q->due = q->t_adm + 1e-6 * s->delay_us;
+    }
+    if (prev >= 0 && prev != s->device) (void)hipSetDevice(prev);
+    lk.lock();
+    s->launching -= (int)adm.size();
+    for (Req *q : adm) s->inflight.push_back(q);
+    s->cv_compl.notify_one();
+}
+
 void scheduler_main(lf2_server s)
 {
     if (!s->fake) (void)hipSetDevice(s->device);
@@ -294,27 +332,13 @@ void scheduler_main(lf2_server s)
         s->cv_sched.wait(lk, [&] {
             if (s->stop) return true;
             if (s->queue.empty()) return false;
-            return (int)s->inflight.size() < s->max_slots &&
+            return (int)s->inflight.size() + s->launching < s->max_slots &&
                    s->bytes_inflight + s->queue.front()->bytes <= s->budget;
         });
         if (s->stop) break;
         std::vector<Req *> adm;
-        while (!s->queue.empty()) {
-            Req *q = s->queue.front();
-            if ((int)(s->inflight.size() + adm.size()) >= s->max_slots) break;
-            if (s->bytes_inflight + q->bytes > s->budget) break;
-            s->queue.pop_front();
-            s->bytes_inflight += q->bytes;
-            s->peak = std::max(s->peak, s->bytes_inflight);
-            adm.push_back(q);
-        }
-        s->launching = (int)adm.size();
-        lk.unlock();
-        for (Req *q : adm) launch(s, q);
-        lk.lock();
-        s->launching = 0;
-        for (Req *q : adm) s->inflight.push_back(q);
-        s->cv_compl.notify_one();
+        admit_locked(s, adm);
+        launch_admitted(s, lk, adm);
     }
 }
 
@@ -352,8 +376,13 @@ void completion_main(lf2_server s)
         for (Req *q : fin) release(s, q);
         lk.lock();
         if (fin.empty()) {
+            // requests in flight: poll again at once (yield the core to
+            // other runnable threads); the fake executor's delays are long
             lk.unlock();
-            std::this_thread::sleep_for(std::chrono::microseconds(20));
+            if (s->fake)
+                std::this_thread::sleep_for(std::chrono::microseconds(50));
+            else
+                std::this_thread::yield();
             lk.lock();
             continue;
         }
@@ -505,11 +534,12 @@ lf2_status lf2_server_submit(lf2_server s, const lf2_request *r, uint64_t *ticke
     q->ws_bytes = ws_bytes_of(r->lat, r->nbins);
     q->key = LatKey{r->lat.size[0], r->lat.size[1], r->lat.size[2]};
     q->t_arr = r->t_arrival > 0 ? r->t_arrival : now_s();
-    std::lock_guard<std::mutex> lk(s->mu);
+    std::unique_lock<std::mutex> lk(s->mu);
     if (q->bytes > s->budget) {
         s->n_budget += 1;
+        const size_t b = q->bytes;
         delete q;
-        return fail(LF2_ERR_BUDGET, "request footprint %zu bytes exceeds the budget %zu", q->bytes,
+        return fail(LF2_ERR_BUDGET, "request footprint %zu bytes exceeds the budget %zu", b,
                     s->budget);
     }
     if (s->draining || (int)s->queue.size() >= s->max_queue) {
@@ -522,7 +552,14 @@ lf2_status lf2_server_submit(lf2_server s, const lf2_request *r, uint64_t *ticke
     s->queue.push_back(q);
     s->n_sub += 1;
     *ticket = q->ticket;
-    s->cv_sched.notify_one();
+    if (s->queue.size() == 1) {
+        // nothing waits ahead of it: admit and launch on this thread, which
+        // saves the hand-off to the scheduler thread
+        std::vector<Req *> adm;
+        admit_locked(s, adm);
+        launch_admitted(s, lk, adm);
+    }
+    if (!s->queue.empty()) s->cv_sched.notify_one();
     return LF2_OK;
 }
 
