@@ -59,13 +59,21 @@ def _ptr(t, what, dtype, shape):
 class Plan:
     """A PlanFFT (paper section 3.6) on an N0 x N1 x N2 lattice with halo h."""
 
-    def __init__(self, sizes, kind=LF2_R2C, ncomp=1, halo=0):
+    def __init__(self, sizes, kind=LF2_R2C, ncomp=1, halo=0, autotune=False):
         self.sizes = tuple(int(s) for s in sizes)
         self.kind = kind
         self.ncomp = int(ncomp)
         self.halo = int(halo)
-        self.handle = lf2_fft_plan(self.sizes, self.halo, self.ncomp, kind)
+        flags = _lib.LF2_PLAN_AUTOTUNE if autotune else 0
+        self.handle = lf2_fft_plan(self.sizes, self.halo, self.ncomp, kind, flags)
         self.ksize, self.kstride = lf2_fft_kspace(self.handle)
+
+    def variant(self, axis):
+        """(variant, us_narrow, us_wide) of the strided pass along axis 1 or 2."""
+        return _lib.lf2_plan_get_variant(self.handle, axis)
+
+    def set_variant(self, axis, variant):
+        _lib.lf2_plan_set_variant(self.handle, axis, variant)
 
     def close(self):
         if self.handle:

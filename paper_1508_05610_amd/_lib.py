@@ -27,6 +27,7 @@ LF2_C2C = 1
 LF2_FORWARD = -1
 LF2_BACKWARD = 1
 
+LF2_PLAN_AUTOTUNE = 0x10
 LF2_POISSON_CONTINUOUS_K2 = 0
 LF2_POISSON_DISCRETE_K2 = 1
 LF2_PK_OF_PHI = 2
@@ -71,6 +72,9 @@ _SIGS = {
     "lf2_fft_plan": (_i32, [ctypes.POINTER(_vp), ctypes.POINTER(lf2_lattice), _i32, _i32, _u32]),
     "lf2_fft_kspace": (_i32, [_vp, ctypes.POINTER(_i64), ctypes.POINTER(_i64)]),
     "lf2_plan_workspace_bytes": (_i32, [_vp, ctypes.POINTER(ctypes.c_size_t)]),
+    "lf2_plan_get_variant": (_i32, [_vp, _i32, ctypes.POINTER(_i32), ctypes.POINTER(_f64),
+                                    ctypes.POINTER(_f64)]),
+    "lf2_plan_set_variant": (_i32, [_vp, _i32, _i32]),
     "lf2_plan_set_workspace": (_i32, [_vp, _vp, ctypes.c_size_t]),
     "lf2_fft_execute": (_i32, [_vp, _i32, _vp, _vp, _vp]),
     "lf2_poisson_solve": (_i32, [_vp, _vp, _vp, _f64, _u32, _i32, _vp, _vp, _vp, _vp, _vp]),
@@ -164,6 +168,19 @@ def lf2_fft_kspace(plan: int):
     st = (_i64 * 3)()
     _check(load().lf2_fft_kspace(plan, ks, st), "lf2_fft_kspace")
     return tuple(ks), tuple(st)
+
+
+def lf2_plan_get_variant(plan: int, axis: int):
+    v = _i32()
+    a = _f64()
+    b = _f64()
+    _check(load().lf2_plan_get_variant(plan, int(axis), ctypes.byref(v), ctypes.byref(a),
+                                       ctypes.byref(b)), "lf2_plan_get_variant")
+    return int(v.value), float(a.value), float(b.value)
+
+
+def lf2_plan_set_variant(plan: int, axis: int, variant: int):
+    _check(load().lf2_plan_set_variant(plan, int(axis), int(variant)), "lf2_plan_set_variant")
 
 
 def lf2_plan_workspace_bytes(plan: int) -> int:

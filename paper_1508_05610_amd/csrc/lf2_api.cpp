@@ -419,14 +419,16 @@ lf2_status run_strided(const lf2_plan_s *p, int axis, int sign, const SArgs &a, 
 {
     const double sb = (double)spectrum_bytes(p);
     const bool epi = (a.epi & (EPI_PK | EPI_PK_AFTER | EPI_POISSON)) != 0;
+    const int variant = epi ? 0 : p->svar[axis];
     // "<kernel symbol> <pass>": the symbol part matches the profiler's name
-    const int t = prof::begin(kname("k_strided<%d,%d,%d> %s%s%s %lldx%lldx%lld/%d", p->len[axis], sign,
-                                    epi ? 1 : 0, axis == 1 ? "y" : "z",
+    const std::string sym = variant ? kname("k_strided_w<%d,%d>", p->len[axis], sign)
+                                    : kname("k_strided<%d,%d,%d>", p->len[axis], sign, epi ? 1 : 0);
+    const int t = prof::begin(sym + kname(" %s%s%s %lldx%lldx%lld/%d", axis == 1 ? "y" : "z",
                                     (a.epi & EPI_POISSON) ? "+poisson" : "",
                                     (a.epi & (EPI_PK | EPI_PK_AFTER)) ? "+pk" : "",
                                     (long long)p->n[0], (long long)p->n[1], (long long)p->n[2], p->nc),
                               (a.epi & EPI_STORE) ? 2 * sb : sb, s);
-    hipError_t e = launch_strided(p->len[axis], sign, a, grid_cap, s, grid_used);
+    hipError_t e = launch_strided(p->len[axis], sign, a, grid_cap, s, grid_used, variant);
     prof::end(t, s);
     if (e != hipSuccess)
         return fail(LF2_ERR_DEVICE, "strided pass (axis %d, L=%d) launch: %s", axis, p->len[axis],
@@ -558,6 +560,60 @@ lf2_status lf2_profile_get(int32_t i, char *name, size_t name_len, int64_t *laun
 
 const char *lf2_version(void) { return "lf2 0.1.0 gfx950"; }
 
+}  // extern "C"
+
+namespace {
+
+// Time each tile variant of the y and z passes on a scratch spectrum of the
+// plan's shape (one warm-up, then the mean of three launches) and keep the
+// faster one.  Without memory for the scratch spectrum the defaults stay.
+lf2_status autotune(lf2_plan p)
+{
+    const size_t bytes = spectrum_bytes(p);
+    void *w = nullptr;
+    if (hipMalloc(&w, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        return LF2_OK;
+    }
+    hipStream_t s = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    lf2_status st = LF2_OK;
+    auto hip_ok = [&](hipError_t e, const char *what) {
+        if (e != hipSuccess && st == LF2_OK) st = fail(LF2_ERR_DEVICE, "autotune %s: %s", what, hipGetErrorString(e));
+        return st == LF2_OK;
+    };
+    if (hip_ok(hipStreamCreateWithFlags(&s, hipStreamNonBlocking), "stream") &&
+        hip_ok(hipEventCreate(&e0), "event") && hip_ok(hipEventCreate(&e1), "event") &&
+        hip_ok(hipMemsetAsync(w, 0, bytes, s), "memset")) {
+        for (int axis = 1; axis <= 2 && st == LF2_OK; ++axis) {
+            const int nv = s_wide_supported(p->len[axis]) ? 2 : 1;
+            if (nv == 1) continue;
+            const SArgs a = s_args(p, axis, w, w, EPI_STORE);
+            for (int v = 0; v < nv && st == LF2_OK; ++v) {
+                hip_ok(launch_strided(p->len[axis], -1, a, kStridedGridCap, s, nullptr, v), "launch");
+                hip_ok(hipEventRecord(e0, s), "record");
+                for (int r = 0; r < 3; ++r)
+                    hip_ok(launch_strided(p->len[axis], -1, a, kStridedGridCap, s, nullptr, v), "launch");
+                hip_ok(hipEventRecord(e1, s), "record");
+                float ms = 0.f;
+                if (hip_ok(hipEventSynchronize(e1), "sync") && hip_ok(hipEventElapsedTime(&ms, e0, e1), "elapsed"))
+                    p->tune_us[axis][v] = 1e3 * ms / 3.0;
+            }
+            if (st == LF2_OK) p->svar[axis] = p->tune_us[axis][1] < p->tune_us[axis][0] ? 1 : 0;
+        }
+    }
+    if (s) (void)hipStreamSynchronize(s);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (s) (void)hipStreamDestroy(s);
+    (void)hipFree(w);
+    return st;
+}
+
+}  // namespace
+
+extern "C" {
+
 lf2_status lf2_fft_plan(lf2_plan *out, const lf2_lattice *lat, int32_t ncomp, lf2_fft_kind kind,
                         uint32_t flags)
 {
@@ -568,7 +624,7 @@ lf2_status lf2_fft_plan(lf2_plan *out, const lf2_lattice *lat, int32_t ncomp, lf
     if (lat->halo < 0) return fail(LF2_ERR_INVALID_ARG, "halo %d < 0", lat->halo);
     if (kind != LF2_R2C && kind != LF2_C2C) return fail(LF2_ERR_INVALID_ARG, "bad kind %d", (int)kind);
     if (ncomp < 1) return fail(LF2_ERR_INVALID_ARG, "ncomp %d < 1", ncomp);
-    if (flags != 0) return fail(LF2_ERR_UNSUPPORTED, "plan flags 0x%x not supported", flags);
+    if (flags & ~LF2_PLAN_AUTOTUNE) return fail(LF2_ERR_UNSUPPORTED, "plan flags 0x%x not supported", flags);
     for (int i = 0; i < 3; ++i) {
         if (lat->size[i] < 1) return fail(LF2_ERR_INVALID_ARG, "size[%d] = %lld < 1", i, (long long)lat->size[i]);
         if (lat->size[i] > (1 << 20)) return fail(LF2_ERR_UNSUPPORTED, "size[%d] too large", i);
@@ -636,11 +692,34 @@ lf2_status lf2_fft_plan(lf2_plan *out, const lf2_lattice *lat, int32_t ncomp, lf
         e = hipDeviceSynchronize();
         if (e != hipSuccess) st = fail(LF2_ERR_DEVICE, "plan setup: %s", hipGetErrorString(e));
     }
+    if (st == LF2_OK && (flags & LF2_PLAN_AUTOTUNE)) st = autotune(p);
     if (st != LF2_OK) {
         lf2_plan_destroy(p);
         return st;
     }
     *out = p;
+    return LF2_OK;
+}
+
+lf2_status lf2_plan_get_variant(lf2_plan p, int32_t axis, int32_t *variant, double *us_narrow,
+                                double *us_wide)
+{
+    if (!p) return fail(LF2_ERR_INVALID_ARG, "plan is NULL");
+    if (axis != 1 && axis != 2) return fail(LF2_ERR_INVALID_ARG, "axis %d is not 1 or 2", axis);
+    if (variant) *variant = p->svar[axis];
+    if (us_narrow) *us_narrow = p->tune_us[axis][0];
+    if (us_wide) *us_wide = p->tune_us[axis][1];
+    return LF2_OK;
+}
+
+lf2_status lf2_plan_set_variant(lf2_plan p, int32_t axis, int32_t variant)
+{
+    if (!p) return fail(LF2_ERR_INVALID_ARG, "plan is NULL");
+    if (axis != 1 && axis != 2) return fail(LF2_ERR_INVALID_ARG, "axis %d is not 1 or 2", axis);
+    if (variant != 0 && variant != 1) return fail(LF2_ERR_INVALID_ARG, "variant %d is not 0 or 1", variant);
+    if (variant == 1 && !s_wide_supported(p->len[axis]))
+        return fail(LF2_ERR_UNSUPPORTED, "no wide tiles for line length %d", p->len[axis]);
+    p->svar[axis] = variant;
     return LF2_OK;
 }
 

@@ -2,8 +2,8 @@
 //
 // Every pass is written as a per-tile device function that works in an LDS
 // area handed to it by the caller.  The standalone kernels below run one
-// pass over one field; the batch kernel (lf2_kbatch.hip) runs the same tile
-// functions for many fields and passes inside one persistent launch.
+// pass over one field; the batch kernels (lf2_kbatch.hip) run the same tile
+// functions over the tiles of many fields, one launch per (pass, length).
 //
 // x pass  : lines along dimension 0 are contiguous in memory.  A tile is RB
 //           rows (all components of each row).  One-component rows with
@@ -333,18 +333,35 @@ struct XC2RV {
         for (int i = tid; i < RB; i += NT) ob[i] >>= 1;
         const int nv = rows_valid<RB>(a, r0);
         const c32 *in = (const c32 *)a.in;
-        // TPR threads per row, each walking one row: a single row offset per
-        // thread, loads of a wave contiguous within each row.
-        constexpr int TPR = NT / RB >= 1 ? NT / RB : 1;
-        constexpr int NK = (NH + TPR - 1) / TPR;
-        for (int l = tid / TPR; l < RB; l += NT / TPR) {
-            const int64_t base = ib[l];
-            const bool ok = l < nv;
-            const int k0 = tid % TPR;
+        if (a.in_row == NH && a.in_plane == (int64_t)a.n1 * NH) {
+            // Dense half spectrum: the tile's rows are one contiguous run of
+            // nv * NH values with the LDS layout's pitch (LP = NH), copied
+            // with 16-byte loads when the run is 16-byte aligned.
+            const c32 *src = in + ib[0];
+            const int cnt = nv * NH;
+            if (((uintptr_t)src & 15) == 0) {
+                const float4 *s4 = (const float4 *)src;
+                float4 *d4 = (float4 *)buf;
+                for (int e = tid; e < cnt / 2; e += NT) d4[e] = s4[e];
+                if ((cnt & 1) && tid == 0) buf[cnt - 1] = src[cnt - 1];
+            } else {
+                for (int e = tid; e < cnt; e += NT) buf[e] = src[e];
+            }
+            for (int e = cnt + tid; e < RB * LP; e += NT) buf[e] = c32{0.f, 0.f};
+        } else {
+            // TPR threads per row, each walking one row: a single row offset
+            // per thread, loads of a wave contiguous within each row.
+            constexpr int TPR = NT / RB >= 1 ? NT / RB : 1;
+            constexpr int NK = (NH + TPR - 1) / TPR;
+            for (int l = tid / TPR; l < RB; l += NT / TPR) {
+                const int64_t base = ib[l];
+                const bool ok = l < nv;
+                const int k0 = tid % TPR;
 #pragma unroll
-            for (int i = 0; i < NK; ++i) {
-                const int k = k0 + i * TPR;
-                if (k < NH) buf[l * LP + k] = ok ? in[base + k] : c32{0.f, 0.f};
+                for (int i = 0; i < NK; ++i) {
+                    const int k = k0 + i * TPR;
+                    if (k < NH) buf[l * LP + k] = ok ? in[base + k] : c32{0.f, 0.f};
+                }
             }
         }
         __syncthreads();
@@ -418,6 +435,24 @@ __device__ __forceinline__ int bin_of(int64_t q, const int64_t *thresh, int nbin
     return b;
 }
 
+// The same bin for q, walking the thresholds from bin b (exact for any b).
+__device__ __forceinline__ int bin_step(int64_t q, int b, const int64_t *thresh, int nbins)
+{
+    while (b + 1 < nbins && thresh[b + 1] <= q) ++b;
+    while (b > 0 && thresh[b] > q) --b;
+    return b;
+}
+
+// 1/d for d > 0 in FP64: hardware reciprocal refined by two Newton steps
+// (relative error near one FP64 ulp; the scale it feeds is rounded to FP32).
+__device__ __forceinline__ double rcp_f64(double d)
+{
+    double r = __builtin_amdgcn_rcp(d);
+    r = fma(fma(-d, r, 1.0), r, r);
+    r = fma(fma(-d, r, 1.0), r, r);
+    return r;
+}
+
 // ============================================================ strided tiles
 // EPI = false: plain pass (no epilogue code, fewest registers);
 // EPI = true : last-axis pass with the binning / Poisson epilogue.
@@ -468,7 +503,7 @@ struct STile {
             int64_t qxy = 0;
             if (valid && (a.epi & EPI_POISSON)) k2xy = a.mt.k2[0][kx] + a.mt.k2[1][ky];
             if (valid && pk) qxy = a.mt.q[0][kx] + a.mt.q[1][ky];
-            int cur = -1;
+            int cur = -1, bprev = -1;
             double acc = 0.0;
             for (int e = 0; e < EP; ++e) {
                 const int kz = rg * EP + e;
@@ -476,7 +511,13 @@ struct STile {
                 c32 v = buf[kz * B + col];
                 const bool zero = (kx == 0 && ky == 0 && kz == 0);
                 int b = nb;
-                if (pk && !zero) b = bin_of(qxy + a.mt.q[2][kz], thresh, nb, inv_qmax);
+                if (pk && !zero) {
+                    // consecutive kz move q a little: walk the thresholds from
+                    // the previous bin instead of a fresh estimate
+                    const int64_t q = qxy + a.mt.q[2][kz];
+                    b = bprev < 0 ? bin_of(q, thresh, nb, inv_qmax) : bin_step(q, bprev, thresh, nb);
+                    bprev = b;
+                }
                 if (a.epi & EPI_PK) {
                     const double p = wgt * ((double)v.x * v.x + (double)v.y * v.y);
                     if (b != cur) {
@@ -487,7 +528,7 @@ struct STile {
                     acc += p;
                 }
                 if (a.epi & EPI_POISSON) {
-                    const double sc = zero ? 0.0 : -a.mt.scale_n / (k2xy + a.mt.k2[2][kz]);
+                    const double sc = zero ? 0.0 : -a.mt.scale_n * rcp_f64(k2xy + a.mt.k2[2][kz]);
                     v = c32{(float)((double)v.x * sc), (float)((double)v.y * sc)};
                     buf[kz * B + col] = v;
                 }
@@ -516,6 +557,39 @@ struct STile {
                     gout[(int64_t)row * a.stride] = buf[row * B + col];
             }
         }
+        __syncthreads();
+    }
+};
+
+// Wide strided tile: twice the columns of STile (256-byte row segments at
+// L = 512) with twice the threads, one block per CU: for long strides (the
+// last axis of large or multi-component fields), where longer contiguous
+// segments per row pay for the lower block count.  No epilogue.
+constexpr int kSWThreads = 1024;
+
+template <int L, int S, int NT>
+struct STileW {
+    static constexpr int B = 2 * s_b(L);
+    static constexpr size_t O_BUF = 0, O_TW = al16(sizeof(c32) * L * B),
+                            BYTES = al16(O_TW + sizeof(c32) * L);
+    static __device__ void tables(const SArgs &a, char *sm, int tid)
+    {
+        load_table((c32 *)(sm + O_TW), a.tw, L, tid, NT);
+    }
+    static __device__ void tile(const SArgs &a, int64_t t, char *sm, int tid)
+    {
+        c32 *buf = (c32 *)(sm + O_BUF);
+        const c32 *tw = (const c32 *)(sm + O_TW);
+        const int col = tid % B;
+        const int64_t f = t * B + col;
+        const bool valid = f < a.ncols;
+        int64_t base = 0;
+        if (valid) {
+            const int64_t o = f / a.ncols_inner;
+            base = o * a.outer + (f - o * a.ncols_inner);
+        }
+        col_fft<L, S, B, NT, true, true>(buf, (const c32 *)a.in + base, (c32 *)a.out + base,
+                                         a.stride, valid && (a.epi & EPI_STORE) != 0, tw, tid);
         __syncthreads();
     }
 };
@@ -608,6 +682,26 @@ __global__ __launch_bounds__(kSThreads) __attribute__((amdgpu_waves_per_eu(4))) 
     if (pk) {
         __syncthreads();
         for (int i = tid; i <= nb; i += NT) a.partial[(int64_t)blockIdx.x * (nb + 1) + i] = hist[i];
+    }
+}
+
+template <int L, int S>
+__global__ __launch_bounds__(kSWThreads) void k_strided_w(SArgs a)
+{
+    using T = STileW<L, S, kSWThreads>;
+    constexpr int B = T::B;
+    __shared__ __align__(16) char sm[T::BYTES];
+    const int tid = threadIdx.x;
+    T::tables(a, sm, tid);
+    __syncthreads();
+    const int64_t ntiles = (a.ncols + B - 1) / B;
+    const int64_t K = a.xcd_chunk;  // the XCD-aware walk of k_strided
+    const int64_t span = (ntiles + 8 * K - 1) / (8 * K) * (8 * K);
+    for (int64_t vb = blockIdx.x; vb < span; vb += gridDim.x) {
+        const int64_t lb = vb / 8;
+        const int64_t t = ((lb / K) * 8 + (vb % 8)) * K + lb % K;
+        if (t >= ntiles) continue;  // uniform over the block
+        T::tile(a, t, sm, tid);
     }
 }
 

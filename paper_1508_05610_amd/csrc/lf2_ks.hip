@@ -18,8 +18,48 @@ bool s_supported(int len)
 
 int s_cols_per_block(int len) { return s_b(len); }
 
+// Lengths with a wide (split-exchange) tile: the long lines, whose narrow
+// tiles read the shortest row segments.
+#define LF2_WIDE_LENGTHS(X) X(256) X(320) X(384) X(512) X(640) X(768) X(1024)
+
+bool s_wide_supported(int len)
+{
+    switch (len) {
+#define LF2_CASE(L) case L:
+        LF2_WIDE_LENGTHS(LF2_CASE)
+#undef LF2_CASE
+        return true;
+    default:
+        return false;
+    }
+}
+
+static hipError_t launch_wide(int len, int sign, const SArgs &a, int grid_cap, hipStream_t s,
+                              int *grid_used, int chunk)
+{
+#define LF2_CASE(L)                                                                          \
+    case L: {                                                                                \
+        constexpr int B = STileW<L, 1, kSWThreads>::B;                                        \
+        int64_t ntiles = (a.ncols + B - 1) / B;                                              \
+        int64_t span = (ntiles + 8 * chunk - 1) / (8 * chunk) * (8 * chunk);                 \
+        int g = (int)(span < grid_cap ? span : grid_cap);                                    \
+        if (grid_used) *grid_used = g;                                                       \
+        if (sign < 0)                                                                        \
+            hipLaunchKernelGGL((k_strided_w<L, -1>), dim3(g), dim3(kSWThreads), 0, s, a);     \
+        else                                                                                 \
+            hipLaunchKernelGGL((k_strided_w<L, 1>), dim3(g), dim3(kSWThreads), 0, s, a);     \
+        return hipGetLastError();                                                            \
+    }
+    switch (len) {
+        LF2_WIDE_LENGTHS(LF2_CASE)
+    default:
+        return hipErrorInvalidValue;
+    }
+#undef LF2_CASE
+}
+
 hipError_t launch_strided(int len, int sign, const SArgs &a_in, int grid_cap, hipStream_t s,
-                          int *grid_used)
+                          int *grid_used, int variant)
 {
     // 16 tiles per XCD chunk; the grid is a multiple of 8 (grid_cap is).
     constexpr int kChunk = 16;
@@ -30,6 +70,10 @@ hipError_t launch_strided(int len, int sign, const SArgs &a_in, int grid_cap, hi
     const bool pk = (a.epi & (EPI_PK | EPI_PK_AFTER)) != 0;
     const bool epi = (a.epi & (EPI_PK | EPI_PK_AFTER | EPI_POISSON)) != 0;
     const size_t shm = pk ? (size_t)(a.mt.nbins + 1) * 16 : 0;
+    if (variant == 1) {
+        if (epi || !s_wide_supported(len)) return hipErrorInvalidValue;
+        return launch_wide(len, sign, a, grid_cap, s, grid_used, kChunk);
+    }
 #define LF2_CASE(L)                                                                          \
     case L: {                                                                                \
         int64_t ntiles = (a.ncols + s_b(L) - 1) / s_b(L);                                    \

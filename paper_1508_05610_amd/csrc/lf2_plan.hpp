@@ -33,6 +33,8 @@ struct lf2_plan_s {
     int64_t nxk = 0;   // k-space extent of dimension 0
     int64_t ntot = 0;  // N0 N1 N2
     int len[3] = {0, 0, 0};
+    int svar[3] = {0, 0, 0};              // strided tile variant per axis (1, 2)
+    double tune_us[3][2] = {{-1, -1}, {-1, -1}, {-1, -1}};
     void *tw[3] = {nullptr, nullptr, nullptr};
     void *tw_post = nullptr;
     int64_t *q[3] = {nullptr, nullptr, nullptr};

@@ -68,3 +68,16 @@ def test_python_binding_raises(lib):
     with pytest.raises(lib.LF2Error) as ei:
         lib.lf2_fft_plan((7, 8, 8), 0, 1, 0)
     assert ei.value.status == lib.LF2_ERR_UNSUPPORTED
+
+
+def test_variant_calls_validate(lib):
+    so = lib.load()
+    import ctypes
+    v = ctypes.c_int32()
+    assert so.lf2_plan_get_variant(None, 1, ctypes.byref(v), None, None) == lib.LF2_ERR_INVALID_ARG
+    assert so.lf2_plan_set_variant(None, 2, 1) == lib.LF2_ERR_INVALID_ARG
+
+
+def test_unknown_plan_flag(lib):
+    st = lib.lf2_fft_plan_status((32, 32, 32), 0, 1, 0, flags=0x20)
+    assert st == lib.LF2_ERR_UNSUPPORTED

@@ -166,3 +166,60 @@ def test_round_trip(lf2):
     back = plan.backward(plan.forward(x)) / float(np.prod(shape))
     torch.cuda.synchronize()
     assert rel_l2(back.cpu().numpy(), dense[..., 0]) <= tol(shape)
+
+
+# lines of 256..1024 points along y or z take either tile variant
+WIDE_CASES = [((16, 256, 384), 0, 1), ((32, 64, 512), 0, 1), ((8, 24, 1024), 0, 1),
+              ((40, 320, 96), 0, 1), ((12, 96, 768), 0, 1), ((6, 640, 16), 0, 1),
+              ((16, 512, 256), 1, 3), ((10, 16, 512), 1, 1)]
+
+
+@pytest.mark.parametrize("shape,kind,ncomp", WIDE_CASES)
+def test_wide_tiles_match_oracle_and_narrow(lf2, shape, kind, ncomp):
+    print(f"case wide tiles {shape} kind={kind} ncomp={ncomp}", flush=True)
+    pn = lf2.Plan(shape, kind, ncomp=ncomp)
+    pw = lf2.Plan(shape, kind, ncomp=ncomp)
+    for axis in (1, 2):
+        if shape[axis] >= 256:
+            pw.set_variant(axis, 1)
+            assert pw.variant(axis)[0] == 1
+    if kind == lf2.LF2_R2C:
+        f = real_field(shape, seed=11)[0][..., 0]
+        x = torch.from_numpy(f).to(dev())
+        ref = oracle.r2c(f.astype(np.float64))
+    else:
+        z = complex_field(shape, seed=12, ncomp=ncomp)
+        x = torch.from_numpy(z if ncomp > 1 else z[..., 0]).to(dev())
+        ref = oracle.c2c(z[..., 0].astype(np.complex128), -1)
+    Fn = pn.forward(x)
+    Fw = pw.forward(x)
+    bn = pn.backward(Fn)
+    bw = pw.backward(Fw)
+    torch.cuda.synchronize()
+    got = Fw.cpu().numpy()
+    if ncomp > 1:
+        got = got[..., 0]
+    e = rel_l2(got, ref)
+    report("wide fwd", shape, e, rel_max(got, ref))
+    assert e <= tol(shape)
+    print(f"  wide == narrow bitwise: fwd {bool(torch.equal(Fn, Fw))} bwd {bool(torch.equal(bn, bw))}",
+          flush=True)
+    assert rel_l2(Fw.cpu().numpy(), Fn.cpu().numpy()) <= 1e-6
+    assert rel_l2(bw.cpu().numpy(), bn.cpu().numpy()) <= 1e-6
+
+
+def test_autotune_picks_a_variant(lf2):
+    shape = (64, 256, 512)
+    print(f"case autotune {shape}", flush=True)
+    p = lf2.Plan(shape, lf2.LF2_R2C, autotune=True)
+    for axis in (1, 2):
+        v, un, uw = p.variant(axis)
+        print(f"  axis {axis}: variant {v} narrow {un:.1f} us wide {uw:.1f} us", flush=True)
+        assert v in (0, 1) and un > 0 and uw > 0
+        assert v == (1 if uw < un else 0)
+    q = lf2.Plan((64, 48, 40), lf2.LF2_R2C, autotune=True)
+    assert q.variant(1) == (0, -1.0, -1.0)   # no wide tiles for these lengths
+    f = real_field(shape, seed=13)[0][..., 0]
+    F = p.forward(torch.from_numpy(f).to(dev()))
+    torch.cuda.synchronize()
+    assert rel_l2(F.cpu().numpy(), oracle.r2c(f.astype(np.float64))) <= tol(shape)
