@@ -335,7 +335,8 @@ def main():
     # plans autotuned at creation (tile variant per strided axis; untimed)
     pr = lf2.Plan(n, lf2.LF2_R2C, autotune=True)
     pc = lf2.Plan(n, lf2.LF2_C2C, ncomp=3, autotune=True)
-    tuning = {nm: {f"axis{ax}": dict(zip(("variant", "us_narrow", "us_wide"), p_.variant(ax)))
+    tuning = {nm: {f"axis{ax}": dict(zip(("variant", "chunk", "us_default", "us_tuned"),
+                                         p_.tuning(ax)))
                    for ax in (1, 2)} for nm, p_ in (("r2c", pr), ("c2c3", pc))}
     F = torch.empty(pr.k_shape, dtype=torch.complex64, device=dev)
     back = torch.empty(pr.x_shape, dtype=torch.float32, device=dev)

@@ -84,8 +84,8 @@ typedef enum { LF2_FORWARD = -1, LF2_BACKWARD = +1 } lf2_direction;
 
 /* Plan flags. */
 #define LF2_OUT_OF_PLACE 0u           /* default (section 3.6) */
-#define LF2_PLAN_AUTOTUNE 0x10u       /* time the tile variants of the y and z passes at plan
-                                         time and keep the faster one per axis */
+#define LF2_PLAN_AUTOTUNE 0x10u       /* time the tile variants and XCD chunk sizes of the y and
+                                         z passes at plan time and keep the fastest per axis */
 /* Poisson flags. */
 #define LF2_POISSON_CONTINUOUS_K2 0u  /* k^2 = sum_i (2 pi nt_i / (N_i dx))^2 (default) */
 #define LF2_POISSON_DISCRETE_K2 1u    /* k^2 = sum_i (2/dx)^2 sin^2(pi n_i / N_i) */
@@ -114,19 +114,21 @@ lf2_status lf2_fft_plan(lf2_plan *out, const lf2_lattice *lat, int32_t ncomp, lf
 lf2_status lf2_fft_kspace(lf2_plan p, int64_t ksize[3], int64_t kstride[3]);
 
 /*
- * Tile variant of the strided pass along `axis` (1 = y, 2 = z) for plain
- * transforms: 0 = narrow tiles (all lengths), 1 = wide tiles (twice the
- * columns per tile with a split real/imaginary LDS exchange; lengths 256,
- * 320, 384, 512, 640, 768, 1024).  Both give the same transform up to FP32
- * rounding.  The fused Poisson / power-spectrum pass always uses narrow
- * tiles.  get reports the variant and, after LF2_PLAN_AUTOTUNE, the measured
- * microseconds of each variant (-1 if not measured); null outputs are
- * skipped.  set overrides the choice (LF2_ERR_UNSUPPORTED for a length
- * without wide tiles).
+ * Tuning of the strided pass along `axis` (1 = y, 2 = z) for plain
+ * transforms.  variant 0 = narrow tiles (all lengths); 1 = wide tiles
+ * (twice the columns per tile, one 1024-thread block per CU; lengths 256,
+ * 320, 384, 512, 640, 768, 1024).  chunk = consecutive tiles given to one
+ * XCD in the tile order (1..1024, default 16).  Every setting computes the
+ * same transform bit for bit.  The fused Poisson / power-spectrum pass
+ * always uses narrow tiles and chunk 16.  get reports the setting and,
+ * after LF2_PLAN_AUTOTUNE, the measured microseconds of the default setting
+ * (narrow, 16) and of the chosen one (-1 if not measured); null outputs are
+ * skipped.  set overrides the setting (LF2_ERR_UNSUPPORTED for wide tiles
+ * on a length without them).
  */
-lf2_status lf2_plan_get_variant(lf2_plan p, int32_t axis, int32_t *variant, double *us_narrow,
-                                double *us_wide);
-lf2_status lf2_plan_set_variant(lf2_plan p, int32_t axis, int32_t variant);
+lf2_status lf2_plan_get_tuning(lf2_plan p, int32_t axis, int32_t *variant, int32_t *chunk,
+                               double *us_default, double *us_tuned);
+lf2_status lf2_plan_set_tuning(lf2_plan p, int32_t axis, int32_t variant, int32_t chunk);
 
 /* Bytes of shared workspace an execute call on this plan may use. */
 lf2_status lf2_plan_workspace_bytes(lf2_plan p, size_t *bytes);

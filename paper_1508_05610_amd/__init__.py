@@ -68,12 +68,12 @@ class Plan:
         self.handle = lf2_fft_plan(self.sizes, self.halo, self.ncomp, kind, flags)
         self.ksize, self.kstride = lf2_fft_kspace(self.handle)
 
-    def variant(self, axis):
-        """(variant, us_narrow, us_wide) of the strided pass along axis 1 or 2."""
-        return _lib.lf2_plan_get_variant(self.handle, axis)
+    def tuning(self, axis):
+        """(variant, chunk, us_default, us_tuned) of the strided pass along axis 1 or 2."""
+        return _lib.lf2_plan_get_tuning(self.handle, axis)
 
-    def set_variant(self, axis, variant):
-        _lib.lf2_plan_set_variant(self.handle, axis, variant)
+    def set_tuning(self, axis, variant, chunk=16):
+        _lib.lf2_plan_set_tuning(self.handle, axis, variant, chunk)
 
     def close(self):
         if self.handle:

@@ -72,9 +72,9 @@ _SIGS = {
     "lf2_fft_plan": (_i32, [ctypes.POINTER(_vp), ctypes.POINTER(lf2_lattice), _i32, _i32, _u32]),
     "lf2_fft_kspace": (_i32, [_vp, ctypes.POINTER(_i64), ctypes.POINTER(_i64)]),
     "lf2_plan_workspace_bytes": (_i32, [_vp, ctypes.POINTER(ctypes.c_size_t)]),
-    "lf2_plan_get_variant": (_i32, [_vp, _i32, ctypes.POINTER(_i32), ctypes.POINTER(_f64),
-                                    ctypes.POINTER(_f64)]),
-    "lf2_plan_set_variant": (_i32, [_vp, _i32, _i32]),
+    "lf2_plan_get_tuning": (_i32, [_vp, _i32, ctypes.POINTER(_i32), ctypes.POINTER(_i32),
+                                   ctypes.POINTER(_f64), ctypes.POINTER(_f64)]),
+    "lf2_plan_set_tuning": (_i32, [_vp, _i32, _i32, _i32]),
     "lf2_plan_set_workspace": (_i32, [_vp, _vp, ctypes.c_size_t]),
     "lf2_fft_execute": (_i32, [_vp, _i32, _vp, _vp, _vp]),
     "lf2_poisson_solve": (_i32, [_vp, _vp, _vp, _f64, _u32, _i32, _vp, _vp, _vp, _vp, _vp]),
@@ -170,17 +170,20 @@ def lf2_fft_kspace(plan: int):
     return tuple(ks), tuple(st)
 
 
-def lf2_plan_get_variant(plan: int, axis: int):
+def lf2_plan_get_tuning(plan: int, axis: int):
+    """(variant, chunk, us_default, us_tuned) of the strided pass along axis."""
     v = _i32()
+    c = _i32()
     a = _f64()
     b = _f64()
-    _check(load().lf2_plan_get_variant(plan, int(axis), ctypes.byref(v), ctypes.byref(a),
-                                       ctypes.byref(b)), "lf2_plan_get_variant")
-    return int(v.value), float(a.value), float(b.value)
+    _check(load().lf2_plan_get_tuning(plan, int(axis), ctypes.byref(v), ctypes.byref(c),
+                                      ctypes.byref(a), ctypes.byref(b)), "lf2_plan_get_tuning")
+    return int(v.value), int(c.value), float(a.value), float(b.value)
 
 
-def lf2_plan_set_variant(plan: int, axis: int, variant: int):
-    _check(load().lf2_plan_set_variant(plan, int(axis), int(variant)), "lf2_plan_set_variant")
+def lf2_plan_set_tuning(plan: int, axis: int, variant: int, chunk: int = 16):
+    _check(load().lf2_plan_set_tuning(plan, int(axis), int(variant), int(chunk)),
+           "lf2_plan_set_tuning")
 
 
 def lf2_plan_workspace_bytes(plan: int) -> int:

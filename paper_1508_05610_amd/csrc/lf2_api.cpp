@@ -428,7 +428,8 @@ lf2_status run_strided(const lf2_plan_s *p, int axis, int sign, const SArgs &a, 
                                     (a.epi & (EPI_PK | EPI_PK_AFTER)) ? "+pk" : "",
                                     (long long)p->n[0], (long long)p->n[1], (long long)p->n[2], p->nc),
                               (a.epi & EPI_STORE) ? 2 * sb : sb, s);
-    hipError_t e = launch_strided(p->len[axis], sign, a, grid_cap, s, grid_used, variant);
+    hipError_t e = launch_strided(p->len[axis], sign, a, grid_cap, s, grid_used, variant,
+                                  epi ? 16 : p->schunk[axis]);
     prof::end(t, s);
     if (e != hipSuccess)
         return fail(LF2_ERR_DEVICE, "strided pass (axis %d, L=%d) launch: %s", axis, p->len[axis],
@@ -564,9 +565,10 @@ const char *lf2_version(void) { return "lf2 0.1.0 gfx950"; }
 
 namespace {
 
-// Time each tile variant of the y and z passes on a scratch spectrum of the
-// plan's shape (one warm-up, then the mean of three launches) and keep the
-// faster one.  Without memory for the scratch spectrum the defaults stay.
+// Time the tile variants and XCD chunk sizes of the y and z passes on a
+// scratch spectrum of the plan's shape (one warm-up, then the mean of three
+// launches each) and keep the fastest.  Without memory for the scratch
+// spectrum the defaults stay.
 lf2_status autotune(lf2_plan p)
 {
     const size_t bytes = spectrum_bytes(p);
@@ -582,24 +584,34 @@ lf2_status autotune(lf2_plan p)
         if (e != hipSuccess && st == LF2_OK) st = fail(LF2_ERR_DEVICE, "autotune %s: %s", what, hipGetErrorString(e));
         return st == LF2_OK;
     };
+    static const int kChunks[] = {16, 4, 64};  // the default first
     if (hip_ok(hipStreamCreateWithFlags(&s, hipStreamNonBlocking), "stream") &&
         hip_ok(hipEventCreate(&e0), "event") && hip_ok(hipEventCreate(&e1), "event") &&
         hip_ok(hipMemsetAsync(w, 0, bytes, s), "memset")) {
         for (int axis = 1; axis <= 2 && st == LF2_OK; ++axis) {
             const int nv = s_wide_supported(p->len[axis]) ? 2 : 1;
-            if (nv == 1) continue;
             const SArgs a = s_args(p, axis, w, w, EPI_STORE);
+            double best = -1.0;
             for (int v = 0; v < nv && st == LF2_OK; ++v) {
-                hip_ok(launch_strided(p->len[axis], -1, a, kStridedGridCap, s, nullptr, v), "launch");
-                hip_ok(hipEventRecord(e0, s), "record");
-                for (int r = 0; r < 3; ++r)
-                    hip_ok(launch_strided(p->len[axis], -1, a, kStridedGridCap, s, nullptr, v), "launch");
-                hip_ok(hipEventRecord(e1, s), "record");
-                float ms = 0.f;
-                if (hip_ok(hipEventSynchronize(e1), "sync") && hip_ok(hipEventElapsedTime(&ms, e0, e1), "elapsed"))
-                    p->tune_us[axis][v] = 1e3 * ms / 3.0;
+                for (int c : kChunks) {
+                    hip_ok(launch_strided(p->len[axis], -1, a, kStridedGridCap, s, nullptr, v, c), "launch");
+                    hip_ok(hipEventRecord(e0, s), "record");
+                    for (int r = 0; r < 3; ++r)
+                        hip_ok(launch_strided(p->len[axis], -1, a, kStridedGridCap, s, nullptr, v, c), "launch");
+                    hip_ok(hipEventRecord(e1, s), "record");
+                    float ms = 0.f;
+                    if (!hip_ok(hipEventSynchronize(e1), "sync") || !hip_ok(hipEventElapsedTime(&ms, e0, e1), "elapsed"))
+                        break;
+                    const double us = 1e3 * ms / 3.0;
+                    if (v == 0 && c == 16) p->tune_us[axis][0] = us;
+                    if (best < 0 || us < best) {
+                        best = us;
+                        p->svar[axis] = v;
+                        p->schunk[axis] = c;
+                    }
+                }
             }
-            if (st == LF2_OK) p->svar[axis] = p->tune_us[axis][1] < p->tune_us[axis][0] ? 1 : 0;
+            p->tune_us[axis][1] = best;
         }
     }
     if (s) (void)hipStreamSynchronize(s);
@@ -701,25 +713,28 @@ lf2_status lf2_fft_plan(lf2_plan *out, const lf2_lattice *lat, int32_t ncomp, lf
     return LF2_OK;
 }
 
-lf2_status lf2_plan_get_variant(lf2_plan p, int32_t axis, int32_t *variant, double *us_narrow,
-                                double *us_wide)
+lf2_status lf2_plan_get_tuning(lf2_plan p, int32_t axis, int32_t *variant, int32_t *chunk,
+                               double *us_default, double *us_tuned)
 {
     if (!p) return fail(LF2_ERR_INVALID_ARG, "plan is NULL");
     if (axis != 1 && axis != 2) return fail(LF2_ERR_INVALID_ARG, "axis %d is not 1 or 2", axis);
     if (variant) *variant = p->svar[axis];
-    if (us_narrow) *us_narrow = p->tune_us[axis][0];
-    if (us_wide) *us_wide = p->tune_us[axis][1];
+    if (chunk) *chunk = p->schunk[axis];
+    if (us_default) *us_default = p->tune_us[axis][0];
+    if (us_tuned) *us_tuned = p->tune_us[axis][1];
     return LF2_OK;
 }
 
-lf2_status lf2_plan_set_variant(lf2_plan p, int32_t axis, int32_t variant)
+lf2_status lf2_plan_set_tuning(lf2_plan p, int32_t axis, int32_t variant, int32_t chunk)
 {
     if (!p) return fail(LF2_ERR_INVALID_ARG, "plan is NULL");
     if (axis != 1 && axis != 2) return fail(LF2_ERR_INVALID_ARG, "axis %d is not 1 or 2", axis);
     if (variant != 0 && variant != 1) return fail(LF2_ERR_INVALID_ARG, "variant %d is not 0 or 1", variant);
+    if (chunk < 1 || chunk > 1024) return fail(LF2_ERR_INVALID_ARG, "chunk %d outside [1, 1024]", chunk);
     if (variant == 1 && !s_wide_supported(p->len[axis]))
         return fail(LF2_ERR_UNSUPPORTED, "no wide tiles for line length %d", p->len[axis]);
     p->svar[axis] = variant;
+    p->schunk[axis] = chunk;
     return LF2_OK;
 }
 

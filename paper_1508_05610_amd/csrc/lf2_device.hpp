@@ -334,12 +334,19 @@ __device__ __forceinline__ void col_stage(c32 *buf, const c32 *gin, c32 *gout, i
 // ------------------------------------------------------------ row engine
 // RB rows of NC interleaved components (the x pass): component c of point p
 // of row q sits at global offset rowoff[q] + p * NC + c and at
-// buf[(q * NC + c) * LP + p] in LDS (one LDS line per row and component).
+// buf[(q * NC + c) * LP + lpad(p)] in LDS (one LDS line per row and
+// component).  lpad inserts one empty slot after every 16 points, so the
+// stride-R writes of the early Stockham stages (points j R + r over
+// consecutive j) fall in different banks; LP must be at least
+// lpad(points per line - 1) + 1 (row_pitch).
 // Butterfly b = tid + i NT of a stage maps to component b % NC, then
 // j = (b / NC) % Q, then row b / (NC Q): consecutive lanes walk consecutive
 // memory, so the first stage's global loads (point j + r Q) and the last
 // stage's global stores are contiguous across a wave.  Only rows < nvalid
 // exist in memory.
+
+__host__ __device__ constexpr int lpad(int p) { return p + (p >> 4); }
+__host__ __device__ constexpr int row_pitch(int npoints) { return lpad(npoints - 1) + 1; }
 
 template <int L, int R, int NS, int S, int RB, int NC, int LP, int NT, bool SRC_G, bool DST_G>
 __device__ __forceinline__ void row_stage(c32 *buf, const c32 *gin, c32 *gout,
@@ -363,7 +370,7 @@ __device__ __forceinline__ void row_stage(c32 *buf, const c32 *gin, c32 *gout,
                 if (SRC_G)
                     v[i][r] = q < nvalid ? gin[rowoff_in[q] + (j + r * Q) * NC + c] : c32{0.f, 0.f};
                 else
-                    v[i][r] = buf[l * LP + j + r * Q];
+                    v[i][r] = buf[l * LP + lpad(j + r * Q)];
             }
             if (SRC_G && ssq) {
 #pragma unroll
@@ -396,9 +403,10 @@ __device__ __forceinline__ void row_stage(c32 *buf, const c32 *gin, c32 *gout,
                     for (int r = 0; r < R; ++r) gout[rowoff_out[q] + (j + r * Q) * NC + c] = v[i][r];
                 }
             } else {
-                c32 *dst = buf + l * LP + (j / NS) * NS * R + k;
+                c32 *dst = buf + l * LP;
+                const int p0 = (j / NS) * NS * R + k;
 #pragma unroll
-                for (int r = 0; r < R; ++r) dst[r * NS] = v[i][r];
+                for (int r = 0; r < R; ++r) dst[lpad(p0 + r * NS)] = v[i][r];
             }
         }
     }

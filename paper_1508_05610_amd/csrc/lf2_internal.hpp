@@ -66,9 +66,10 @@ hipError_t launch_x_r2c(int m, int nc, const XArgs &a, hipStream_t s);
 hipError_t launch_x_c2r(int m, int nc, const XArgs &a, hipStream_t s);
 hipError_t launch_x_c2c(int len, int nc, int sign, const XArgs &a, hipStream_t s);
 // variant 0: STile (narrow, any pass); 1: STileW (wide, plain passes of
-// s_wide_supported lengths).
+// s_wide_supported lengths).  chunk: consecutive tiles per XCD in the tile
+// order (16 by default).
 hipError_t launch_strided(int len, int sign, const SArgs &a, int grid_cap, hipStream_t s,
-                          int *grid_used, int variant = 0);
+                          int *grid_used, int variant = 0, int chunk = 16);
 bool s_wide_supported(int len);
 
 // Setup and reduction kernels (FP64).

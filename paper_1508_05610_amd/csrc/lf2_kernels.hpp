@@ -256,7 +256,7 @@ struct XC2RGen {
 // fe = (Z[k] + conj Z[M-k]) / 2, fo = (Z[k] - conj Z[M-k]) / (2i).
 template <int M, int NT>
 struct XR2CV {
-    static constexpr int RB = x_rb(M, 1, NT), LP = M, NH = M + 1, HALF = M / 2 + 1;
+    static constexpr int RB = x_rb(M, 1, NT), LP = row_pitch(M), NH = M + 1, HALF = M / 2 + 1;
     static constexpr size_t O_BUF = 0, O_TW = al16(O_BUF + sizeof(c32) * RB * LP),
                             O_TWP = al16(O_TW + sizeof(c32) * M),
                             O_IB = al16(O_TWP + sizeof(c32) * NH), O_OB = O_IB + 8 * RB,
@@ -291,8 +291,8 @@ struct XR2CV {
                 const int k = idx - l * HALF;
                 if (l < nv) {
                     const c32 *line = buf + l * LP;
-                    const c32 z = line[k];
-                    const c32 zc = conjg(line[k == 0 ? 0 : M - k]);
+                    const c32 z = line[lpad(k)];
+                    const c32 zc = conjg(line[lpad(k == 0 ? 0 : M - k)]);
                     const c32 fe = scl(add(z, zc), 0.5f);
                     const c32 d = sub(z, zc);
                     const c32 fo = c32{0.5f * d.y, -0.5f * d.x};
@@ -312,7 +312,7 @@ struct XR2CV {
 // owns the pair (k, M-k), so the update is in place without a barrier.
 template <int M, int NT>
 struct XC2RV {
-    static constexpr int RB = x_rb(M, 1, NT), LP = M + 1, NH = M + 1, HALF = M / 2 + 1;
+    static constexpr int RB = x_rb(M, 1, NT), LP = row_pitch(M + 1), NH = M + 1, HALF = M / 2 + 1;
     static constexpr size_t O_BUF = 0, O_TW = al16(O_BUF + sizeof(c32) * RB * LP),
                             O_TWP = al16(O_TW + sizeof(c32) * M),
                             O_IB = al16(O_TWP + sizeof(c32) * NH), O_OB = O_IB + 8 * RB,
@@ -335,19 +335,26 @@ struct XC2RV {
         const c32 *in = (const c32 *)a.in;
         if (a.in_row == NH && a.in_plane == (int64_t)a.n1 * NH) {
             // Dense half spectrum: the tile's rows are one contiguous run of
-            // nv * NH values with the LDS layout's pitch (LP = NH), copied
-            // with 16-byte loads when the run is 16-byte aligned.
+            // nv * NH values, read with 16-byte loads when the run is 16-byte
+            // aligned and placed into the padded LDS rows.
             const c32 *src = in + ib[0];
             const int cnt = nv * NH;
+            auto put = [&](int e, c32 v) {
+                const int l = e / NH, k = e - l * NH;
+                buf[l * LP + lpad(k)] = v;
+            };
             if (((uintptr_t)src & 15) == 0) {
                 const float4 *s4 = (const float4 *)src;
-                float4 *d4 = (float4 *)buf;
-                for (int e = tid; e < cnt / 2; e += NT) d4[e] = s4[e];
-                if ((cnt & 1) && tid == 0) buf[cnt - 1] = src[cnt - 1];
+                for (int e = tid; e < cnt / 2; e += NT) {
+                    const float4 w = s4[e];
+                    put(2 * e, c32{w.x, w.y});
+                    put(2 * e + 1, c32{w.z, w.w});
+                }
+                if ((cnt & 1) && tid == 0) put(cnt - 1, src[cnt - 1]);
             } else {
-                for (int e = tid; e < cnt; e += NT) buf[e] = src[e];
+                for (int e = tid; e < cnt; e += NT) put(e, src[e]);
             }
-            for (int e = cnt + tid; e < RB * LP; e += NT) buf[e] = c32{0.f, 0.f};
+            for (int e = cnt + tid; e < RB * NH; e += NT) put(e, c32{0.f, 0.f});
         } else {
             // TPR threads per row, each walking one row: a single row offset
             // per thread, loads of a wave contiguous within each row.
@@ -360,38 +367,82 @@ struct XC2RV {
 #pragma unroll
                 for (int i = 0; i < NK; ++i) {
                     const int k = k0 + i * TPR;
-                    if (k < NH) buf[l * LP + k] = ok ? in[base + k] : c32{0.f, 0.f};
+                    if (k < NH) buf[l * LP + lpad(k)] = ok ? in[base + k] : c32{0.f, 0.f};
                 }
             }
         }
         __syncthreads();
-        constexpr int NP = RB * HALF;
+        if constexpr (nstages(M) >= 2) {
+            // The first inverse stage forms its inputs Z[k] from the bins
+            // X[k], X[M-k] in LDS as it reads them (every read before the
+            // barrier, every write after it), then the remaining stages.
+            constexpr int R = radix_at(M, 0), Q = M / R;
+            constexpr int NBF = RB * Q, NB = (NBF + NT - 1) / NT;
+            c32 v[NB][R];
 #pragma unroll
-        for (int i = 0; i < (NP + NT - 1) / NT; ++i) {
-            const int idx = tid + i * NT;
-            if (idx < NP) {
-                const int l = idx / HALF;
-                const int k = idx - l * HALF;
-                c32 *line = buf + l * LP;
-                c32 xk = line[k], xm = line[M - k];
-                if (k == 0) {
-                    xk.y = 0.f;
-                    xm.y = 0.f;
+            for (int i = 0; i < NB; ++i) {
+                const int b = tid + i * NT;
+                if (NBF % NT == 0 || b < NBF) {
+                    const int j = b % Q, q = b / Q;
+                    const c32 *line = buf + q * LP;
+#pragma unroll
+                    for (int r = 0; r < R; ++r) {
+                        const int k = j + r * Q;
+                        c32 xk = line[lpad(k)], xm = line[lpad(M - k)];
+                        if (k == 0) {
+                            xk.y = 0.f;
+                            xm.y = 0.f;
+                        }
+                        const c32 s1 = add(xk, conjg(xm));
+                        const c32 d1 = mul(conjg(twp[k]), sub(xk, conjg(xm)));
+                        v[i][r] = c32{s1.x - d1.y, s1.y + d1.x};
+                    }
                 }
-                const c32 s1 = add(xk, conjg(xm));
-                const c32 d1 = mul(conjg(twp[k]), sub(xk, conjg(xm)));
-                const c32 zk = c32{s1.x - d1.y, s1.y + d1.x};
-                if (k != 0 && 2 * k != M) {
-                    const c32 s2 = add(xm, conjg(xk));
-                    const c32 d2 = mul(conjg(twp[M - k]), sub(xm, conjg(xk)));
-                    line[M - k] = c32{s2.x - d2.y, s2.y + d2.x};
-                }
-                line[k] = zk;
             }
+            __syncthreads();
+#pragma unroll
+            for (int i = 0; i < NB; ++i) {
+                const int b = tid + i * NT;
+                if (NBF % NT == 0 || b < NBF) {
+                    const int j = b % Q, q = b / Q;
+                    Dft<R, +1>::run(v[i]);
+                    c32 *dst = buf + q * LP;
+#pragma unroll
+                    for (int r = 0; r < R; ++r) dst[lpad(j * R + r)] = v[i][r];
+                }
+            }
+            __syncthreads();
+            row_fft<M, +1, RB, 1, LP, NT, false, true, 1, R>(buf, nullptr, (c32 *)a.out, nullptr,
+                                                             ob, nv, tw, tid);
+        } else {
+            constexpr int NP = RB * HALF;
+#pragma unroll
+            for (int i = 0; i < (NP + NT - 1) / NT; ++i) {
+                const int idx = tid + i * NT;
+                if (idx < NP) {
+                    const int l = idx / HALF;
+                    const int k = idx - l * HALF;
+                    c32 *line = buf + l * LP;
+                    c32 xk = line[lpad(k)], xm = line[lpad(M - k)];
+                    if (k == 0) {
+                        xk.y = 0.f;
+                        xm.y = 0.f;
+                    }
+                    const c32 s1 = add(xk, conjg(xm));
+                    const c32 d1 = mul(conjg(twp[k]), sub(xk, conjg(xm)));
+                    const c32 zk = c32{s1.x - d1.y, s1.y + d1.x};
+                    if (k != 0 && 2 * k != M) {
+                        const c32 s2 = add(xm, conjg(xk));
+                        const c32 d2 = mul(conjg(twp[M - k]), sub(xm, conjg(xk)));
+                        line[lpad(M - k)] = c32{s2.x - d2.y, s2.y + d2.x};
+                    }
+                    line[lpad(k)] = zk;
+                }
+            }
+            __syncthreads();
+            row_fft<M, +1, RB, 1, LP, NT, false, true>(buf, nullptr, (c32 *)a.out, nullptr, ob, nv,
+                                                       tw, tid);
         }
-        __syncthreads();
-        row_fft<M, +1, RB, 1, LP, NT, false, true>(buf, nullptr, (c32 *)a.out, nullptr, ob, nv, tw,
-                                                   tid);
         __syncthreads();
     }
 };
@@ -399,8 +450,8 @@ struct XC2RV {
 // ---- c2c with NC interleaved components, register-direct both ends
 template <int L, int NC, int S, int NT>
 struct XC2CV {
-    static constexpr int RB = x_rb(L, NC, NT);
-    static constexpr size_t O_BUF = 0, O_TW = al16(O_BUF + sizeof(c32) * RB * NC * L),
+    static constexpr int RB = x_rb(L, NC, NT), LP = row_pitch(L);
+    static constexpr size_t O_BUF = 0, O_TW = al16(O_BUF + sizeof(c32) * RB * NC * LP),
                             O_IB = al16(O_TW + sizeof(c32) * L), O_OB = O_IB + 8 * RB,
                             BYTES = al16(O_OB + 8 * RB);
     static __device__ void tables(const XArgs &a, char *sm, int tid)
@@ -416,8 +467,8 @@ struct XC2CV {
         row_bases<RB, NT>(ib, ob, a, r0, tid);
         __syncthreads();
         const int nv = rows_valid<RB>(a, r0);
-        row_fft<L, S, RB, NC, L, NT, true, true>(buf, (const c32 *)a.in, (c32 *)a.out, ib, ob, nv,
-                                                 tw, tid);
+        row_fft<L, S, RB, NC, LP, NT, true, true>(buf, (const c32 *)a.in, (c32 *)a.out, ib, ob,
+                                                  nv, tw, tid);
         __syncthreads();
     }
 };

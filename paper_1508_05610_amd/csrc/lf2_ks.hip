@@ -59,10 +59,10 @@ static hipError_t launch_wide(int len, int sign, const SArgs &a, int grid_cap, h
 }
 
 hipError_t launch_strided(int len, int sign, const SArgs &a_in, int grid_cap, hipStream_t s,
-                          int *grid_used, int variant)
+                          int *grid_used, int variant, int chunk)
 {
-    // 16 tiles per XCD chunk; the grid is a multiple of 8 (grid_cap is).
-    constexpr int kChunk = 16;
+    // `chunk` tiles per XCD chunk; the grid is a multiple of 8 (grid_cap is).
+    const int kChunk = chunk > 0 ? chunk : 16;
     SArgs a = a_in;
     a.xcd_chunk = kChunk;
     grid_cap = grid_cap / 8 * 8;

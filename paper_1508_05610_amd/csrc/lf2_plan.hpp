@@ -34,7 +34,8 @@ struct lf2_plan_s {
     int64_t ntot = 0;  // N0 N1 N2
     int len[3] = {0, 0, 0};
     int svar[3] = {0, 0, 0};              // strided tile variant per axis (1, 2)
-    double tune_us[3][2] = {{-1, -1}, {-1, -1}, {-1, -1}};
+    int schunk[3] = {16, 16, 16};         // tiles per XCD chunk per axis
+    double tune_us[3][2] = {{-1, -1}, {-1, -1}, {-1, -1}};  // [axis][default, tuned]
     void *tw[3] = {nullptr, nullptr, nullptr};
     void *tw_post = nullptr;
     int64_t *q[3] = {nullptr, nullptr, nullptr};

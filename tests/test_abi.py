@@ -74,8 +74,8 @@ def test_variant_calls_validate(lib):
     so = lib.load()
     import ctypes
     v = ctypes.c_int32()
-    assert so.lf2_plan_get_variant(None, 1, ctypes.byref(v), None, None) == lib.LF2_ERR_INVALID_ARG
-    assert so.lf2_plan_set_variant(None, 2, 1) == lib.LF2_ERR_INVALID_ARG
+    assert so.lf2_plan_get_tuning(None, 1, ctypes.byref(v), None, None, None) == lib.LF2_ERR_INVALID_ARG
+    assert so.lf2_plan_set_tuning(None, 2, 1, 16) == lib.LF2_ERR_INVALID_ARG
 
 
 def test_unknown_plan_flag(lib):

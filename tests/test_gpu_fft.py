@@ -181,8 +181,8 @@ def test_wide_tiles_match_oracle_and_narrow(lf2, shape, kind, ncomp):
     pw = lf2.Plan(shape, kind, ncomp=ncomp)
     for axis in (1, 2):
         if shape[axis] >= 256:
-            pw.set_variant(axis, 1)
-            assert pw.variant(axis)[0] == 1
+            pw.set_tuning(axis, 1, chunk=4 if axis == 1 else 64)
+            assert pw.tuning(axis)[:2] == (1, 4 if axis == 1 else 64)
     if kind == lf2.LF2_R2C:
         f = real_field(shape, seed=11)[0][..., 0]
         x = torch.from_numpy(f).to(dev())
@@ -208,17 +208,17 @@ def test_wide_tiles_match_oracle_and_narrow(lf2, shape, kind, ncomp):
     assert rel_l2(bw.cpu().numpy(), bn.cpu().numpy()) <= 1e-6
 
 
-def test_autotune_picks_a_variant(lf2):
+def test_autotune_picks_a_setting(lf2):
     shape = (64, 256, 512)
     print(f"case autotune {shape}", flush=True)
     p = lf2.Plan(shape, lf2.LF2_R2C, autotune=True)
     for axis in (1, 2):
-        v, un, uw = p.variant(axis)
-        print(f"  axis {axis}: variant {v} narrow {un:.1f} us wide {uw:.1f} us", flush=True)
-        assert v in (0, 1) and un > 0 and uw > 0
-        assert v == (1 if uw < un else 0)
+        v, c, ud, ut = p.tuning(axis)
+        print(f"  axis {axis}: variant {v} chunk {c} default {ud:.1f} us tuned {ut:.1f} us", flush=True)
+        assert v in (0, 1) and c in (4, 16, 64) and 0 < ut <= ud
     q = lf2.Plan((64, 48, 40), lf2.LF2_R2C, autotune=True)
-    assert q.variant(1) == (0, -1.0, -1.0)   # no wide tiles for these lengths
+    v, c, ud, ut = q.tuning(1)
+    assert v == 0 and 0 < ut <= ud        # narrow tiles only for these lengths
     f = real_field(shape, seed=13)[0][..., 0]
     F = p.forward(torch.from_numpy(f).to(dev()))
     torch.cuda.synchronize()
