@@ -513,11 +513,23 @@ template <int L, int S, bool EPI, int NT>
 struct STile {
     static constexpr int B = s_b(L);
     static constexpr int RPT = NT / B;  // row groups in the epilogue
+    // EPI tiles also keep the last axis' k^2 and q tables in LDS (read once
+    // per mode in the epilogue)
     static constexpr size_t O_BUF = 0, O_TW = al16(sizeof(c32) * L * B),
-                            BYTES = al16(O_TW + sizeof(c32) * L);
+                            O_K2Z = al16(O_TW + sizeof(c32) * L),
+                            O_QZ = O_K2Z + (EPI ? 8 * L : 0),
+                            BYTES = al16(O_QZ + (EPI ? 8 * L : 0));
     static __device__ void tables(const SArgs &a, char *sm, int tid)
     {
         load_table((c32 *)(sm + O_TW), a.tw, L, tid, NT);
+        if constexpr (EPI) {
+            double *k2z = (double *)(sm + O_K2Z);
+            int64_t *qz = (int64_t *)(sm + O_QZ);
+            for (int i = tid; i < L; i += NT) {
+                if (a.epi & EPI_POISSON) k2z[i] = a.mt.k2[2][i];
+                if (a.epi & (EPI_PK | EPI_PK_AFTER)) qz[i] = a.mt.q[2][i];
+            }
+        }
     }
     static __device__ void tile(const SArgs &a, int64_t t, char *sm, int tid, double *hist,
                                 const int64_t *thresh)
@@ -565,7 +577,7 @@ struct STile {
                 if (pk && !zero) {
                     // consecutive kz move q a little: walk the thresholds from
                     // the previous bin instead of a fresh estimate
-                    const int64_t q = qxy + a.mt.q[2][kz];
+                    const int64_t q = qxy + ((const int64_t *)(sm + O_QZ))[kz];
                     b = bprev < 0 ? bin_of(q, thresh, nb, inv_qmax) : bin_step(q, bprev, thresh, nb);
                     bprev = b;
                 }
@@ -579,7 +591,8 @@ struct STile {
                     acc += p;
                 }
                 if (a.epi & EPI_POISSON) {
-                    const double sc = zero ? 0.0 : -a.mt.scale_n * rcp_f64(k2xy + a.mt.k2[2][kz]);
+                    const double sc =
+                        zero ? 0.0 : -a.mt.scale_n * rcp_f64(k2xy + ((const double *)(sm + O_K2Z))[kz]);
                     v = c32{(float)((double)v.x * sc), (float)((double)v.y * sc)};
                     buf[kz * B + col] = v;
                 }
