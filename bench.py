@@ -45,18 +45,41 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kernel: str):
+def tuning_spec(tuning: dict) -> str:
+    """The --tuning string of a plan_tuning table."""
+    return ";".join(
+        nm + ":" + ",".join(f"{a}={t[f'axis{i}']['variant']}/{t[f'axis{i}']['chunk']}"
+                            for i, a in ((1, "y"), (2, "z")))
+        for nm, t in tuning.items())
+
+
+def measured_traffic(kernel: str, tuning: str):
     """HBM bytes per launch of `kernel` from the committed PMC summary, if it
-    was taken on the current kernel sources; else None."""
+    was taken on the current kernel sources with the same pass tuning (which
+    decides the mix of launches a kernel symbol covers); else None."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
         t = json.load(f)
-    if t.get("source_hash") != kernel_source_hash():
+    if t.get("source_hash") != kernel_source_hash() or t.get("tuning") != tuning:
         return None
     k = t.get("kernels", {}).get(kernel)
     return None if k is None else k.get("hbm_bytes_per_launch")
+
+
+def parse_tuning(spec: str) -> dict:
+    """'r2c:y=0/16,z=1/4;c2c3:y=1/16,z=1/64' -> {'r2c': {1: (0, 16), 2: (1, 4)}, ...}"""
+    out = {}
+    for part in spec.split(";"):
+        nm, rest = part.split(":")
+        d = {}
+        for item in rest.split(","):
+            ax, vc = item.split("=")
+            v, c = vc.split("/")
+            d[{"y": 1, "z": 2}[ax]] = (int(v), int(c))
+        out[nm] = d
+    return out
 
 
 def bench_batch(args, torch, np, lf2, stream):
@@ -300,6 +323,9 @@ def main():
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=1000)
+    ap.add_argument("--tuning", default=None,
+                    help="fixed strided-pass tuning instead of autotuning, e.g. "
+                         "'r2c:y=0/16,z=0/16;c2c3:y=1/16,z=1/64' (variant/chunk)")
     ap.add_argument("--only", default=None,
                     help="time one op alone (r2c_fwd, c2r_bwd, c2c_fwd_3comp, c2c_bwd_3comp, "
                          "poisson_pk, copy) for profiler runs")
@@ -332,9 +358,16 @@ def main():
     z = torch.from_numpy(z3).to(dev).view(torch.complex64).reshape(S, S, S, 3)
     del z3
 
-    # plans autotuned at creation (tile variant per strided axis; untimed)
-    pr = lf2.Plan(n, lf2.LF2_R2C, autotune=True)
-    pc = lf2.Plan(n, lf2.LF2_C2C, ncomp=3, autotune=True)
+    # plans autotuned at creation (tile variant and XCD chunk per strided
+    # axis; untimed), or set from --tuning (profiler runs, where counters
+    # distort the tuner's timings)
+    fixed = parse_tuning(args.tuning) if args.tuning else None
+    pr = lf2.Plan(n, lf2.LF2_R2C, autotune=fixed is None)
+    pc = lf2.Plan(n, lf2.LF2_C2C, ncomp=3, autotune=fixed is None)
+    if fixed:
+        for nm, p_ in (("r2c", pr), ("c2c3", pc)):
+            for ax, (v, c) in fixed.get(nm, {}).items():
+                p_.set_tuning(ax, v, c)
     tuning = {nm: {f"axis{ax}": dict(zip(("variant", "chunk", "us_default", "us_tuned"),
                                          p_.tuning(ax)))
                    for ax in (1, 2)} for nm, p_ in (("r2c", pr), ("c2c3", pc))}
@@ -444,7 +477,7 @@ def main():
     dom = max(by_symbol.items(), key=lambda kv: kv[1][1])
     dname, (dn, dms, dbytes) = dom
     achieved = (dbytes / dn) / (dms / dn * 1e-3) / 1e9
-    traffic = measured_traffic(dname)
+    traffic = measured_traffic(dname, tuning_spec(tuning))
     kernels = {k: {"launches": v[0], "avg_us": 1e3 * v[1] / v[0],
                    "alg_bytes_per_launch": v[2] / v[0],
                    "gbps": (v[2] / v[0]) / (v[1] / v[0] * 1e-3) / 1e9} for k, v in table.items()}
