@@ -311,6 +311,80 @@ def bench_serving(args, torch, np, lf2):
     }
 
 
+def bench_paper_shapes(args, torch, lf2):
+    """The paper's FFT benchmark shapes (section 4.1) on one GPU: 512^3 and
+    1024^3 with 1, 2, 3 and 6 components, r2c forward / c2r backward and c2c
+    forward / backward, plus 2048^3 with one component.  Absolute times and
+    algorithmic HBM GB/s (one pass per axis) instead of the paper's parallel
+    efficiency; the round trip backward(forward(x)) / N - x is the check (it
+    holds at any size).  Inputs: torch N(0,1) on the device, seed 7."""
+    import math
+    from paper_1508_05610_amd import _lib
+    dev = torch.device("cuda:0")
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(7)
+    rows = []
+    cases = [(n, nc) for n in (512, 1024) for nc in (1, 2, 3, 6)] + [(2048, 1)]
+    for n, nc in cases:
+        for kind in (lf2.LF2_R2C, lf2.LF2_C2C):
+            if n == 2048 and kind == lf2.LF2_C2C:
+                continue
+            N = n ** 3
+            p = lf2.Plan((n, n, n), kind, ncomp=nc, autotune=True)
+            comp = (nc,) if nc > 1 else ()
+            if kind == lf2.LF2_R2C:
+                x = torch.randn((n, n, n) + comp, generator=gen, device=dev, dtype=torch.float32)
+                bpp = nc * (4.0 + 5 * 8.0 * (n // 2 + 1) / n)   # bytes per point, 3 passes
+            else:
+                x = torch.randn((n, n, n) + comp + (2,), generator=gen, device=dev,
+                                dtype=torch.float32).view(torch.complex64).reshape((n, n, n) + comp)
+                bpp = nc * 48.0
+            F = p.forward(x)
+            back = p.backward(F)
+            torch.cuda.synchronize()
+            err = float(torch.linalg.vector_norm((back / N - x).flatten()) /
+                        torch.linalg.vector_norm(x.flatten()))
+
+            def timed(fn, reps=3):
+                fn()
+                a = torch.cuda.Event(enable_timing=True)
+                b = torch.cuda.Event(enable_timing=True)
+                torch.cuda.synchronize()
+                a.record()
+                for _ in range(reps):
+                    fn()
+                b.record()
+                torch.cuda.synchronize()
+                return a.elapsed_time(b) / reps
+
+            passes = {}
+            for d, fn in (("fwd", lambda: p.forward(x, out=F)), ("bwd", lambda: p.backward(F, out=back))):
+                fn()
+                torch.cuda.synchronize()
+                _lib.lf2_profile_reset()
+                _lib.lf2_profile_enable(True)
+                fn()
+                torch.cuda.synchronize()
+                passes[d] = {k: round(1e3 * ms / c, 1) for k, (c, ms, _) in _lib.profile_table().items()}
+                _lib.lf2_profile_enable(False)
+            tf = timed(lambda: p.forward(x, out=F))
+            tb = timed(lambda: p.backward(F, out=back))
+            for d, t in (("fwd", tf), ("bwd", tb)):
+                gbs = bpp * N / (t * 1e-3) / 1e9
+                rows.append({"n": n, "ncomp": nc, "kind": "r2c" if kind == lf2.LF2_R2C else "c2c",
+                             "dir": d, "ms": round(t, 3), "gbps": round(gbs, 1),
+                             "frac": round(gbs / HBM_PEAK_GBS, 4),
+                             "gflops": round(5.0 * N * math.log2(N) * nc / (t * 1e-3) / 1e9, 1),
+                             "round_trip_rel_l2": err, "passes_us": passes[d],
+                             "tuning": [p.tuning(1)[:2], p.tuning(2)[:2]]})
+            print(f"paper shape {n}^3 x{nc} {'r2c' if kind == 0 else 'c2c'}: fwd {tf:.3f} ms "
+                  f"bwd {tb:.3f} ms round trip {err:.2e}", file=sys.stderr, flush=True)
+            p.close()
+            del x, F, back
+            torch.cuda.empty_cache()
+    return rows
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -322,6 +396,9 @@ def main():
     ap.add_argument("--no-errors", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--paper-shapes", action="store_true",
+                    help="also time the paper's FFT benchmark shapes (512^3 and 1024^3 x 1/2/3/6 "
+                         "components, 2048^3 x 1)")
     ap.add_argument("--serve-requests", type=int, default=1000)
     ap.add_argument("--tuning", default=None,
                     help="fixed strided-pass tuning instead of autotuning, e.g. "
@@ -530,6 +607,8 @@ def main():
         res["batch"] = bench_batch(args, torch, np, lf2, stream)
     if not args.no_serve:
         res["serving"] = bench_serving(args, torch, np, lf2)
+    if args.paper_shapes:
+        res["paper_shapes"] = bench_paper_shapes(args, torch, lf2)
 
     # ---- CPU baseline: the FP64 oracle on the host cores, bounded sample
     errors = {}

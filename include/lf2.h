@@ -97,7 +97,8 @@ typedef struct lf2_plan_s *lf2_plan;
  * Create a plan for a 3-D transform on `lat` with `ncomp` components
  * (PlanFFT, section 3.6).  Extents must factor into 2, 3 and 5 with at
  * most one factor 3 or 5 per extent (LF2_ERR_UNSUPPORTED otherwise); r2c
- * needs an even N0.  The plan is bound to the current HIP device; its
+ * needs an even N0.  Compiled line lengths: 1..1024 along x (N0/2 for
+ * r2c), 1..2048 along y and z; ncomp 1, 2, 3 or 6.  The plan is bound to the current HIP device; its
  * twiddles (generated in FP64 on the device, rounded once to FP32) stay
  * resident until lf2_plan_destroy.  Synchronises the device once.
  */
@@ -117,7 +118,7 @@ lf2_status lf2_fft_kspace(lf2_plan p, int64_t ksize[3], int64_t kstride[3]);
  * Tuning of the strided pass along `axis` (1 = y, 2 = z) for plain
  * transforms.  variant 0 = narrow tiles (all lengths); 1 = wide tiles
  * (twice the columns per tile, one 1024-thread block per CU; lengths 256,
- * 320, 384, 512, 640, 768, 1024).  chunk = consecutive tiles given to one
+ * 320, 384, 512, 640, 768, 1024, 2048).  chunk = consecutive tiles given to one
  * XCD in the tile order (1..1024, default 16).  Every setting computes the
  * same transform bit for bit.  The fused Poisson / power-spectrum pass
  * always uses narrow tiles and chunk 16.  get reports the setting and,

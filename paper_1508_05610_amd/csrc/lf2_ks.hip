@@ -8,7 +8,7 @@ bool s_supported(int len)
 {
     switch (len) {
 #define LF2_CASE(L) case L:
-        LF2_LENGTHS(LF2_CASE)
+        LF2_S_LENGTHS(LF2_CASE)
 #undef LF2_CASE
         return true;
     default:
@@ -20,7 +20,7 @@ int s_cols_per_block(int len) { return s_b(len); }
 
 // Lengths with a wide (split-exchange) tile: the long lines, whose narrow
 // tiles read the shortest row segments.
-#define LF2_WIDE_LENGTHS(X) X(256) X(320) X(384) X(512) X(640) X(768) X(1024)
+#define LF2_WIDE_LENGTHS(X) X(256) X(320) X(384) X(512) X(640) X(768) X(1024) X(2048)
 
 bool s_wide_supported(int len)
 {
@@ -91,7 +91,7 @@ hipError_t launch_strided(int len, int sign, const SArgs &a_in, int grid_cap, hi
         return hipGetLastError();                                                            \
     }
     switch (len) {
-        LF2_LENGTHS(LF2_CASE)
+        LF2_S_LENGTHS(LF2_CASE)
     default:
         return hipErrorInvalidValue;
     }

@@ -28,7 +28,7 @@ static inline bool pairs_aligned(const void *p, int64_t off, int64_t row, int64_
 #if LF2_KX_PART == 0
 bool x_supported(int len, int nc)
 {
-    if (nc != 1 && nc != 3) return false;
+    if (nc != 1 && nc != 2 && nc != 3 && nc != 6) return false;
     switch (len) {
 #define LF2_CASE(L) case L:
         LF2_LENGTHS(LF2_CASE)
@@ -41,6 +41,13 @@ bool x_supported(int len, int nc)
 
 int x_rows_per_block(int len, int nc) { return x_rb(len, nc); }
 
+template <int L, int NC>
+static void r2c_nc(const XArgs &a, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_x_r2c<L, NC>), dim3(x_grid(a.nrows, x_rb(L, NC))), dim3(kXThreads), 0, s,
+                       a);
+}
+
 hipError_t launch_x_r2c(int m, int nc, const XArgs &a, hipStream_t s)
 {
     const bool vec = nc == 1 && pairs_aligned(a.in, a.in_off, a.in_row, a.in_plane);
@@ -50,11 +57,15 @@ hipError_t launch_x_r2c(int m, int nc, const XArgs &a, hipStream_t s)
             hipLaunchKernelGGL((k_x_r2c_v<L>), dim3(x_grid(a.nrows, x_rb(L, 1))),            \
                                dim3(kXThreads), 0, s, a);                                    \
         else if (nc == 1)                                                                    \
-            hipLaunchKernelGGL((k_x_r2c<L, 1>), dim3(x_grid(a.nrows, x_rb(L, 1))),           \
-                               dim3(kXThreads), 0, s, a);                                    \
+            r2c_nc<L, 1>(a, s);                                                              \
+        else if (nc == 2)                                                                    \
+            r2c_nc<L, 2>(a, s);                                                              \
+        else if (nc == 3)                                                                    \
+            r2c_nc<L, 3>(a, s);                                                              \
+        else if (nc == 6)                                                                    \
+            r2c_nc<L, 6>(a, s);                                                              \
         else                                                                                 \
-            hipLaunchKernelGGL((k_x_r2c<L, 3>), dim3(x_grid(a.nrows, x_rb(L, 3))),           \
-                               dim3(kXThreads), 0, s, a);                                    \
+            return hipErrorInvalidValue;                                                     \
         return hipGetLastError();
     switch (m) {
         LF2_LENGTHS(LF2_CASE)
@@ -66,6 +77,13 @@ hipError_t launch_x_r2c(int m, int nc, const XArgs &a, hipStream_t s)
 #endif
 
 #if LF2_KX_PART == 1
+template <int L, int NC>
+static void c2r_nc(const XArgs &a, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_x_c2r<L, NC>), dim3(x_grid(a.nrows, x_rb(L, NC))), dim3(kXThreads), 0, s,
+                       a);
+}
+
 hipError_t launch_x_c2r(int m, int nc, const XArgs &a, hipStream_t s)
 {
     const bool vec = nc == 1 && pairs_aligned(a.out, a.out_off, a.out_row, a.out_plane);
@@ -75,11 +93,15 @@ hipError_t launch_x_c2r(int m, int nc, const XArgs &a, hipStream_t s)
             hipLaunchKernelGGL((k_x_c2r_v<L>), dim3(x_grid(a.nrows, x_rb(L, 1))),            \
                                dim3(kXThreads), 0, s, a);                                    \
         else if (nc == 1)                                                                    \
-            hipLaunchKernelGGL((k_x_c2r<L, 1>), dim3(x_grid(a.nrows, x_rb(L, 1))),           \
-                               dim3(kXThreads), 0, s, a);                                    \
+            c2r_nc<L, 1>(a, s);                                                              \
+        else if (nc == 2)                                                                    \
+            c2r_nc<L, 2>(a, s);                                                              \
+        else if (nc == 3)                                                                    \
+            c2r_nc<L, 3>(a, s);                                                              \
+        else if (nc == 6)                                                                    \
+            c2r_nc<L, 6>(a, s);                                                              \
         else                                                                                 \
-            hipLaunchKernelGGL((k_x_c2r<L, 3>), dim3(x_grid(a.nrows, x_rb(L, 3))),           \
-                               dim3(kXThreads), 0, s, a);                                    \
+            return hipErrorInvalidValue;                                                     \
         return hipGetLastError();
     switch (m) {
         LF2_LENGTHS(LF2_CASE)
@@ -91,25 +113,31 @@ hipError_t launch_x_c2r(int m, int nc, const XArgs &a, hipStream_t s)
 #endif
 
 #if LF2_KX_PART == 2
+template <int L, int NC>
+static void c2c_nc(int sign, const XArgs &a, hipStream_t s)
+{
+    if (sign < 0)
+        hipLaunchKernelGGL((k_x_c2c_v<L, NC, -1>), dim3(x_grid(a.nrows, x_rb(L, NC))),
+                           dim3(kXThreads), 0, s, a);
+    else
+        hipLaunchKernelGGL((k_x_c2c_v<L, NC, 1>), dim3(x_grid(a.nrows, x_rb(L, NC))),
+                           dim3(kXThreads), 0, s, a);
+}
+
 hipError_t launch_x_c2c(int len, int nc, int sign, const XArgs &a, hipStream_t s)
 {
 #define LF2_CASE(L)                                                                          \
     case L:                                                                                  \
-        if (nc == 1) {                                                                       \
-            if (sign < 0)                                                                    \
-                hipLaunchKernelGGL((k_x_c2c_v<L, 1, -1>), dim3(x_grid(a.nrows, x_rb(L, 1))),    \
-                                   dim3(kXThreads), 0, s, a);                                \
-            else                                                                             \
-                hipLaunchKernelGGL((k_x_c2c_v<L, 1, 1>), dim3(x_grid(a.nrows, x_rb(L, 1))),     \
-                                   dim3(kXThreads), 0, s, a);                                \
-        } else {                                                                             \
-            if (sign < 0)                                                                    \
-                hipLaunchKernelGGL((k_x_c2c_v<L, 3, -1>), dim3(x_grid(a.nrows, x_rb(L, 3))),   \
-                                   dim3(kXThreads), 0, s, a);                                \
-            else                                                                             \
-                hipLaunchKernelGGL((k_x_c2c_v<L, 3, 1>), dim3(x_grid(a.nrows, x_rb(L, 3))),    \
-                                   dim3(kXThreads), 0, s, a);                                \
-        }                                                                                    \
+        if (nc == 1)                                                                         \
+            c2c_nc<L, 1>(sign, a, s);                                                        \
+        else if (nc == 2)                                                                    \
+            c2c_nc<L, 2>(sign, a, s);                                                        \
+        else if (nc == 3)                                                                    \
+            c2c_nc<L, 3>(sign, a, s);                                                        \
+        else if (nc == 6)                                                                    \
+            c2c_nc<L, 6>(sign, a, s);                                                        \
+        else                                                                                 \
+            return hipErrorInvalidValue;                                                     \
         return hipGetLastError();
     switch (len) {
         LF2_LENGTHS(LF2_CASE)

@@ -45,7 +45,7 @@ def test_version_and_status_strings(lib):
     ((14, 32, 32), 0, 1, 0, 3, -2),          # prime factor 7
     ((15, 32, 32), 0, 1, 1, 3, -2),          # both 3 and 5 in one extent
     ((31, 32, 32), 0, 1, 0, 3, -2),          # odd N0 for r2c
-    ((32, 32, 32), 0, 2, 0, 3, -2),          # two components: no kernel in this build
+    ((32, 32, 32), 0, 4, 0, 3, -2),          # four components: no kernel in this build
     ((32, 32, 32), 0, 1, 7, 3, -1),          # bad kind
     ((4096, 32, 32), 0, 1, 1, 3, -2),        # line longer than the compiled kernels
 ])

@@ -92,6 +92,18 @@ C2C_SHAPES = [(32, 32, 32), (8, 8, 8), (12, 10, 6), (64, 48, 40), (3, 5, 4), (16
 @pytest.mark.parametrize("ncomp", [1, 3])
 @pytest.mark.parametrize("direction", [-1, 1])
 def test_c2c(lf2, shape, ncomp, direction):
+    _c2c_case(lf2, shape, ncomp, direction)
+
+
+# the paper's FFT benchmark component counts (section 4.1): 1, 2, 3 and 6
+@pytest.mark.parametrize("shape", [(32, 24, 16), (64, 8, 12), (1024, 4, 2), (6, 10, 512)])
+@pytest.mark.parametrize("ncomp", [2, 6])
+@pytest.mark.parametrize("direction", [-1, 1])
+def test_c2c_paper_components(lf2, shape, ncomp, direction):
+    _c2c_case(lf2, shape, ncomp, direction)
+
+
+def _c2c_case(lf2, shape, ncomp, direction):
     print(f"case c2c {shape} ncomp={ncomp} dir={direction}", flush=True)
     z = complex_field(shape, seed=4, ncomp=ncomp)
     plan = lf2.Plan(shape, lf2.LF2_C2C, ncomp=ncomp)
@@ -171,7 +183,8 @@ def test_round_trip(lf2):
 # lines of 256..1024 points along y or z take either tile variant
 WIDE_CASES = [((16, 256, 384), 0, 1), ((32, 64, 512), 0, 1), ((8, 24, 1024), 0, 1),
               ((40, 320, 96), 0, 1), ((12, 96, 768), 0, 1), ((6, 640, 16), 0, 1),
-              ((16, 512, 256), 1, 3), ((10, 16, 512), 1, 1)]
+              ((16, 512, 256), 1, 3), ((10, 16, 512), 1, 1), ((4, 2048, 8), 0, 1),
+              ((8, 6, 2048), 1, 2)]
 
 
 @pytest.mark.parametrize("shape,kind,ncomp", WIDE_CASES)
@@ -223,3 +236,25 @@ def test_autotune_picks_a_setting(lf2):
     F = p.forward(torch.from_numpy(f).to(dev()))
     torch.cuda.synchronize()
     assert rel_l2(F.cpu().numpy(), oracle.r2c(f.astype(np.float64))) <= tol(shape)
+
+
+@pytest.mark.parametrize("shape", [(32, 24, 16), (48, 10, 6), (512, 4, 4), (2048, 2, 2)])
+@pytest.mark.parametrize("ncomp", [2, 3, 6])
+def test_r2c_c2r_components(lf2, shape, ncomp):
+    """AoS real fields with several components: r2c and c2r per component."""
+    print(f"case r2c/c2r {shape} ncomp={ncomp}", flush=True)
+    dense, _ = real_field(shape, seed=14, ncomp=ncomp)
+    plan = lf2.Plan(shape, lf2.LF2_R2C, ncomp=ncomp)
+    F = plan.forward(torch.from_numpy(dense).to(dev()))
+    back = plan.backward(F)
+    torch.cuda.synchronize()
+    Fg = F.cpu().numpy()
+    bg = back.cpu().numpy()
+    for c in range(ncomp):
+        f64 = dense[..., c].astype(np.float64)
+        ref = oracle.r2c(f64)
+        e = rel_l2(Fg[..., c], ref)
+        report(f"r2c comp{c}", shape, e, rel_max(Fg[..., c], ref))
+        assert e <= tol(shape)
+        refb = oracle.c2r(Fg[..., c].astype(np.complex128), shape[0])
+        assert rel_l2(bg[..., c], refb) <= tol(shape)
