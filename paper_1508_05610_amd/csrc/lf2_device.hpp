@@ -204,68 +204,6 @@ __host__ __device__ constexpr int max_radix(int L, int st = 0)
                                                                       : max_radix(L, st + 1));
 }
 
-// ---------------------------------------------------------------- stage engine
-// Geometry of a group of lines in LDS.  LF (line-fast) selects the mapping of
-// butterfly index b to (line, j): LF = true -> line = b % NL (lines
-// interleaved, PS = NL, LS = 1); LF = false -> j = b % (L/R) (contiguous
-// lines, PS = 1).
-
-template <int L, int R, int NS, int S, int NL, int NT, bool LF>
-__device__ __forceinline__ void stockham_stage(c32 *buf, int nlines, int LS, int PS,
-                                               const c32 *tw, int tid)
-{
-    constexpr int Q = L / R;
-    constexpr int NBF = NL * Q;                 // butterflies if all lines are used
-    constexpr int NB = (NBF + NT - 1) / NT;     // per thread
-    const int nbf = nlines * Q;
-    c32 v[NB][R];
-#pragma unroll
-    for (int i = 0; i < NB; ++i) {
-        const int b = tid + i * NT;
-        if (b < nbf) {
-            const int l = LF ? (b % NL) : (b / Q);
-            const int j = LF ? (b / NL) : (b % Q);
-            const c32 *src = buf + l * LS + j * PS;
-#pragma unroll
-            for (int r = 0; r < R; ++r) v[i][r] = src[r * Q * PS];
-        }
-    }
-    __syncthreads();
-#pragma unroll
-    for (int i = 0; i < NB; ++i) {
-        const int b = tid + i * NT;
-        if (b < nbf) {
-            const int l = LF ? (b % NL) : (b / Q);
-            const int j = LF ? (b / NL) : (b % Q);
-            const int k = j % NS;
-            if (NS > 1) {
-#pragma unroll
-                for (int r = 1; r < R; ++r) {
-                    c32 w = tw[r * k * (L / (NS * R))];
-                    if (S > 0) w = conjg(w);
-                    v[i][r] = mul(v[i][r], w);
-                }
-            }
-            Dft<R, S>::run(v[i]);
-            c32 *dst = buf + l * LS + ((j / NS) * NS * R + k) * PS;
-#pragma unroll
-            for (int r = 0; r < R; ++r) dst[r * NS * PS] = v[i][r];
-        }
-    }
-    __syncthreads();
-}
-
-template <int L, int S, int NL, int NT, bool LF, int ST = 0, int NS = 1>
-__device__ __forceinline__ void stockham(c32 *buf, int nlines, int LS, int PS, const c32 *tw,
-                                         int tid)
-{
-    if constexpr (NS < L) {
-        constexpr int R = radix_at(L, ST);
-        stockham_stage<L, R, NS, S, NL, NT, LF>(buf, nlines, LS, PS, tw, tid);
-        stockham<L, S, NL, NT, LF, ST + 1, NS * R>(buf, nlines, LS, PS, tw, tid);
-    }
-}
-
 // ------------------------------------------------------------ column engine
 // NL interleaved lines (columns of a strided pass), element (line l, point p)
 // at buf[l + p * NL].  NT is a multiple of NL, so thread tid always works on

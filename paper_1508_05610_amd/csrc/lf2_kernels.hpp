@@ -92,10 +92,12 @@ __device__ __forceinline__ void load_table(c32 *dst, const void *src, int n, int
 
 // =================================================================== x tiles
 
-// ---- general r2c: components de-interleaved through LDS
+// ---- general r2c: components de-interleaved through LDS (padded lines of
+// the row engine; complex point n of a line holds reals 2n and 2n + 1)
 template <int M, int NC, int NT>
 struct XR2CGen {
-    static constexpr int RB = x_rb(M, NC, NT), NL = RB * NC, N0 = 2 * M, LP = M, NH = M + 1;
+    static constexpr int RB = x_rb(M, NC, NT), NL = RB * NC, N0 = 2 * M, LP = row_pitch(M),
+                         NH = M + 1;
     static constexpr size_t O_BUF = 0, O_TW = al16(O_BUF + sizeof(c32) * NL * LP),
                             O_TWP = al16(O_TW + sizeof(c32) * M),
                             O_IB = al16(O_TWP + sizeof(c32) * NH), O_OB = O_IB + 8 * RB,
@@ -128,13 +130,14 @@ struct XR2CGen {
                 const int c = rem - x * NC;
                 float v = 0.f;
                 if (r0 + row < a.nrows) v = in[ib[row] + rem];
-                fb[(row * NC + c) * LP * 2 + x] = v;
+                fb[2 * ((row * NC + c) * LP + lpad(x >> 1)) + (x & 1)] = v;
                 ss += (double)v * (double)v;
             }
         }
         if (sumsq) block_sum_f64<NT>(ss, sumsq, (double *)(sm + O_RED));
         __syncthreads();
-        stockham<M, -1, NL, NT, false>(buf, NL, LP, 1, tw, tid);
+        row_fft<M, -1, RB, NC, LP, NT, false, false>(buf, nullptr, nullptr, nullptr, nullptr, RB,
+                                                     tw, tid);
         c32 *out = (c32 *)a.out;
         constexpr int NO = RB * NH * NC;
 #pragma unroll
@@ -147,8 +150,8 @@ struct XR2CGen {
                 const int c = rem - k * NC;
                 if (r0 + row < a.nrows) {
                     const c32 *line = buf + (row * NC + c) * LP;
-                    const c32 z = line[k == M ? 0 : k];
-                    const c32 zc = conjg(line[k == 0 ? 0 : M - k]);
+                    const c32 z = line[lpad(k == M ? 0 : k)];
+                    const c32 zc = conjg(line[lpad(k == 0 ? 0 : M - k)]);
                     const c32 fe = scl(add(z, zc), 0.5f);
                     const c32 d = sub(z, zc);
                     const c32 fo = c32{0.5f * d.y, -0.5f * d.x};  // (z - zc) / (2i)
@@ -163,7 +166,8 @@ struct XR2CGen {
 // ---- general c2r
 template <int M, int NC, int NT>
 struct XC2RGen {
-    static constexpr int RB = x_rb(M, NC, NT), NL = RB * NC, N0 = 2 * M, LP = M + 1, NH = M + 1;
+    static constexpr int RB = x_rb(M, NC, NT), NL = RB * NC, N0 = 2 * M, LP = row_pitch(M + 1),
+                         NH = M + 1;
     static constexpr size_t O_BUF = 0, O_TW = al16(O_BUF + sizeof(c32) * NL * LP),
                             O_TWP = al16(O_TW + sizeof(c32) * M),
                             O_IB = al16(O_TWP + sizeof(c32) * NH), O_OB = O_IB + 8 * RB,
@@ -193,7 +197,7 @@ struct XC2RGen {
                 const int c = rem - k * NC;
                 c32 v = c32{0.f, 0.f};
                 if (r0 + row < a.nrows) v = in[ib[row] + rem];
-                buf[(row * NC + c) * LP + k] = v;
+                buf[(row * NC + c) * LP + lpad(k)] = v;
             }
         }
         __syncthreads();
@@ -209,8 +213,8 @@ struct XC2RGen {
                 const int l = idx / M;
                 const int k = idx - l * M;
                 const c32 *line = buf + l * LP;
-                c32 xk = line[k];
-                c32 xm = line[M - k];
+                c32 xk = line[lpad(k)];
+                c32 xm = line[lpad(M - k)];
                 if (k == 0) {
                     xk.y = 0.f;
                     xm.y = 0.f;
@@ -228,11 +232,12 @@ struct XC2RGen {
             if (idx < NZ) {
                 const int l = idx / M;
                 const int k = idx - l * M;
-                buf[l * LP + k] = zv[i];
+                buf[l * LP + lpad(k)] = zv[i];
             }
         }
         __syncthreads();
-        stockham<M, +1, NL, NT, false>(buf, NL, LP, 1, tw, tid);
+        row_fft<M, +1, RB, NC, LP, NT, false, false>(buf, nullptr, nullptr, nullptr, nullptr, RB,
+                                                     tw, tid);
         float *out = (float *)a.out;
         const float *fb = (const float *)buf;
         constexpr int NE = RB * N0 * NC;
@@ -244,7 +249,8 @@ struct XC2RGen {
                 const int rem = idx - row * (N0 * NC);
                 const int x = rem / NC;
                 const int c = rem - x * NC;
-                if (r0 + row < a.nrows) out[ob[row] + rem] = fb[(row * NC + c) * LP * 2 + x];
+                if (r0 + row < a.nrows)
+                    out[ob[row] + rem] = fb[2 * ((row * NC + c) * LP + lpad(x >> 1)) + (x & 1)];
             }
         }
         __syncthreads();
