@@ -311,6 +311,49 @@ def bench_serving(args, torch, np, lf2):
     }
 
 
+def bench_field_ops(args, torch, lf2):
+    """The paper's field-operation benchmark (section 4.2) on one GPU: the
+    periodic halo update and the first-order derivative of all components
+    of a 512^3 3-component FP32 field with halo 1 into a 9-component field.
+    Algorithmic bytes: the halo sites' words read and written once; the
+    derivative reads the field once and writes the output once (16 bytes per
+    site and component).  Input: torch N(0,1) on the device, seed 8."""
+    dev = torch.device("cuda:0")
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(8)
+    n, h, nc = 512, 1, 3
+    p = n + 2 * h
+    f = torch.randn((p, p, p, nc), generator=gen, device=dev, dtype=torch.float32)
+    out = torch.zeros((p, p, p, 3 * nc), device=dev, dtype=torch.float32)
+    sizes = (n, n, n)
+
+    def timed(fn, reps):
+        fn()
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        a.record()
+        for _ in range(reps):
+            fn()
+        b.record()
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / reps
+
+    reps = max(5, args.steps)
+    th = timed(lambda: lf2.update_halo(f, sizes, h), reps)
+    tg = timed(lambda: lf2.gradient(f, sizes, h, out=out), reps)
+    halo_sites = p ** 3 - n ** 3
+    hb = 2.0 * halo_sites * nc * 4
+    gb = 16.0 * nc * n ** 3
+    del f, out
+    torch.cuda.empty_cache()
+    return {"workload": f"{n}^3 FP32 x {nc} components, halo {h}: halo update + forward "
+                        "derivative of every component along x, y, z",
+            "update_halo_ms": round(th, 4), "update_halo_gbps": round(hb / (th * 1e-3) / 1e9, 1),
+            "gradient_ms": round(tg, 4), "gradient_gbps": round(gb / (tg * 1e-3) / 1e9, 1),
+            "gradient_frac": round(gb / (tg * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+
+
 def bench_paper_shapes(args, torch, lf2):
     """The paper's FFT benchmark shapes (section 4.1) on one GPU: 512^3 and
     1024^3 with 1, 2, 3 and 6 components, r2c forward / c2r backward and c2c
@@ -396,6 +439,7 @@ def main():
     ap.add_argument("--no-errors", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--no-field-ops", action="store_true")
     ap.add_argument("--paper-shapes", action="store_true",
                     help="also time the paper's FFT benchmark shapes (512^3 and 1024^3 x 1/2/3/6 "
                          "components, 2048^3 x 1)")
@@ -607,6 +651,8 @@ def main():
         res["batch"] = bench_batch(args, torch, np, lf2, stream)
     if not args.no_serve:
         res["serving"] = bench_serving(args, torch, np, lf2)
+    if not args.no_field_ops:
+        res["field_ops"] = bench_field_ops(args, torch, lf2)
     if args.paper_shapes:
         res["paper_shapes"] = bench_paper_shapes(args, torch, lf2)
 

@@ -322,6 +322,28 @@ lf2_status lf2_server_destroy(lf2_server s);
 double lf2_server_now(void);
 
 /*
+ * Field operations (the paper's second benchmark, section 4.2; halo cells,
+ * section 3.3.1).  A field is float[N2+2h][N1+2h][N0+2h][ncomp] (complex
+ * fields: elem_bytes = 8), dimension 0 fastest, components innermost, on
+ * the current device; all calls are asynchronous on `stream`.
+ *
+ * lf2_update_halo: periodic halo update of a field on one GPU: every halo
+ * site takes the value of the interior site at its coordinates modulo the
+ * lattice extents (faces, edges and corners).  h = 0 is a no-op; h larger
+ * than an extent is LF2_ERR_UNSUPPORTED.  elem_bytes is 4 or 8.
+ *
+ * lf2_gradient: first-order forward derivative of every component along x,
+ * y and z into another field with the same halo width and 3 * ncomp
+ * components: out(x)[3 c + i] = (in(x + e_i) - in(x))[c] / dx.  Reads the
+ * input's halo (h >= 1; update it first); writes the output's interior only.
+ * in and out must not alias.
+ */
+lf2_status lf2_update_halo(const lf2_lattice *lat, int32_t ncomp, int32_t elem_bytes, void *field,
+                           void *stream);
+lf2_status lf2_gradient(const lf2_lattice *lat, int32_t ncomp, const float *in, float *out,
+                        double dx, void *stream);
+
+/*
  * Kernel timing (tracing).  While enabled, every kernel launch made by the
  * calls above is bracketed by two HIP events recorded on the launch's
  * stream and tagged with the kernel's name and its algorithmic HBM bytes

@@ -29,7 +29,7 @@ __all__ = ["Plan", "Batch", "LF2Error", "LF2_R2C", "LF2_C2C", "LF2_FORWARD", "LF
            "lf2_power_spectrum", "lf2_plan_destroy", "lf2_plan_workspace_bytes",
            "lf2_plan_set_workspace", "lf2_batch_plan", "lf2_batch_execute", "lf2_batch_error",
            "lf2_batch_info", "lf2_batch_destroy", "lf2_version", "load", "Server",
-           "latency_percentiles"]
+           "latency_percentiles", "update_halo", "gradient"]
 
 
 def load():
@@ -295,3 +295,41 @@ def latency_percentiles(values, qs=(50, 99)):
             raise ValueError("percentile must be in (0, 100]")
         out.append(v[max(1, math.ceil(q * len(v) / 100.0)) - 1])
     return tuple(out)
+
+
+def update_halo(field, sizes, halo, stream=None):
+    """Periodic halo update of a (N2+2h, N1+2h, N0+2h[, ncomp]) float32 or
+    complex64 tensor in place (lf2_update_halo)."""
+    import torch
+    n0, n1, n2 = (int(v) for v in sizes)
+    h = int(halo)
+    if not isinstance(field, torch.Tensor) or not field.is_cuda or not field.is_contiguous():
+        raise TypeError("field must be a contiguous CUDA (HIP) tensor")
+    if tuple(field.shape[:3]) != (n2 + 2 * h, n1 + 2 * h, n0 + 2 * h):
+        raise ValueError("field shape does not match the lattice")
+    if field.dtype not in (torch.float32, torch.complex64):
+        raise TypeError("field must be float32 or complex64")
+    ncomp = int(field[0, 0, 0].numel())
+    eb = 4 if field.dtype == torch.float32 else 8
+    _lib.lf2_update_halo((n0, n1, n2), h, ncomp, eb, field.data_ptr(), _stream_handle(stream))
+    return field
+
+
+def gradient(field, sizes, halo, dx=1.0, out=None, stream=None):
+    """First-order forward derivative of every component (lf2_gradient): a
+    (N2+2h, N1+2h, N0+2h, 3 ncomp) float32 tensor whose interior is written."""
+    import torch
+    n0, n1, n2 = (int(v) for v in sizes)
+    h = int(halo)
+    if field.dtype != torch.float32 or not field.is_cuda or not field.is_contiguous():
+        raise TypeError("field must be a contiguous float32 CUDA (HIP) tensor")
+    if tuple(field.shape[:3]) != (n2 + 2 * h, n1 + 2 * h, n0 + 2 * h):
+        raise ValueError("field shape does not match the lattice")
+    ncomp = int(field[0, 0, 0].numel())
+    shape = (n2 + 2 * h, n1 + 2 * h, n0 + 2 * h, 3 * ncomp)
+    if out is None:
+        out = torch.zeros(shape, dtype=torch.float32, device=field.device)
+    _ptr(out, "out", torch.float32, shape)
+    _lib.lf2_gradient((n0, n1, n2), h, ncomp, field.data_ptr(), out.data_ptr(), dx,
+                      _stream_handle(stream))
+    return out

@@ -99,6 +99,8 @@ _SIGS = {
     "lf2_server_get_stats": (_i32, [_vp, ctypes.POINTER(lf2_server_stats)]),
     "lf2_server_destroy": (_i32, [_vp]),
     "lf2_server_now": (_f64, []),
+    "lf2_update_halo": (_i32, [ctypes.POINTER(lf2_lattice), _i32, _i32, _vp, _vp]),
+    "lf2_gradient": (_i32, [ctypes.POINTER(lf2_lattice), _i32, _vp, _vp, _f64, _vp]),
     "lf2_profile_enable": (_i32, [_i32]),
     "lf2_profile_reset": (_i32, []),
     "lf2_profile_count": (_i32, []),
@@ -350,6 +352,20 @@ def lf2_server_destroy(server: int):
 
 def lf2_server_now() -> float:
     return float(load().lf2_server_now())
+
+
+def lf2_update_halo(sizes, halo: int, ncomp: int, elem_bytes: int, field_ptr: int,
+                    stream: int = 0):
+    lat = lf2_lattice(3, int(halo), (ctypes.c_int64 * 3)(*[int(v) for v in sizes]))
+    _check(load().lf2_update_halo(ctypes.byref(lat), int(ncomp), int(elem_bytes),
+                                  field_ptr or None, stream or None), "lf2_update_halo")
+
+
+def lf2_gradient(sizes, halo: int, ncomp: int, in_ptr: int, out_ptr: int, dx: float = 1.0,
+                 stream: int = 0):
+    lat = lf2_lattice(3, int(halo), (ctypes.c_int64 * 3)(*[int(v) for v in sizes]))
+    _check(load().lf2_gradient(ctypes.byref(lat), int(ncomp), in_ptr or None, out_ptr or None,
+                               float(dx), stream or None), "lf2_gradient")
 
 
 def lf2_profile_enable(on: bool = True):

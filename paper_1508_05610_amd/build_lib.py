@@ -40,6 +40,8 @@ UNITS = [
     ("lf2_api.cpp", ["-x", "hip"], "api.o"),
     ("lf2_batch.cpp", ["-x", "hip"], "batch.o"),
     ("lf2_server.cpp", ["-x", "hip"], "server.o"),
+    ("lf2_kfield.hip", [], "kfield.o"),
+    ("lf2_field.cpp", ["-x", "hip"], "field.o"),
 ]
 
 

@@ -72,6 +72,12 @@ hipError_t launch_strided(int len, int sign, const SArgs &a, int grid_cap, hipSt
                           int *grid_used, int variant = 0, int chunk = 16);
 bool s_wide_supported(int len);
 
+// Field operations (lf2_kfield.hip).
+hipError_t launch_update_halo(void *field, const int64_t n[3], int64_t h, int64_t site_words,
+                              hipStream_t s);
+hipError_t launch_gradient(const float *in, float *out, const int64_t n[3], int64_t h, int nc,
+                           double dx, hipStream_t s);
+
 // Setup and reduction kernels (FP64).
 hipError_t launch_twiddles(void *tw, int len, hipStream_t s);
 hipError_t launch_k2_table(double *dst, int n, int count, double dx, int discrete, hipStream_t s);

@@ -81,3 +81,18 @@ def test_variant_calls_validate(lib):
 def test_unknown_plan_flag(lib):
     st = lib.lf2_fft_plan_status((32, 32, 32), 0, 1, 0, flags=0x20)
     assert st == lib.LF2_ERR_UNSUPPORTED
+
+
+def test_field_ops_validate(lib):
+    import ctypes
+    so = lib.load()
+    lat = lib.lf2_lattice(3, 1, (ctypes.c_int64 * 3)(8, 8, 8))
+    assert so.lf2_update_halo(ctypes.byref(lat), 1, 4, None, None) == lib.LF2_ERR_INVALID_ARG
+    assert so.lf2_update_halo(ctypes.byref(lat), 1, 2, 256, None) == lib.LF2_ERR_UNSUPPORTED
+    assert so.lf2_update_halo(None, 1, 4, 256, None) == lib.LF2_ERR_INVALID_ARG
+    assert so.lf2_gradient(ctypes.byref(lat), 1, 256, 256, 1.0, None) == lib.LF2_ERR_INVALID_ARG
+    assert so.lf2_gradient(ctypes.byref(lat), 1, 256, 512, 0.0, None) == lib.LF2_ERR_INVALID_ARG
+    lat0 = lib.lf2_lattice(3, 0, (ctypes.c_int64 * 3)(8, 8, 8))
+    assert so.lf2_gradient(ctypes.byref(lat0), 1, 256, 512, 1.0, None) == lib.LF2_ERR_INVALID_ARG
+    wide = lib.lf2_lattice(3, 9, (ctypes.c_int64 * 3)(8, 8, 8))
+    assert so.lf2_update_halo(ctypes.byref(wide), 1, 4, 256, None) == lib.LF2_ERR_UNSUPPORTED
