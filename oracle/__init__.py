@@ -200,3 +200,18 @@ def grf(shape3, alpha, u):
     scale = _load().orc_grf(_dims(shape3).ctypes.data, float(alpha), u.ctypes.data,
                             out.ctypes.data)
     return out, float(scale)
+
+
+def to_paper_layout(F, kind):
+    """A natural spectrum (C shape (N2, N1, Nk[, ncomp]), k_x fastest) in the
+    k-space order of the paper's distributed transform (section 3.6): for
+    r2c the dimensions run (k_x, k_z, k_y), k_x fastest -> C shape
+    (N1, N2, Nh); for c2c (k_z, k_x, k_y), k_z fastest -> C shape
+    (N1, N0, N2).  A trailing component axis stays innermost."""
+    F = np.asarray(F)
+    rest = tuple(range(3, F.ndim))
+    if kind == "r2c":
+        return np.ascontiguousarray(np.transpose(F, (1, 0, 2) + rest))
+    if kind == "c2c":
+        return np.ascontiguousarray(np.transpose(F, (1, 2, 0) + rest))
+    raise ValueError(kind)
