@@ -59,12 +59,17 @@ def _ptr(t, what, dtype, shape):
 class Plan:
     """A PlanFFT (paper section 3.6) on an N0 x N1 x N2 lattice with halo h."""
 
-    def __init__(self, sizes, kind=LF2_R2C, ncomp=1, halo=0, autotune=False):
+    def __init__(self, sizes, kind=LF2_R2C, ncomp=1, halo=0, autotune=False, in_place=False,
+                 paper_layout=False):
         self.sizes = tuple(int(s) for s in sizes)
         self.kind = kind
         self.ncomp = int(ncomp)
         self.halo = int(halo)
-        flags = _lib.LF2_PLAN_AUTOTUNE if autotune else 0
+        self.in_place = bool(in_place)
+        self.paper_layout = bool(paper_layout)
+        flags = ((_lib.LF2_PLAN_AUTOTUNE if autotune else 0) |
+                 (_lib.LF2_IN_PLACE if in_place else 0) |
+                 (_lib.LF2_KLAYOUT_PAPER if paper_layout else 0))
         self.handle = lf2_fft_plan(self.sizes, self.halo, self.ncomp, kind, flags)
         self.ksize, self.kstride = lf2_fft_kspace(self.handle)
 
@@ -92,12 +97,19 @@ class Plan:
 
     @property
     def x_shape(self):
+        """Real-space array shape; in-place r2c rows are padded to 2 (N0/2 + 1)."""
         n0, n1, n2 = self.sizes
         h = self.halo
+        if self.in_place and self.kind == LF2_R2C:
+            return (n2, n1, 2 * (n0 // 2 + 1)) + self._comp()
         return (n2 + 2 * h, n1 + 2 * h, n0 + 2 * h) + self._comp()
 
     @property
     def k_shape(self):
+        """Spectrum array shape: natural (N2, N1, Nk) or, with paper_layout
+        (r2c), the paper's (N1, N2, Nh)."""
+        if self.paper_layout:
+            return (self.ksize[1], self.ksize[2], self.ksize[0]) + self._comp()
         return (self.ksize[2], self.ksize[1], self.ksize[0]) + self._comp()
 
     # transforms -------------------------------------------------------------
@@ -110,6 +122,31 @@ class Plan:
         op = _ptr(out, "out", torch.complex64, self.k_shape)
         lf2_fft_execute(self.handle, LF2_FORWARD, xp, op, _stream_handle(stream))
         return out
+
+    def forward_(self, x, stream=None):
+        """In-place forward (plan made with in_place=True): x is overwritten by
+        its spectrum; returns the spectrum as a complex64 view of x's memory."""
+        import torch
+        if not self.in_place:
+            raise ValueError("plan was not made with in_place=True")
+        xdt = torch.float32 if self.kind == LF2_R2C else torch.complex64
+        xp = _ptr(x, "x", xdt, self.x_shape)
+        lf2_fft_execute(self.handle, LF2_FORWARD, xp, xp, _stream_handle(stream))
+        if self.kind == LF2_R2C:  # each padded real row holds one spectrum row
+            return x.reshape(x.shape[0], x.shape[1], -1).view(torch.complex64).reshape(self.k_shape)
+        return x.reshape(self.k_shape)
+
+    def backward_(self, k, stream=None):
+        """In-place backward: k is overwritten by the real (or complex) field;
+        returns it as a view of k's memory with x_shape."""
+        import torch
+        if not self.in_place:
+            raise ValueError("plan was not made with in_place=True")
+        kp = _ptr(k, "k", torch.complex64, self.k_shape)
+        lf2_fft_execute(self.handle, LF2_BACKWARD, kp, kp, _stream_handle(stream))
+        if self.kind == LF2_R2C:
+            return k.reshape(k.shape[0], k.shape[1], -1).view(torch.float32).reshape(self.x_shape)
+        return k.reshape(self.x_shape)
 
     def backward(self, k, out=None, stream=None):
         import torch

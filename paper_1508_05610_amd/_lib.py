@@ -28,6 +28,8 @@ LF2_FORWARD = -1
 LF2_BACKWARD = 1
 
 LF2_PLAN_AUTOTUNE = 0x10
+LF2_IN_PLACE = 0x1
+LF2_KLAYOUT_PAPER = 0x2
 LF2_POISSON_CONTINUOUS_K2 = 0
 LF2_POISSON_DISCRETE_K2 = 1
 LF2_PK_OF_PHI = 2

@@ -362,9 +362,13 @@ XArgs x_args(const lf2_plan_s *p, const void *in, void *out, bool in_is_x, bool 
     a.nrows = p->n[1] * p->n[2];
     a.n1 = (int)p->n[1];
     const int64_t h = p->halo, nc = p->nc;
-    const int64_t xrow = (p->n[0] + 2 * h) * nc, xplane = (p->n[1] + 2 * h) * xrow;
+    // in-place r2c: real rows padded to the spectrum row's 2 Nh floats
+    const int64_t xrow = (p->inplace && p->kind == LF2_R2C) ? 2 * p->nh * nc : (p->n[0] + 2 * h) * nc;
+    const int64_t xplane = (p->n[1] + 2 * h) * xrow;
     const int64_t xoff = h * nc + h * xrow + h * xplane;
-    const int64_t krow = p->nxk * nc, kplane = p->n[1] * krow;
+    // k-space rows: natural [N2][N1][Nk]; the paper's r2c order [N1][N2][Nh]
+    const int64_t C1 = p->nxk * nc;
+    const int64_t krow = p->klay ? p->n[2] * C1 : C1, kplane = p->klay ? C1 : p->n[1] * C1;
     (void)real_x;
     if (in_is_x) {
         a.in_off = xoff;
@@ -396,7 +400,19 @@ SArgs s_args(const lf2_plan_s *p, int axis, const void *in, void *out, int epi)
     a.in = in;
     a.out = out;
     const int64_t C1 = p->nxk * p->nc;
-    if (axis == 1) {
+    if (p->klay) {  // r2c in the paper's order [N1][N2][Nh]
+        if (axis == 1) {  // y is the slowest dimension; every (k_x, z) column is contiguous
+            a.stride = p->n[2] * C1;
+            a.ncols_inner = p->n[2] * C1;
+            a.outer = 0;
+            a.ncols = p->n[2] * C1;
+        } else {  // z jumps a row; columns (k_x, y): column f at (f / C1) N2 C1 + f mod C1
+            a.stride = C1;
+            a.ncols_inner = C1;
+            a.outer = p->n[2] * C1;
+            a.ncols = p->n[1] * C1;
+        }
+    } else if (axis == 1) {
         a.stride = C1;
         a.ncols_inner = C1;
         a.outer = p->n[1] * C1;
@@ -638,7 +654,12 @@ lf2_status lf2_fft_plan(lf2_plan *out, const lf2_lattice *lat, int32_t ncomp, lf
     if (lat->halo < 0) return fail(LF2_ERR_INVALID_ARG, "halo %d < 0", lat->halo);
     if (kind != LF2_R2C && kind != LF2_C2C) return fail(LF2_ERR_INVALID_ARG, "bad kind %d", (int)kind);
     if (ncomp < 1) return fail(LF2_ERR_INVALID_ARG, "ncomp %d < 1", ncomp);
-    if (flags & ~LF2_PLAN_AUTOTUNE) return fail(LF2_ERR_UNSUPPORTED, "plan flags 0x%x not supported", flags);
+    if (flags & ~(LF2_PLAN_AUTOTUNE | LF2_IN_PLACE | LF2_KLAYOUT_PAPER))
+        return fail(LF2_ERR_UNSUPPORTED, "plan flags 0x%x not supported", flags);
+    if ((flags & LF2_IN_PLACE) && lat->halo != 0)
+        return fail(LF2_ERR_UNSUPPORTED, "in-place transforms need halo 0");
+    if ((flags & LF2_KLAYOUT_PAPER) && kind == LF2_C2C)
+        return fail(LF2_ERR_UNSUPPORTED, "the paper's c2c k-space order is not built");
     for (int i = 0; i < 3; ++i) {
         if (lat->size[i] < 1) return fail(LF2_ERR_INVALID_ARG, "size[%d] = %lld < 1", i, (long long)lat->size[i]);
         if (lat->size[i] > (1 << 20)) return fail(LF2_ERR_UNSUPPORTED, "size[%d] too large", i);
@@ -667,6 +688,8 @@ lf2_status lf2_fft_plan(lf2_plan *out, const lf2_lattice *lat, int32_t ncomp, lf
     p->nc = ncomp;
     p->halo = lat->halo;
     p->flags = flags;
+    p->inplace = (flags & LF2_IN_PLACE) != 0;
+    p->klay = (flags & LF2_KLAYOUT_PAPER) ? 1 : 0;
     for (int i = 0; i < 3; ++i) {
         p->n[i] = lat->size[i];
         p->len[i] = lens[i];
@@ -758,8 +781,8 @@ lf2_status lf2_fft_kspace(lf2_plan p, int64_t ksize[3], int64_t kstride[3])
     }
     if (kstride) {
         kstride[0] = p->nc;
-        kstride[1] = p->nc * p->nxk;
-        kstride[2] = p->nc * p->nxk * p->n[1];
+        kstride[1] = p->klay ? p->nc * p->nxk * p->n[2] : p->nc * p->nxk;
+        kstride[2] = p->klay ? p->nc * p->nxk : p->nc * p->nxk * p->n[1];
     }
     return LF2_OK;
 }
@@ -787,7 +810,8 @@ lf2_status lf2_fft_execute(lf2_plan p, lf2_direction dir, const void *in, void *
     if (dir != LF2_FORWARD && dir != LF2_BACKWARD) return fail(LF2_ERR_INVALID_ARG, "bad direction %d", (int)dir);
     lf2_status st;
     if ((st = check_ptr(in, "in", 8)) || (st = check_ptr(out, "out", 8))) return st;
-    if (in == out) return fail(LF2_ERR_UNSUPPORTED, "in-place transforms are not supported (in == out)");
+    if (in == out && !p->inplace)
+        return fail(LF2_ERR_UNSUPPORTED, "in == out needs a plan made with LF2_IN_PLACE");
     if ((st = check_device(p))) return st;
     hipStream_t s = (hipStream_t)stream;
     if (p->kind == LF2_R2C && dir == LF2_FORWARD) {
@@ -848,7 +872,8 @@ lf2_status poisson_impl(lf2_plan p, const float *rho, float *phi, double dx, uin
         return fail(LF2_ERR_UNSUPPORTED, "Poisson needs an r2c plan with ncomp = 1");
     lf2_status st;
     if ((st = check_ptr(rho, "rho", 4)) || (st = check_ptr(phi, "phi", 4))) return st;
-    if ((const void *)rho == (const void *)phi) return fail(LF2_ERR_INVALID_ARG, "rho and phi must not alias");
+    if ((const void *)rho == (const void *)phi && !p->inplace)
+        return fail(LF2_ERR_INVALID_ARG, "rho and phi alias: needs a plan made with LF2_IN_PLACE");
     if (!(dx > 0.0) || !std::isfinite(dx)) return fail(LF2_ERR_INVALID_ARG, "dx must be > 0");
     if (flags & ~(uint32_t)(LF2_POISSON_DISCRETE_K2 | LF2_PK_OF_PHI))
         return fail(LF2_ERR_INVALID_ARG, "unknown Poisson flags 0x%x", flags);
@@ -947,7 +972,10 @@ lf2_status lf2_power_spectrum(lf2_plan p, const void *field, int32_t field_is_ks
         mt.nbins = nbins;
         grid = kPkGrid;
         const int t = prof::begin("k_pk_kspace", (double)spectrum_bytes(p), s);
-        hipError_t e = launch_pk_kspace(field, (int)p->n[1], (int)p->n[2], mt, part, grid, s);
+        int64_t kst[3];
+        (void)lf2_fft_kspace(p, nullptr, kst);
+        hipError_t e = launch_pk_kspace(field, (int)p->n[1], (int)p->n[2], kst[1], kst[2], mt, part,
+                                        grid, s);
         prof::end(t, s);
         LF2_HIP(e);
     } else {

@@ -89,8 +89,8 @@ hipError_t launch_shell_partials(const ModeTables &mt, int n1, int n2, double ls
 // out[b] = sum_g partial[g * width + b] in a fixed order, b < width.
 hipError_t launch_reduce_cols(const double *partial, int64_t grid, int width, double *out,
                               hipStream_t s);
-hipError_t launch_pk_kspace(const void *F, int n1, int n2, const ModeTables &mt,
-                            double *partial, int grid, hipStream_t s);
+hipError_t launch_pk_kspace(const void *F, int n1, int n2, int64_t sy, int64_t sz,
+                            const ModeTables &mt, double *partial, int grid, hipStream_t s);
 hipError_t launch_pk_finalize(const double *S, int nbins, const double *count, const double *sumk,
                               double norm, double vscale, double kscale, double *pk,
                               double *kmean, double *count_out, double *parseval,

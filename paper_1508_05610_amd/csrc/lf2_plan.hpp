@@ -28,6 +28,8 @@ struct lf2_plan_s {
     int nc = 1;
     int halo = 0;
     uint32_t flags = 0;
+    bool inplace = false;   // LF2_IN_PLACE
+    int klay = 0;           // 0 natural k-space order, 1 the paper's (LF2_KLAYOUT_PAPER)
     int64_t n[3] = {0, 0, 0};
     int64_t nh = 0;    // N0/2 + 1
     int64_t nxk = 0;   // k-space extent of dimension 0
