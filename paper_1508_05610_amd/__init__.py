@@ -106,10 +106,12 @@ class Plan:
 
     @property
     def k_shape(self):
-        """Spectrum array shape: natural (N2, N1, Nk) or, with paper_layout
-        (r2c), the paper's (N1, N2, Nh)."""
-        if self.paper_layout:
+        """Spectrum array shape: natural (N2, N1, Nk) or, with paper_layout,
+        the paper's order: r2c (N1, N2, Nh), c2c (N1, N0, N2)."""
+        if self.paper_layout and self.kind == LF2_R2C:
             return (self.ksize[1], self.ksize[2], self.ksize[0]) + self._comp()
+        if self.paper_layout:
+            return (self.ksize[1], self.ksize[0], self.ksize[2]) + self._comp()
         return (self.ksize[2], self.ksize[1], self.ksize[0]) + self._comp()
 
     # transforms -------------------------------------------------------------

@@ -368,7 +368,7 @@ XArgs x_args(const lf2_plan_s *p, const void *in, void *out, bool in_is_x, bool 
     const int64_t xoff = h * nc + h * xrow + h * xplane;
     // k-space rows: natural [N2][N1][Nk]; the paper's r2c order [N1][N2][Nh]
     const int64_t C1 = p->nxk * nc;
-    const int64_t krow = p->klay ? p->n[2] * C1 : C1, kplane = p->klay ? C1 : p->n[1] * C1;
+    const int64_t krow = p->klay == 1 ? p->n[2] * C1 : C1, kplane = p->klay == 1 ? C1 : p->n[1] * C1;
     (void)real_x;
     if (in_is_x) {
         a.in_off = xoff;
@@ -400,7 +400,7 @@ SArgs s_args(const lf2_plan_s *p, int axis, const void *in, void *out, int epi)
     a.in = in;
     a.out = out;
     const int64_t C1 = p->nxk * p->nc;
-    if (p->klay) {  // r2c in the paper's order [N1][N2][Nh]
+    if (p->klay == 1) {  // r2c in the paper's order [N1][N2][Nh]
         if (axis == 1) {  // y is the slowest dimension; every (k_x, z) column is contiguous
             a.stride = p->n[2] * C1;
             a.ncols_inner = p->n[2] * C1;
@@ -430,15 +430,27 @@ SArgs s_args(const lf2_plan_s *p, int axis, const void *in, void *out, int epi)
     return a;
 }
 
+// z pass between the natural order and the paper's c2c order
+SArgs t_args(const lf2_plan_s *p, const void *in, void *out, int epi)
+{
+    SArgs a = s_args(p, 2, in, out, epi);
+    a.t_n0 = p->n[0];
+    a.t_n2 = p->n[2];
+    a.t_nc = p->nc;
+    return a;
+}
+
 lf2_status run_strided(const lf2_plan_s *p, int axis, int sign, const SArgs &a, int grid_cap,
                        hipStream_t s, int *grid_used)
 {
     const double sb = (double)spectrum_bytes(p);
     const bool epi = (a.epi & (EPI_PK | EPI_PK_AFTER | EPI_POISSON)) != 0;
-    const int variant = epi ? 0 : p->svar[axis];
+    const bool tr = (a.epi & (EPI_TSTORE | EPI_TLOAD)) != 0;
+    const int variant = tr ? 2 : epi ? 0 : p->svar[axis];
     // "<kernel symbol> <pass>": the symbol part matches the profiler's name
-    const std::string sym = variant ? kname("k_strided_w<%d,%d>", p->len[axis], sign)
-                                    : kname("k_strided<%d,%d,%d>", p->len[axis], sign, epi ? 1 : 0);
+    const std::string sym = variant == 2   ? kname("k_strided_t<%d,%d>", p->len[axis], sign)
+                            : variant == 1 ? kname("k_strided_w<%d,%d>", p->len[axis], sign)
+                                           : kname("k_strided<%d,%d,%d>", p->len[axis], sign, epi ? 1 : 0);
     const int t = prof::begin(sym + kname(" %s%s%s %lldx%lldx%lld/%d", axis == 1 ? "y" : "z",
                                     (a.epi & EPI_POISSON) ? "+poisson" : "",
                                     (a.epi & (EPI_PK | EPI_PK_AFTER)) ? "+pk" : "",
@@ -658,8 +670,6 @@ lf2_status lf2_fft_plan(lf2_plan *out, const lf2_lattice *lat, int32_t ncomp, lf
         return fail(LF2_ERR_UNSUPPORTED, "plan flags 0x%x not supported", flags);
     if ((flags & LF2_IN_PLACE) && lat->halo != 0)
         return fail(LF2_ERR_UNSUPPORTED, "in-place transforms need halo 0");
-    if ((flags & LF2_KLAYOUT_PAPER) && kind == LF2_C2C)
-        return fail(LF2_ERR_UNSUPPORTED, "the paper's c2c k-space order is not built");
     for (int i = 0; i < 3; ++i) {
         if (lat->size[i] < 1) return fail(LF2_ERR_INVALID_ARG, "size[%d] = %lld < 1", i, (long long)lat->size[i]);
         if (lat->size[i] > (1 << 20)) return fail(LF2_ERR_UNSUPPORTED, "size[%d] too large", i);
@@ -689,7 +699,7 @@ lf2_status lf2_fft_plan(lf2_plan *out, const lf2_lattice *lat, int32_t ncomp, lf
     p->halo = lat->halo;
     p->flags = flags;
     p->inplace = (flags & LF2_IN_PLACE) != 0;
-    p->klay = (flags & LF2_KLAYOUT_PAPER) ? 1 : 0;
+    p->klay = (flags & LF2_KLAYOUT_PAPER) ? (kind == LF2_R2C ? 1 : 2) : 0;
     for (int i = 0; i < 3; ++i) {
         p->n[i] = lat->size[i];
         p->len[i] = lens[i];
@@ -781,8 +791,14 @@ lf2_status lf2_fft_kspace(lf2_plan p, int64_t ksize[3], int64_t kstride[3])
     }
     if (kstride) {
         kstride[0] = p->nc;
-        kstride[1] = p->klay ? p->nc * p->nxk * p->n[2] : p->nc * p->nxk;
-        kstride[2] = p->klay ? p->nc * p->nxk : p->nc * p->nxk * p->n[1];
+        if (p->klay == 2) {  // c2c (k_z, k_x, k_y): [N1][N0][N2]
+            kstride[0] = p->nc * p->n[2];
+            kstride[1] = p->nc * p->n[2] * p->n[0];
+            kstride[2] = p->nc;
+        } else {
+            kstride[1] = p->klay == 1 ? p->nc * p->nxk * p->n[2] : p->nc * p->nxk;
+            kstride[2] = p->klay == 1 ? p->nc * p->nxk : p->nc * p->nxk * p->n[1];
+        }
     }
     return LF2_OK;
 }
@@ -830,6 +846,22 @@ lf2_status lf2_fft_execute(lf2_plan p, lf2_direction dir, const void *in, void *
     }
     // c2c
     const int sg = (int)dir;
+    if (p->klay == 2) {
+        // the paper's (k_z, k_x, k_y) order: natural passes in the workspace,
+        // the z pass stores (forward) or loads (backward) transposed
+        WsLayout L = ws_layout(p, true, 0, false);
+        char *ws;
+        if ((st = get_workspace(p, L.total, &ws))) return st;
+        void *W = ws + L.w;
+        if (dir == LF2_FORWARD) {
+            if ((st = run_x(p, 2, sg, x_args(p, in, W, true, false, false), s))) return st;
+            if ((st = run_strided(p, 1, sg, s_args(p, 1, W, W, EPI_STORE), kStridedGridCap, s, nullptr))) return st;
+            return run_strided(p, 2, sg, t_args(p, W, out, EPI_STORE | EPI_TSTORE), kStridedGridCap, s, nullptr);
+        }
+        if ((st = run_strided(p, 2, sg, t_args(p, in, W, EPI_STORE | EPI_TLOAD), kStridedGridCap, s, nullptr))) return st;
+        if ((st = run_strided(p, 1, sg, s_args(p, 1, W, W, EPI_STORE), kStridedGridCap, s, nullptr))) return st;
+        return run_x(p, 2, sg, x_args(p, W, out, false, true, false), s);
+    }
     if (dir == LF2_FORWARD) {
         if ((st = run_x(p, 2, sg, x_args(p, in, out, true, false, false), s))) return st;
         if ((st = run_strided(p, 1, sg, s_args(p, 1, out, out, EPI_STORE), kStridedGridCap, s, nullptr))) return st;
@@ -974,8 +1006,8 @@ lf2_status lf2_power_spectrum(lf2_plan p, const void *field, int32_t field_is_ks
         const int t = prof::begin("k_pk_kspace", (double)spectrum_bytes(p), s);
         int64_t kst[3];
         (void)lf2_fft_kspace(p, nullptr, kst);
-        hipError_t e = launch_pk_kspace(field, (int)p->n[1], (int)p->n[2], kst[1], kst[2], mt, part,
-                                        grid, s);
+        hipError_t e = launch_pk_kspace(field, (int)p->n[1], (int)p->n[2], kst[0], kst[1], kst[2], mt,
+                                        part, grid, s);
         prof::end(t, s);
         LF2_HIP(e);
     } else {

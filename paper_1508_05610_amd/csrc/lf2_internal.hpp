@@ -13,7 +13,9 @@ enum : int {
     EPI_STORE = 1,    // write the transformed column back
     EPI_PK = 2,       // accumulate w|F|^2 per bin after the forward transform
     EPI_POISSON = 4,  // scale by -1/(N k^2) (FP64) and run the backward transform
-    EPI_PK_AFTER = 8  // accumulate after the Poisson scale instead (spectrum of phi)
+    EPI_PK_AFTER = 8, // accumulate after the Poisson scale instead (spectrum of phi)
+    EPI_TSTORE = 16,  // store in the c2c (k_z, k_x, k_y) order (k_strided_t)
+    EPI_TLOAD = 32    // load from the c2c (k_z, k_x, k_y) order (k_strided_t)
 };
 
 // Description of mode (kx, ky, kz) -> tables, for the fused epilogues.
@@ -56,6 +58,9 @@ struct SArgs {
     const void *tw;      // twiddles, length L
     ModeTables mt;
     double *partial;     // [gridDim.x][nbins + 1]
+    // the transposed side of k_strided_t: column f = (y, x, c) of the
+    // natural order, point z, sits at ((y n0 + x) n2 + z) nc + c
+    int64_t t_n0, t_n2, t_nc;
 };
 
 // Kernel launchers (return hipSuccess or the launch error).  `len` is the
@@ -66,7 +71,8 @@ hipError_t launch_x_r2c(int m, int nc, const XArgs &a, hipStream_t s);
 hipError_t launch_x_c2r(int m, int nc, const XArgs &a, hipStream_t s);
 hipError_t launch_x_c2c(int len, int nc, int sign, const XArgs &a, hipStream_t s);
 // variant 0: STile (narrow, any pass); 1: STileW (wide, plain passes of
-// s_wide_supported lengths).  chunk: consecutive tiles per XCD in the tile
+// s_wide_supported lengths); 2: STileT (z pass to / from the paper's c2c
+// k-space order, EPI_TSTORE or EPI_TLOAD).  chunk: consecutive tiles per XCD in the tile
 // order (16 by default).
 hipError_t launch_strided(int len, int sign, const SArgs &a, int grid_cap, hipStream_t s,
                           int *grid_used, int variant = 0, int chunk = 16);
@@ -89,7 +95,7 @@ hipError_t launch_shell_partials(const ModeTables &mt, int n1, int n2, double ls
 // out[b] = sum_g partial[g * width + b] in a fixed order, b < width.
 hipError_t launch_reduce_cols(const double *partial, int64_t grid, int width, double *out,
                               hipStream_t s);
-hipError_t launch_pk_kspace(const void *F, int n1, int n2, int64_t sy, int64_t sz,
+hipError_t launch_pk_kspace(const void *F, int n1, int n2, int64_t sx, int64_t sy, int64_t sz,
                             const ModeTables &mt, double *partial, int grid, hipStream_t s);
 hipError_t launch_pk_finalize(const double *S, int nbins, const double *count, const double *sumk,
                               double norm, double vscale, double kscale, double *pk,

@@ -664,6 +664,62 @@ struct STileW {
     }
 };
 
+// Transposing strided tile for the z pass of a c2c plan in the paper's
+// k-space order (k_z, k_x, k_y): every column's points are contiguous there
+// (stride ncomp).  Forward (EPI_TSTORE): natural columns in, the last stage
+// writes LDS and the tile is stored point-fastest; backward (EPI_TLOAD): the
+// tile is loaded point-fastest into LDS and the last stage writes the
+// natural columns.  Threads walk the tile's (column, point) pairs with the
+// point fastest, so each column's run is read or written contiguously.
+template <int L, int S, int NT>
+struct STileT {
+    static constexpr int B = s_b(L);
+    static constexpr size_t O_BUF = 0, O_TW = al16(sizeof(c32) * L * B),
+                            BYTES = al16(O_TW + sizeof(c32) * L);
+    static __device__ void tables(const SArgs &a, char *sm, int tid)
+    {
+        load_table((c32 *)(sm + O_TW), a.tw, L, tid, NT);
+    }
+    static __device__ __forceinline__ int64_t tpos(const SArgs &a, int64_t f, int kz)
+    {
+        const int64_t c1 = a.t_n0 * a.t_nc;
+        const int64_t y = f / c1, r = f - y * c1;
+        const int64_t x = r / a.t_nc, c = r - x * a.t_nc;
+        return ((y * a.t_n0 + x) * a.t_n2 + kz) * a.t_nc + c;
+    }
+    static __device__ void tile(const SArgs &a, int64_t t, char *sm, int tid)
+    {
+        c32 *buf = (c32 *)(sm + O_BUF);
+        const c32 *tw = (const c32 *)(sm + O_TW);
+        const int col = tid % B;
+        const int64_t f0 = t * B;
+        const int64_t f = f0 + col;
+        const bool valid = f < a.ncols;
+        const int64_t base = valid ? f : 0;  // natural z pass: column f at f
+        if (a.epi & EPI_TLOAD) {
+            const c32 *in = (const c32 *)a.in;
+            for (int e = tid; e < B * L; e += NT) {
+                const int kz = e % L, cl = e / L;
+                const int64_t ff = f0 + cl;
+                buf[kz * B + cl] = ff < a.ncols ? in[tpos(a, ff, kz)] : c32{0.f, 0.f};
+            }
+            __syncthreads();
+            col_fft<L, S, B, NT, false, true>(buf, nullptr, (c32 *)a.out + base, a.stride, valid,
+                                              tw, tid);
+        } else {
+            col_fft<L, S, B, NT, true, false>(buf, (const c32 *)a.in + base, nullptr, a.stride,
+                                              valid, tw, tid);
+            c32 *out = (c32 *)a.out;
+            for (int e = tid; e < B * L; e += NT) {
+                const int kz = e % L, cl = e / L;
+                const int64_t ff = f0 + cl;
+                if (ff < a.ncols) out[tpos(a, ff, kz)] = buf[kz * B + cl];
+            }
+        }
+        __syncthreads();
+    }
+};
+
 // ======================================================= standalone kernels
 // One x tile per block (tile index = blockIdx.x).
 
@@ -773,6 +829,18 @@ __global__ __launch_bounds__(kSWThreads) void k_strided_w(SArgs a)
         if (t >= ntiles) continue;  // uniform over the block
         T::tile(a, t, sm, tid);
     }
+}
+
+template <int L, int S>
+__global__ __launch_bounds__(kSThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_strided_t(SArgs a)
+{
+    using T = STileT<L, S, kSThreads>;
+    __shared__ __align__(16) char sm[T::BYTES];
+    const int tid = threadIdx.x;
+    T::tables(a, sm, tid);
+    __syncthreads();
+    const int64_t ntiles = (a.ncols + T::B - 1) / T::B;
+    for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) T::tile(a, t, sm, tid);
 }
 
 }  // namespace lf2

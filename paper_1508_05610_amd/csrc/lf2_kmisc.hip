@@ -165,8 +165,9 @@ hipError_t launch_reduce_cols(const double *partial, int64_t grid, int width, do
 // Tile of 64 adjacent (kx, ky) columns; thread (col, rg) walks a contiguous
 // run of kz, flushing its running bin sum to the LDS histogram when the bin
 // changes.  Partials [grid][nbins + 1] (slot nbins = zero mode).
-__global__ __launch_bounds__(256) void k_pk_kspace(const c32 *F, int n1, int n2, int64_t sy,
-                                                   int64_t sz, ModeTables mt, double *partial)
+__global__ __launch_bounds__(256) void k_pk_kspace(const c32 *F, int n1, int n2, int64_t sx,
+                                                   int64_t sy, int64_t sz, ModeTables mt,
+                                                   double *partial)
 {
     constexpr int B = 64, NT = 256, RG = NT / B;
     extern __shared__ double sh[];
@@ -194,7 +195,7 @@ __global__ __launch_bounds__(256) void k_pk_kspace(const c32 *F, int n1, int n2,
         for (int e = 0; e < ep; ++e) {
             const int kz = rg * ep + e;
             if (kz >= n2) break;
-            const c32 v = F[(int64_t)kz * sz + (int64_t)ky * sy + kx];
+            const c32 v = F[(int64_t)kz * sz + (int64_t)ky * sy + (int64_t)kx * sx];
             const bool zero = (kx == 0 && ky == 0 && kz == 0);
             const int b = zero ? nb : bin_of(qxy + mt.q[2][kz], th, nb, inv_qmax);
             const double p = w * ((double)v.x * v.x + (double)v.y * v.y);
@@ -211,12 +212,12 @@ __global__ __launch_bounds__(256) void k_pk_kspace(const c32 *F, int n1, int n2,
     for (int i = threadIdx.x; i <= nb; i += NT) partial[(int64_t)blockIdx.x * (nb + 1) + i] = hist[i];
 }
 
-hipError_t launch_pk_kspace(const void *F, int n1, int n2, int64_t sy, int64_t sz,
+hipError_t launch_pk_kspace(const void *F, int n1, int n2, int64_t sx, int64_t sy, int64_t sz,
                             const ModeTables &mt, double *partial, int grid, hipStream_t s)
 {
     const size_t shm = (size_t)(mt.nbins + 1) * 16;
-    hipLaunchKernelGGL(k_pk_kspace, dim3(grid), dim3(256), shm, s, (const c32 *)F, n1, n2, sy, sz,
-                       mt, partial);
+    hipLaunchKernelGGL(k_pk_kspace, dim3(grid), dim3(256), shm, s, (const c32 *)F, n1, n2, sx, sy,
+                       sz, mt, partial);
     return hipGetLastError();
 }
 

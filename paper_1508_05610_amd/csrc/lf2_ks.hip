@@ -58,6 +58,28 @@ static hipError_t launch_wide(int len, int sign, const SArgs &a, int grid_cap, h
 #undef LF2_CASE
 }
 
+static hipError_t launch_transposed(int len, int sign, const SArgs &a, int grid_cap,
+                                    hipStream_t s, int *grid_used)
+{
+#define LF2_CASE(L)                                                                          \
+    case L: {                                                                                \
+        int64_t ntiles = (a.ncols + s_b(L) - 1) / s_b(L);                                    \
+        int g = (int)(ntiles < grid_cap ? ntiles : grid_cap);                                \
+        if (grid_used) *grid_used = g;                                                       \
+        if (sign < 0)                                                                        \
+            hipLaunchKernelGGL((k_strided_t<L, -1>), dim3(g), dim3(kSThreads), 0, s, a);     \
+        else                                                                                 \
+            hipLaunchKernelGGL((k_strided_t<L, 1>), dim3(g), dim3(kSThreads), 0, s, a);      \
+        return hipGetLastError();                                                            \
+    }
+    switch (len) {
+        LF2_S_LENGTHS(LF2_CASE)
+    default:
+        return hipErrorInvalidValue;
+    }
+#undef LF2_CASE
+}
+
 hipError_t launch_strided(int len, int sign, const SArgs &a_in, int grid_cap, hipStream_t s,
                           int *grid_used, int variant, int chunk)
 {
@@ -73,6 +95,10 @@ hipError_t launch_strided(int len, int sign, const SArgs &a_in, int grid_cap, hi
     if (variant == 1) {
         if (epi || !s_wide_supported(len)) return hipErrorInvalidValue;
         return launch_wide(len, sign, a, grid_cap, s, grid_used, kChunk);
+    }
+    if (variant == 2) {
+        if (epi || !(a.epi & (EPI_TSTORE | EPI_TLOAD))) return hipErrorInvalidValue;
+        return launch_transposed(len, sign, a, grid_cap, s, grid_used);
     }
 #define LF2_CASE(L)                                                                          \
     case L: {                                                                                \

@@ -84,10 +84,10 @@ def test_unknown_plan_flag(lib):
 
 
 def test_layout_flag_validation(lib):
-    # in place needs halo 0; the paper's c2c order is not built
+    # in place needs halo 0
     assert lib.lf2_fft_plan_status((32, 32, 32), 1, 1, 0, flags=lib.LF2_IN_PLACE) == \
         lib.LF2_ERR_UNSUPPORTED
-    assert lib.lf2_fft_plan_status((32, 32, 32), 0, 1, 1, flags=lib.LF2_KLAYOUT_PAPER) == \
+    assert lib.lf2_fft_plan_status((32, 32, 32), 1, 1, 1, flags=lib.LF2_IN_PLACE) == \
         lib.LF2_ERR_UNSUPPORTED
 
 
