@@ -123,16 +123,18 @@ lf2_status lf2_fft_kspace(lf2_plan p, int64_t ksize[3], int64_t kstride[3]);
 
 /*
  * Tuning of the strided pass along `axis` (1 = y, 2 = z) for plain
- * transforms.  variant 0 = narrow tiles (all lengths); 1 = wide tiles
- * (twice the columns per tile, one 1024-thread block per CU; lengths 256,
- * 320, 384, 512, 640, 768, 1024, 2048).  chunk = consecutive tiles given to one
- * XCD in the tile order (1..1024, default 16).  Every setting computes the
- * same transform bit for bit.  The fused Poisson / power-spectrum pass
- * always uses narrow tiles and chunk 16.  get reports the setting and,
- * after LF2_PLAN_AUTOTUNE, the measured microseconds of the default setting
- * (narrow, 16) and of the chosen one (-1 if not measured); null outputs are
- * skipped.  set overrides the setting (LF2_ERR_UNSUPPORTED for wide tiles
- * on a length without them).
+ * transforms.  variant bit 0: wide tiles (twice the columns per tile, one
+ * 1024-thread block per CU; lengths 256, 320, 384, 512, 640, 768, 1024,
+ * 2048) instead of narrow tiles (all lengths); bit 1: nontemporal global
+ * loads and stores (they pay on long strides, where each line is touched
+ * once).  chunk = consecutive tiles given to one XCD in the tile order
+ * (1..1024, default 16).  Every setting computes the same transform bit for
+ * bit.  The fused Poisson / power-spectrum pass always uses narrow tiles,
+ * normal accesses and chunk 16.  get reports the setting and, after
+ * LF2_PLAN_AUTOTUNE, the measured microseconds of the default setting
+ * (variant 0, chunk 16) and of the chosen one (-1 if not measured); null
+ * outputs are skipped.  set overrides the setting (LF2_ERR_UNSUPPORTED for
+ * wide tiles on a length without them).
  */
 lf2_status lf2_plan_get_tuning(lf2_plan p, int32_t axis, int32_t *variant, int32_t *chunk,
                                double *us_default, double *us_tuned);

@@ -446,11 +446,13 @@ lf2_status run_strided(const lf2_plan_s *p, int axis, int sign, const SArgs &a, 
     const double sb = (double)spectrum_bytes(p);
     const bool epi = (a.epi & (EPI_PK | EPI_PK_AFTER | EPI_POISSON)) != 0;
     const bool tr = (a.epi & (EPI_TSTORE | EPI_TLOAD)) != 0;
-    const int variant = tr ? 2 : epi ? 0 : p->svar[axis];
+    const int variant = (tr || epi) ? 0 : p->svar[axis];
+    const int ntm = (variant & 2) ? 1 : 0;
     // "<kernel symbol> <pass>": the symbol part matches the profiler's name
-    const std::string sym = variant == 2   ? kname("k_strided_t<%d,%d>", p->len[axis], sign)
-                            : variant == 1 ? kname("k_strided_w<%d,%d>", p->len[axis], sign)
-                                           : kname("k_strided<%d,%d,%d>", p->len[axis], sign, epi ? 1 : 0);
+    const std::string sym = tr ? kname("k_strided_t<%d,%d>", p->len[axis], sign)
+                            : (variant & 1) ? kname("k_strided_w<%d,%d,%d>", p->len[axis], sign, ntm)
+                                            : kname("k_strided<%d,%d,%d,%d>", p->len[axis], sign,
+                                                    epi ? 1 : 0, ntm);
     const int t = prof::begin(sym + kname(" %s%s%s %lldx%lldx%lld/%d", axis == 1 ? "y" : "z",
                                     (a.epi & EPI_POISSON) ? "+poisson" : "",
                                     (a.epi & (EPI_PK | EPI_PK_AFTER)) ? "+pk" : "",
@@ -617,10 +619,11 @@ lf2_status autotune(lf2_plan p)
         hip_ok(hipEventCreate(&e0), "event") && hip_ok(hipEventCreate(&e1), "event") &&
         hip_ok(hipMemsetAsync(w, 0, bytes, s), "memset")) {
         for (int axis = 1; axis <= 2 && st == LF2_OK; ++axis) {
-            const int nv = s_wide_supported(p->len[axis]) ? 2 : 1;
+            const bool wide = s_wide_supported(p->len[axis]);
             const SArgs a = s_args(p, axis, w, w, EPI_STORE);
             double best = -1.0;
-            for (int v = 0; v < nv && st == LF2_OK; ++v) {
+            for (int v = 0; v < 4 && st == LF2_OK; ++v) {
+                if ((v & 1) && !wide) continue;
                 for (int c : kChunks) {
                     hip_ok(launch_strided(p->len[axis], -1, a, kStridedGridCap, s, nullptr, v, c), "launch");
                     hip_ok(hipEventRecord(e0, s), "record");
@@ -764,9 +767,9 @@ lf2_status lf2_plan_set_tuning(lf2_plan p, int32_t axis, int32_t variant, int32_
 {
     if (!p) return fail(LF2_ERR_INVALID_ARG, "plan is NULL");
     if (axis != 1 && axis != 2) return fail(LF2_ERR_INVALID_ARG, "axis %d is not 1 or 2", axis);
-    if (variant != 0 && variant != 1) return fail(LF2_ERR_INVALID_ARG, "variant %d is not 0 or 1", variant);
+    if (variant < 0 || variant > 3) return fail(LF2_ERR_INVALID_ARG, "variant %d outside [0, 3]", variant);
     if (chunk < 1 || chunk > 1024) return fail(LF2_ERR_INVALID_ARG, "chunk %d outside [1, 1024]", chunk);
-    if (variant == 1 && !s_wide_supported(p->len[axis]))
+    if ((variant & 1) && !s_wide_supported(p->len[axis]))
         return fail(LF2_ERR_UNSUPPORTED, "no wide tiles for line length %d", p->len[axis]);
     p->svar[axis] = variant;
     p->schunk[axis] = chunk;

@@ -214,7 +214,36 @@ __host__ __device__ constexpr int max_radix(int L, int st = 0)
 // last stage of a Stockham DIT writes point j + r L/R).  Stages that read
 // and write LDS wait at a barrier between their reads and their writes.
 
-template <int L, int R, int NS, int S, int NL, int NT, bool SRC_G, bool DST_G>
+// Global loads and stores of one complex value; NTM = true marks them
+// nontemporal (streamed past the caches' normal allocation), which pays for
+// the long-stride passes whose lines are touched once.
+typedef float lf2_f2 __attribute__((ext_vector_type(2)));
+
+template <bool NTM>
+__device__ __forceinline__ c32 gload(const c32 *p)
+{
+    if constexpr (NTM) {
+        const lf2_f2 t = __builtin_nontemporal_load((const lf2_f2 *)p);
+        return c32{t.x, t.y};
+    } else {
+        return *p;
+    }
+}
+
+template <bool NTM>
+__device__ __forceinline__ void gstore(c32 *p, c32 v)
+{
+    if constexpr (NTM) {
+        lf2_f2 t;
+        t.x = v.x;
+        t.y = v.y;
+        __builtin_nontemporal_store(t, (lf2_f2 *)p);
+    } else {
+        *p = v;
+    }
+}
+
+template <int L, int R, int NS, int S, int NL, int NT, bool SRC_G, bool DST_G, bool NTM = false>
 __device__ __forceinline__ void col_stage(c32 *buf, const c32 *gin, c32 *gout, int64_t gs,
                                           bool gv, const c32 *tw, int tid)
 {
@@ -233,7 +262,7 @@ __device__ __forceinline__ void col_stage(c32 *buf, const c32 *gin, c32 *gout, i
 #pragma unroll
             for (int r = 0; r < R; ++r) {
                 if (SRC_G)
-                    v[i][r] = gv ? gin[(int64_t)(j + r * Q) * gs] : c32{0.f, 0.f};
+                    v[i][r] = gv ? gload<NTM>(gin + (int64_t)(j + r * Q) * gs) : c32{0.f, 0.f};
                 else
                     v[i][r] = buf[l + (j + r * Q) * NL];
             }
@@ -257,7 +286,7 @@ __device__ __forceinline__ void col_stage(c32 *buf, const c32 *gin, c32 *gout, i
             if (DST_G) {
                 if (gv) {
 #pragma unroll
-                    for (int r = 0; r < R; ++r) gout[(int64_t)(j + r * Q) * gs] = v[i][r];
+                    for (int r = 0; r < R; ++r) gstore<NTM>(gout + (int64_t)(j + r * Q) * gs, v[i][r]);
                 }
             } else {
                 c32 *dst = buf + l + ((j / NS) * NS * R + k) * NL;
@@ -381,7 +410,8 @@ __device__ __forceinline__ void row_fft(c32 *buf, const c32 *gin, c32 *gout,
 
 // Whole transform of the NL columns; SRC_G / DST_G select global input for
 // the first stage and global output for the last stage.  L = 1 is a copy.
-template <int L, int S, int NL, int NT, bool SRC_G, bool DST_G, int ST = 0, int NS = 1>
+template <int L, int S, int NL, int NT, bool SRC_G, bool DST_G, int ST = 0, int NS = 1,
+          bool NTM = false>
 __device__ __forceinline__ void col_fft(c32 *buf, const c32 *gin, c32 *gout, int64_t gs, bool gv,
                                         const c32 *tw, int tid)
 {
@@ -399,9 +429,9 @@ __device__ __forceinline__ void col_fft(c32 *buf, const c32 *gin, c32 *gout, int
     } else if constexpr (NS < L) {
         constexpr int R = radix_at(L, ST);
         constexpr bool first = ST == 0, last = NS * R == L;
-        col_stage<L, R, NS, S, NL, NT, first && SRC_G, last && DST_G>(buf, gin, gout, gs, gv, tw,
-                                                                      tid);
-        col_fft<L, S, NL, NT, SRC_G, DST_G, ST + 1, NS * R>(buf, gin, gout, gs, gv, tw, tid);
+        col_stage<L, R, NS, S, NL, NT, first && SRC_G, last && DST_G, NTM>(buf, gin, gout, gs, gv,
+                                                                           tw, tid);
+        col_fft<L, S, NL, NT, SRC_G, DST_G, ST + 1, NS * R, NTM>(buf, gin, gout, gs, gv, tw, tid);
     }
 }
 

@@ -70,9 +70,11 @@ bool s_supported(int len);
 hipError_t launch_x_r2c(int m, int nc, const XArgs &a, hipStream_t s);
 hipError_t launch_x_c2r(int m, int nc, const XArgs &a, hipStream_t s);
 hipError_t launch_x_c2c(int len, int nc, int sign, const XArgs &a, hipStream_t s);
-// variant 0: STile (narrow, any pass); 1: STileW (wide, plain passes of
-// s_wide_supported lengths); 2: STileT (z pass to / from the paper's c2c
-// k-space order, EPI_TSTORE or EPI_TLOAD).  chunk: consecutive tiles per XCD in the tile
+// variant bit 0: STileW (wide tiles, plain passes of s_wide_supported
+// lengths) instead of STile (narrow, any pass); bit 1: nontemporal global
+// loads and stores (plain passes).  EPI_TSTORE / EPI_TLOAD in a.epi select
+// STileT (z pass to / from the paper's c2c k-space order) whatever the
+// variant.  chunk: consecutive tiles per XCD in the tile
 // order (16 by default).
 hipError_t launch_strided(int len, int sign, const SArgs &a, int grid_cap, hipStream_t s,
                           int *grid_used, int variant = 0, int chunk = 16);

@@ -515,7 +515,7 @@ __device__ __forceinline__ double rcp_f64(double d)
 // EPI = true : last-axis pass with the binning / Poisson epilogue.
 // hist / thresh: LDS arrays of nbins + 1 entries (EPI with binning only);
 // the tile adds its w|F|^2 sums into hist.
-template <int L, int S, bool EPI, int NT>
+template <int L, int S, bool EPI, int NT, bool NTM = false>
 struct STile {
     static constexpr int B = s_b(L);
     static constexpr int RPT = NT / B;  // row groups in the epilogue
@@ -556,7 +556,8 @@ struct STile {
         c32 *gout = (c32 *)a.out + base;
         if constexpr (!EPI) {
             // global -> registers -> stages -> registers -> global
-            col_fft<L, S, B, NT, true, true>(buf, gin, gout, a.stride, valid && store, tw, tid);
+            col_fft<L, S, B, NT, true, true, 0, 1, NTM>(buf, gin, gout, a.stride, valid && store,
+                                                         tw, tid);
         } else {
             const bool pk = (a.epi & (EPI_PK | EPI_PK_AFTER)) != 0;
             const int nb = a.mt.nbins;
@@ -637,7 +638,7 @@ struct STile {
 // segments per row pay for the lower block count.  No epilogue.
 constexpr int kSWThreads = 1024;
 
-template <int L, int S, int NT>
+template <int L, int S, int NT, bool NTM = false>
 struct STileW {
     static constexpr int B = 2 * s_b(L);
     static constexpr size_t O_BUF = 0, O_TW = al16(sizeof(c32) * L * B),
@@ -658,7 +659,7 @@ struct STileW {
             const int64_t o = f / a.ncols_inner;
             base = o * a.outer + (f - o * a.ncols_inner);
         }
-        col_fft<L, S, B, NT, true, true>(buf, (const c32 *)a.in + base, (c32 *)a.out + base,
+        col_fft<L, S, B, NT, true, true, 0, 1, NTM>(buf, (const c32 *)a.in + base, (c32 *)a.out + base,
                                          a.stride, valid && (a.epi & EPI_STORE) != 0, tw, tid);
         __syncthreads();
     }
@@ -769,10 +770,10 @@ __global__ __launch_bounds__(kXThreads) void k_x_c2c_v(XArgs a)
 }
 
 // Strided pass: persistent-style walk over tiles.
-template <int L, int S, bool EPI>
+template <int L, int S, bool EPI, bool NTM = false>
 __global__ __launch_bounds__(kSThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_strided(SArgs a)
 {
-    using T = STile<L, S, EPI, kSThreads>;
+    using T = STile<L, S, EPI, kSThreads, NTM>;
     constexpr int NT = kSThreads;
     constexpr int B = T::B;
     __shared__ __align__(16) char sm[T::BYTES];
@@ -811,10 +812,10 @@ __global__ __launch_bounds__(kSThreads) __attribute__((amdgpu_waves_per_eu(4))) 
     }
 }
 
-template <int L, int S>
+template <int L, int S, bool NTM = false>
 __global__ __launch_bounds__(kSWThreads) void k_strided_w(SArgs a)
 {
-    using T = STileW<L, S, kSWThreads>;
+    using T = STileW<L, S, kSWThreads, NTM>;
     constexpr int B = T::B;
     __shared__ __align__(16) char sm[T::BYTES];
     const int tid = threadIdx.x;

@@ -34,8 +34,26 @@ bool s_wide_supported(int len)
     }
 }
 
+template <int L, bool NTM>
+static void wide_k(int sign, int g, const SArgs &a, hipStream_t s)
+{
+    if (sign < 0)
+        hipLaunchKernelGGL((k_strided_w<L, -1, NTM>), dim3(g), dim3(kSWThreads), 0, s, a);
+    else
+        hipLaunchKernelGGL((k_strided_w<L, 1, NTM>), dim3(g), dim3(kSWThreads), 0, s, a);
+}
+
+template <int L, bool NTM>
+static void narrow_k(int sign, int g, const SArgs &a, hipStream_t s)
+{
+    if (sign < 0)
+        hipLaunchKernelGGL((k_strided<L, -1, false, NTM>), dim3(g), dim3(kSThreads), 0, s, a);
+    else
+        hipLaunchKernelGGL((k_strided<L, 1, false, NTM>), dim3(g), dim3(kSThreads), 0, s, a);
+}
+
 static hipError_t launch_wide(int len, int sign, const SArgs &a, int grid_cap, hipStream_t s,
-                              int *grid_used, int chunk)
+                              int *grid_used, int chunk, bool ntm)
 {
 #define LF2_CASE(L)                                                                          \
     case L: {                                                                                \
@@ -44,10 +62,10 @@ static hipError_t launch_wide(int len, int sign, const SArgs &a, int grid_cap, h
         int64_t span = (ntiles + 8 * chunk - 1) / (8 * chunk) * (8 * chunk);                 \
         int g = (int)(span < grid_cap ? span : grid_cap);                                    \
         if (grid_used) *grid_used = g;                                                       \
-        if (sign < 0)                                                                        \
-            hipLaunchKernelGGL((k_strided_w<L, -1>), dim3(g), dim3(kSWThreads), 0, s, a);     \
+        if (ntm)                                                                             \
+            wide_k<L, true>(sign, g, a, s);                                                  \
         else                                                                                 \
-            hipLaunchKernelGGL((k_strided_w<L, 1>), dim3(g), dim3(kSWThreads), 0, s, a);     \
+            wide_k<L, false>(sign, g, a, s);                                                 \
         return hipGetLastError();                                                            \
     }
     switch (len) {
@@ -92,14 +110,16 @@ hipError_t launch_strided(int len, int sign, const SArgs &a_in, int grid_cap, hi
     const bool pk = (a.epi & (EPI_PK | EPI_PK_AFTER)) != 0;
     const bool epi = (a.epi & (EPI_PK | EPI_PK_AFTER | EPI_POISSON)) != 0;
     const size_t shm = pk ? (size_t)(a.mt.nbins + 1) * 16 : 0;
-    if (variant == 1) {
-        if (epi || !s_wide_supported(len)) return hipErrorInvalidValue;
-        return launch_wide(len, sign, a, grid_cap, s, grid_used, kChunk);
-    }
-    if (variant == 2) {
-        if (epi || !(a.epi & (EPI_TSTORE | EPI_TLOAD))) return hipErrorInvalidValue;
+    if (a.epi & (EPI_TSTORE | EPI_TLOAD)) {
+        if (epi) return hipErrorInvalidValue;
         return launch_transposed(len, sign, a, grid_cap, s, grid_used);
     }
+    const bool ntm = (variant & 2) != 0;
+    if (variant & 1) {
+        if (epi || !s_wide_supported(len)) return hipErrorInvalidValue;
+        return launch_wide(len, sign, a, grid_cap, s, grid_used, kChunk, ntm);
+    }
+    if (epi && ntm) return hipErrorInvalidValue;
 #define LF2_CASE(L)                                                                          \
     case L: {                                                                                \
         int64_t ntiles = (a.ncols + s_b(L) - 1) / s_b(L);                                    \
@@ -110,10 +130,10 @@ hipError_t launch_strided(int len, int sign, const SArgs &a_in, int grid_cap, hi
             hipLaunchKernelGGL((k_strided<L, -1, true>), dim3(g), dim3(kSThreads), shm, s, a);\
         else if (epi)                                                                        \
             return hipErrorInvalidValue;                                                     \
-        else if (sign < 0)                                                                   \
-            hipLaunchKernelGGL((k_strided<L, -1, false>), dim3(g), dim3(kSThreads), 0, s, a); \
+        else if (ntm)                                                                        \
+            narrow_k<L, true>(sign, g, a, s);                                                \
         else                                                                                 \
-            hipLaunchKernelGGL((k_strided<L, 1, false>), dim3(g), dim3(kSThreads), 0, s, a);  \
+            narrow_k<L, false>(sign, g, a, s);                                               \
         return hipGetLastError();                                                            \
     }
     switch (len) {

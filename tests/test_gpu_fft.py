@@ -193,9 +193,12 @@ def test_wide_tiles_match_oracle_and_narrow(lf2, shape, kind, ncomp):
     pn = lf2.Plan(shape, kind, ncomp=ncomp)
     pw = lf2.Plan(shape, kind, ncomp=ncomp)
     for axis in (1, 2):
-        if shape[axis] >= 256:
-            pw.set_tuning(axis, 1, chunk=4 if axis == 1 else 64)
-            assert pw.tuning(axis)[:2] == (1, 4 if axis == 1 else 64)
+        if shape[axis] >= 256:  # wide tiles; nontemporal accesses on z
+            v = 1 if axis == 1 else 3
+            pw.set_tuning(axis, v, chunk=4 if axis == 1 else 64)
+            assert pw.tuning(axis)[:2] == (v, 4 if axis == 1 else 64)
+        else:
+            pw.set_tuning(axis, 2)  # narrow tiles, nontemporal accesses
     if kind == lf2.LF2_R2C:
         f = real_field(shape, seed=11)[0][..., 0]
         x = torch.from_numpy(f).to(dev())
@@ -228,7 +231,7 @@ def test_autotune_picks_a_setting(lf2):
     for axis in (1, 2):
         v, c, ud, ut = p.tuning(axis)
         print(f"  axis {axis}: variant {v} chunk {c} default {ud:.1f} us tuned {ut:.1f} us", flush=True)
-        assert v in (0, 1) and c in (4, 16, 64) and 0 < ut <= ud
+        assert v in (0, 1, 2, 3) and c in (4, 16, 64) and 0 < ut <= ud
     q = lf2.Plan((64, 48, 40), lf2.LF2_R2C, autotune=True)
     v, c, ud, ut = q.tuning(1)
     assert v == 0 and 0 < ut <= ud        # narrow tiles only for these lengths
