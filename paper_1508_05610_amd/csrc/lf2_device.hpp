@@ -315,7 +315,8 @@ __device__ __forceinline__ void col_stage(c32 *buf, const c32 *gin, c32 *gout, i
 __host__ __device__ constexpr int lpad(int p) { return p + (p >> 4); }
 __host__ __device__ constexpr int row_pitch(int npoints) { return lpad(npoints - 1) + 1; }
 
-template <int L, int R, int NS, int S, int RB, int NC, int LP, int NT, bool SRC_G, bool DST_G>
+template <int L, int R, int NS, int S, int RB, int NC, int LP, int NT, bool SRC_G, bool DST_G,
+          bool NTM = false>
 __device__ __forceinline__ void row_stage(c32 *buf, const c32 *gin, c32 *gout,
                                           const int64_t *rowoff_in, const int64_t *rowoff_out,
                                           int nvalid, const c32 *tw, int tid, double *ssq)
@@ -335,7 +336,8 @@ __device__ __forceinline__ void row_stage(c32 *buf, const c32 *gin, c32 *gout,
 #pragma unroll
             for (int r = 0; r < R; ++r) {
                 if (SRC_G)
-                    v[i][r] = q < nvalid ? gin[rowoff_in[q] + (j + r * Q) * NC + c] : c32{0.f, 0.f};
+                    v[i][r] = q < nvalid ? gload<NTM>(gin + rowoff_in[q] + (j + r * Q) * NC + c)
+                                         : c32{0.f, 0.f};
                 else
                     v[i][r] = buf[l * LP + lpad(j + r * Q)];
             }
@@ -367,7 +369,8 @@ __device__ __forceinline__ void row_stage(c32 *buf, const c32 *gin, c32 *gout,
             if (DST_G) {
                 if (q < nvalid) {
 #pragma unroll
-                    for (int r = 0; r < R; ++r) gout[rowoff_out[q] + (j + r * Q) * NC + c] = v[i][r];
+                    for (int r = 0; r < R; ++r)
+                        gstore<NTM>(gout + rowoff_out[q] + (j + r * Q) * NC + c, v[i][r]);
                 }
             } else {
                 c32 *dst = buf + l * LP;
@@ -381,7 +384,7 @@ __device__ __forceinline__ void row_stage(c32 *buf, const c32 *gin, c32 *gout,
 }
 
 template <int L, int S, int RB, int NC, int LP, int NT, bool SRC_G, bool DST_G, int ST = 0,
-          int NS = 1>
+          int NS = 1, bool NTM = false>
 __device__ __forceinline__ void row_fft(c32 *buf, const c32 *gin, c32 *gout,
                                         const int64_t *rowoff_in, const int64_t *rowoff_out,
                                         int nvalid, const c32 *tw, int tid, double *ssq = nullptr)
@@ -401,9 +404,9 @@ __device__ __forceinline__ void row_fft(c32 *buf, const c32 *gin, c32 *gout,
     } else if constexpr (NS < L) {
         constexpr int R = radix_at(L, ST);
         constexpr bool first = ST == 0, last = NS * R == L;
-        row_stage<L, R, NS, S, RB, NC, LP, NT, first && SRC_G, last && DST_G>(
+        row_stage<L, R, NS, S, RB, NC, LP, NT, first && SRC_G, last && DST_G, NTM>(
             buf, gin, gout, rowoff_in, rowoff_out, nvalid, tw, tid, ssq);
-        row_fft<L, S, RB, NC, LP, NT, SRC_G, DST_G, ST + 1, NS * R>(
+        row_fft<L, S, RB, NC, LP, NT, SRC_G, DST_G, ST + 1, NS * R, NTM>(
             buf, gin, gout, rowoff_in, rowoff_out, nvalid, tw, tid, ssq);
     }
 }

@@ -284,7 +284,7 @@ struct XR2CV {
         __syncthreads();
         const int nv = rows_valid<RB>(a, r0);
         double ss = 0.0;
-        row_fft<M, -1, RB, 1, LP, NT, true, false>(buf, (const c32 *)a.in, nullptr, ib, nullptr,
+        row_fft<M, -1, RB, 1, LP, NT, true, false, 0, 1, true>(buf, (const c32 *)a.in, nullptr, ib, nullptr,
                                                    nv, tw, tid, sumsq ? &ss : nullptr);
         if (sumsq) block_sum_f64<NT>(ss, sumsq, (double *)(sm + O_RED));
         c32 *out = (c32 *)a.out;
@@ -304,8 +304,8 @@ struct XR2CV {
                     const c32 fo = c32{0.5f * d.y, -0.5f * d.x};
                     const c32 wf = mul(twp[k], fo);
                     c32 *orow = out + ob[l];
-                    orow[k] = add(fe, wf);
-                    if (2 * k != M) orow[M - k] = conjg(sub(fe, wf));
+                    gstore<true>(orow + k, add(fe, wf));
+                    if (2 * k != M) gstore<true>(orow + (M - k), conjg(sub(fe, wf)));
                 }
             }
         }
@@ -350,9 +350,10 @@ struct XC2RV {
                 buf[l * LP + lpad(k)] = v;
             };
             if (((uintptr_t)src & 15) == 0) {
-                const float4 *s4 = (const float4 *)src;
+                typedef float nf4 __attribute__((ext_vector_type(4)));
+                const nf4 *s4 = (const nf4 *)src;
                 for (int e = tid; e < cnt / 2; e += NT) {
-                    const float4 w = s4[e];
+                    const nf4 w = __builtin_nontemporal_load(s4 + e);
                     put(2 * e, c32{w.x, w.y});
                     put(2 * e + 1, c32{w.z, w.w});
                 }
@@ -418,7 +419,7 @@ struct XC2RV {
                 }
             }
             __syncthreads();
-            row_fft<M, +1, RB, 1, LP, NT, false, true, 1, R>(buf, nullptr, (c32 *)a.out, nullptr,
+            row_fft<M, +1, RB, 1, LP, NT, false, true, 1, R, true>(buf, nullptr, (c32 *)a.out, nullptr,
                                                              ob, nv, tw, tid);
         } else {
             constexpr int NP = RB * HALF;
@@ -473,7 +474,7 @@ struct XC2CV {
         row_bases<RB, NT>(ib, ob, a, r0, tid);
         __syncthreads();
         const int nv = rows_valid<RB>(a, r0);
-        row_fft<L, S, RB, NC, LP, NT, true, true>(buf, (const c32 *)a.in, (c32 *)a.out, ib, ob,
+        row_fft<L, S, RB, NC, LP, NT, true, true, 0, 1, true>(buf, (const c32 *)a.in, (c32 *)a.out, ib, ob,
                                                   nv, tw, tid);
         __syncthreads();
     }
