@@ -447,7 +447,7 @@ lf2_status run_strided(const lf2_plan_s *p, int axis, int sign, const SArgs &a, 
     const bool epi = (a.epi & (EPI_PK | EPI_PK_AFTER | EPI_POISSON)) != 0;
     const bool tr = (a.epi & (EPI_TSTORE | EPI_TLOAD)) != 0;
     const int variant = (tr || epi) ? 0 : p->svar[axis];
-    const int ntm = (variant & 2) ? 1 : 0;
+    const int ntm = ((variant & 2) || epi) ? 1 : 0;  // the fused pass always streams
     // "<kernel symbol> <pass>": the symbol part matches the profiler's name
     const std::string sym = tr ? kname("k_strided_t<%d,%d>", p->len[axis], sign)
                             : (variant & 1) ? kname("k_strided_w<%d,%d,%d>", p->len[axis], sign, ntm)

@@ -77,7 +77,7 @@ template <int L>
 __global__ __launch_bounds__(kSThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_bz(
     const BatchField *fields, const BatchItem *items)
 {
-    using T = STile<L, -1, true, kSThreads>;
+    using T = STile<L, -1, true, kSThreads, true>;
     __shared__ __align__(16) char sm[T::BYTES];
     extern __shared__ double dyn[];  // hist[nbins + 1], thresh[nbins + 1]
     const int tid = threadIdx.x;

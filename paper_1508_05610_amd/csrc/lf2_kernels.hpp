@@ -563,7 +563,7 @@ struct STile {
             const bool pk = (a.epi & (EPI_PK | EPI_PK_AFTER)) != 0;
             const int nb = a.mt.nbins;
             const double inv_qmax = 1.0 / a.mt.qmax;
-            col_fft<L, S, B, NT, true, false>(buf, gin, nullptr, a.stride, valid, tw, tid);
+            col_fft<L, S, B, NT, true, false, 0, 1, NTM>(buf, gin, nullptr, a.stride, valid, tw, tid);
             // Epilogue on the last axis: thread (col, rg) walks a contiguous run
             // of kz so that consecutive modes mostly share a bin.
             constexpr int EP = (L + RPT - 1) / RPT;
@@ -619,8 +619,8 @@ struct STile {
             bool stored = false;
             if constexpr (S < 0) {
                 if (a.epi & EPI_POISSON) {
-                    col_fft<L, +1, B, NT, false, true>(buf, nullptr, gout, a.stride,
-                                                       valid && store, tw, tid);
+                    col_fft<L, +1, B, NT, false, true, 0, 1, NTM>(buf, nullptr, gout, a.stride,
+                                                                  valid && store, tw, tid);
                     stored = true;
                 }
             }

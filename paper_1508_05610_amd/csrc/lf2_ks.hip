@@ -127,7 +127,7 @@ hipError_t launch_strided(int len, int sign, const SArgs &a_in, int grid_cap, hi
         int g = (int)(span < grid_cap ? span : grid_cap);                                    \
         if (grid_used) *grid_used = g;                                                       \
         if (epi && sign < 0)                                                                 \
-            hipLaunchKernelGGL((k_strided<L, -1, true>), dim3(g), dim3(kSThreads), shm, s, a);\
+            hipLaunchKernelGGL((k_strided<L, -1, true, true>), dim3(g), dim3(kSThreads), shm, s, a);\
         else if (epi)                                                                        \
             return hipErrorInvalidValue;                                                     \
         else if (ntm)                                                                        \
