@@ -234,7 +234,7 @@ def test_autotune_picks_a_setting(lf2):
         assert v in (0, 1, 2, 3) and c in (4, 16, 64) and 0 < ut <= ud
     q = lf2.Plan((64, 48, 40), lf2.LF2_R2C, autotune=True)
     v, c, ud, ut = q.tuning(1)
-    assert v == 0 and 0 < ut <= ud        # narrow tiles only for these lengths
+    assert (v & 1) == 0 and 0 < ut <= ud  # no wide tiles for these lengths
     f = real_field(shape, seed=13)[0][..., 0]
     F = p.forward(torch.from_numpy(f).to(dev()))
     torch.cuda.synchronize()
