@@ -87,7 +87,8 @@ typedef enum { LF2_FORWARD = -1, LF2_BACKWARD = +1 } lf2_direction;
 #define LF2_IN_PLACE 0x1u             /* in == out allowed (section 3.6); needs halo 0.  An r2c
                                          plan's real fields then have rows padded to 2 (N0/2 + 1)
                                          floats per component, so each real row and its spectrum
-                                         row share their bytes */
+                                         row share their bytes (with LF2_KLAYOUT_PAPER the rows move,
+                                         so the forward r2c stages its x pass in the workspace) */
 #define LF2_KLAYOUT_PAPER 0x2u        /* k-space in the paper's order (section 3.6): r2c
                                          (k_x, k_z, k_y), i.e. C array [N1][N2][Nh][ncomp]; c2c
                                          (k_z, k_x, k_y), i.e. [N1][N0][N2][ncomp] */

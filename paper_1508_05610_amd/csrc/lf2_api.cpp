@@ -720,6 +720,10 @@ lf2_status lf2_fft_plan(lf2_plan *out, const lf2_lattice *lat, int32_t ncomp, lf
     }
     hipStream_t s = nullptr;
     lf2_status st = LF2_OK;
+    // the fused binning evaluates the bin rule in 32 x 32 -> 64-bit products
+    // (qmax < 7.1e8 for every supported line length)
+    if (p->qmax >= ((int64_t)1 << 32))
+        st = fail(LF2_ERR_UNSUPPORTED, "lattice too large for the exact bin rule");
     for (int i = 0; i < 3 && st == LF2_OK; ++i) {
         st = plan_alloc(p, &p->tw[i], (size_t)p->len[i] * 8);
         if (st == LF2_OK && launch_twiddles(p->tw[i], p->len[i], s) != hipSuccess)
@@ -834,8 +838,20 @@ lf2_status lf2_fft_execute(lf2_plan p, lf2_direction dir, const void *in, void *
     if ((st = check_device(p))) return st;
     hipStream_t s = (hipStream_t)stream;
     if (p->kind == LF2_R2C && dir == LF2_FORWARD) {
-        if ((st = run_x(p, 0, -1, x_args(p, in, out, true, false, true), s))) return st;
-        if ((st = run_strided(p, 1, -1, s_args(p, 1, out, out, EPI_STORE), kStridedGridCap, s, nullptr))) return st;
+        if (p->klay == 1 && in == out) {
+            // in place in the paper's order: the x pass moves row (y, z) to
+            // another row's place, so it writes the workspace and the y pass
+            // brings the spectrum back
+            WsLayout L = ws_layout(p, true, 0, false);
+            char *ws;
+            if ((st = get_workspace(p, L.total, &ws))) return st;
+            void *W = ws + L.w;
+            if ((st = run_x(p, 0, -1, x_args(p, in, W, true, false, true), s))) return st;
+            if ((st = run_strided(p, 1, -1, s_args(p, 1, W, out, EPI_STORE), kStridedGridCap, s, nullptr))) return st;
+        } else {
+            if ((st = run_x(p, 0, -1, x_args(p, in, out, true, false, true), s))) return st;
+            if ((st = run_strided(p, 1, -1, s_args(p, 1, out, out, EPI_STORE), kStridedGridCap, s, nullptr))) return st;
+        }
         return run_strided(p, 2, -1, s_args(p, 2, out, out, EPI_STORE), kStridedGridCap, s, nullptr);
     }
     if (p->kind == LF2_R2C) {

@@ -262,7 +262,7 @@ __device__ __forceinline__ void col_stage(c32 *buf, const c32 *gin, c32 *gout, i
 #pragma unroll
             for (int r = 0; r < R; ++r) {
                 if (SRC_G)
-                    v[i][r] = gv ? gload<NTM>(gin + (int64_t)(j + r * Q) * gs) : c32{0.f, 0.f};
+                    v[i][r] = gv ? gload<NTM>(gin + (int64_t)j * gs + (int64_t)(r * Q) * gs) : c32{0.f, 0.f};
                 else
                     v[i][r] = buf[l + (j + r * Q) * NL];
             }
@@ -286,7 +286,7 @@ __device__ __forceinline__ void col_stage(c32 *buf, const c32 *gin, c32 *gout, i
             if (DST_G) {
                 if (gv) {
 #pragma unroll
-                    for (int r = 0; r < R; ++r) gstore<NTM>(gout + (int64_t)(j + r * Q) * gs, v[i][r]);
+                    for (int r = 0; r < R; ++r) gstore<NTM>(gout + (int64_t)j * gs + (int64_t)(r * Q) * gs, v[i][r]);
                 }
             } else {
                 c32 *dst = buf + l + ((j / NS) * NS * R + k) * NL;
@@ -411,10 +411,108 @@ __device__ __forceinline__ void row_fft(c32 *buf, const c32 *gin, c32 *gout,
     }
 }
 
+// Radix of stage st, in the plan's order or (REV) in reverse order.  Any
+// order of the factors gives the same DFT; the reverse order lets a
+// transform start with the radix another one ended with (register hand-off
+// in the fused Poisson pass).
+__host__ __device__ constexpr int radix_sel(int L, int st, bool rev)
+{
+    return rev ? radix_at(L, nstages(L) - 1 - st) : radix_at(L, st);
+}
+
+// Butterflies per thread of a column stage with Q = L / R butterflies per
+// line and NT / NL threads per line.
+__host__ __device__ constexpr int col_nb(int L, int R, int NL, int NT)
+{
+    return (L / R + NT / NL - 1) / (NT / NL);
+}
+
+// First half of a column stage: load the butterfly inputs (global memory or
+// LDS), apply the stage twiddles and the radix-R DFT, and leave the R outputs
+// of each butterfly j in v (they belong at points j + r Q when this is the
+// last stage).  After LDS reads the block waits at a barrier, so LDS may be
+// rewritten afterwards.
+template <int L, int R, int NS, int S, int NL, int NT, bool SRC_G, bool NTM = false>
+__device__ __forceinline__ void col_stage_in(const c32 *buf, const c32 *gin, int64_t gs, bool gv,
+                                             const c32 *tw, int tid,
+                                             c32 (&v)[col_nb(L, R, NL, NT)][R])
+{
+    constexpr int Q = L / R;
+    constexpr int JS = NT / NL;
+    constexpr int NB = col_nb(L, R, NL, NT);
+    const int l = tid % NL;
+    const int j0 = tid / NL;
+#pragma unroll
+    for (int i = 0; i < NB; ++i) {
+        const int j = j0 + i * JS;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            if (Q % JS == 0 || j < Q) {
+                if (SRC_G)
+                    v[i][r] = gv ? gload<NTM>(gin + (int64_t)j * gs + (int64_t)(r * Q) * gs) : c32{0.f, 0.f};
+                else
+                    v[i][r] = buf[l + (j + r * Q) * NL];
+            } else {
+                v[i][r] = c32{0.f, 0.f};
+            }
+        }
+    }
+    if (!SRC_G) __syncthreads();
+#pragma unroll
+    for (int i = 0; i < NB; ++i) {
+        const int j = j0 + i * JS;
+        const int k = j % NS;
+        if (NS > 1) {
+#pragma unroll
+            for (int r = 1; r < R; ++r) {
+                c32 w = tw[r * k * (L / (NS * R))];
+                if (S > 0) w = conjg(w);
+                v[i][r] = mul(v[i][r], w);
+            }
+        }
+        Dft<R, S>::run(v[i]);
+    }
+}
+
+// Second half of a column stage: store v (as produced by col_stage_in with
+// the same L, R, NS) to global memory (last stage only) or to the LDS slots
+// the next stage reads; LDS writes end at a barrier.
+template <int L, int R, int NS, int NL, int NT, bool DST_G, bool NTM = false>
+__device__ __forceinline__ void col_stage_out(c32 *buf, c32 *gout, int64_t gs, bool gv, int tid,
+                                              const c32 (&v)[col_nb(L, R, NL, NT)][R])
+{
+    constexpr int Q = L / R;
+    constexpr int JS = NT / NL;
+    constexpr int NB = col_nb(L, R, NL, NT);
+    static_assert(!DST_G || NS * R == L, "only the last stage stores to global memory");
+    const int l = tid % NL;
+    const int j0 = tid / NL;
+#pragma unroll
+    for (int i = 0; i < NB; ++i) {
+        const int j = j0 + i * JS;
+        if (Q % JS == 0 || j < Q) {
+            const int k = j % NS;
+            if (DST_G) {
+                if (gv) {
+#pragma unroll
+                    for (int r = 0; r < R; ++r) gstore<NTM>(gout + (int64_t)j * gs + (int64_t)(r * Q) * gs, v[i][r]);
+                }
+            } else {
+                c32 *dst = buf + l + ((j / NS) * NS * R + k) * NL;
+#pragma unroll
+                for (int r = 0; r < R; ++r) dst[r * NS * NL] = v[i][r];
+            }
+        }
+    }
+    if (!DST_G) __syncthreads();
+}
+
 // Whole transform of the NL columns; SRC_G / DST_G select global input for
 // the first stage and global output for the last stage.  L = 1 is a copy.
+// REV runs the radices in reverse order; SKIP_LAST stops before the last
+// stage (whose inputs are then in LDS).
 template <int L, int S, int NL, int NT, bool SRC_G, bool DST_G, int ST = 0, int NS = 1,
-          bool NTM = false>
+          bool NTM = false, bool REV = false, bool SKIP_LAST = false>
 __device__ __forceinline__ void col_fft(c32 *buf, const c32 *gin, c32 *gout, int64_t gs, bool gv,
                                         const c32 *tw, int tid)
 {
@@ -430,11 +528,14 @@ __device__ __forceinline__ void col_fft(c32 *buf, const c32 *gin, c32 *gout, int
         }
         __syncthreads();
     } else if constexpr (NS < L) {
-        constexpr int R = radix_at(L, ST);
+        constexpr int R = radix_sel(L, ST, REV);
         constexpr bool first = ST == 0, last = NS * R == L;
-        col_stage<L, R, NS, S, NL, NT, first && SRC_G, last && DST_G, NTM>(buf, gin, gout, gs, gv,
-                                                                           tw, tid);
-        col_fft<L, S, NL, NT, SRC_G, DST_G, ST + 1, NS * R, NTM>(buf, gin, gout, gs, gv, tw, tid);
+        if constexpr (!(last && SKIP_LAST)) {
+            col_stage<L, R, NS, S, NL, NT, first && SRC_G, last && DST_G, NTM>(buf, gin, gout, gs,
+                                                                               gv, tw, tid);
+            col_fft<L, S, NL, NT, SRC_G, DST_G, ST + 1, NS * R, NTM, REV, SKIP_LAST>(buf, gin, gout,
+                                                                                    gs, gv, tw, tid);
+        }
     }
 }
 

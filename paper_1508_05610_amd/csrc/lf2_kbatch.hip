@@ -79,22 +79,17 @@ __global__ __launch_bounds__(kSThreads) __attribute__((amdgpu_waves_per_eu(4))) 
 {
     using T = STile<L, -1, true, kSThreads, true>;
     __shared__ __align__(16) char sm[T::BYTES];
-    extern __shared__ double dyn[];  // hist[nbins + 1], thresh[nbins + 1]
+    extern __shared__ double dyn[];  // hist[nbins + 1], edges[nbins + 1]
     const int tid = threadIdx.x;
     const BatchItem it = items[blockIdx.x];
     const BatchField &F = fields[it.field];
     const int nb = F.nbins;
     double *hist = dyn;
-    int64_t *thresh = (int64_t *)(dyn + (nb + 1));
+    BinEdge *edges = (BinEdge *)(dyn + (nb + 1));
     T::tables(F.z, sm, tid);
-    if (nb > 0) {
-        for (int i = tid; i <= nb; i += kSThreads) {
-            hist[i] = 0.0;
-            thresh[i] = F.z.mt.thresh[i];
-        }
-    }
+    if (nb > 0) load_edges(F.z.mt, hist, edges, tid, kSThreads);
     __syncthreads();
-    T::tile(F.z, it.tile, sm, tid, hist, thresh);
+    T::tile(F.z, it.tile, sm, tid, hist, edges);
     if (nb > 0) {
         for (int i = tid; i <= nb; i += kSThreads)
             F.partial[(int64_t)it.tile * (nb + 1) + i] = hist[i];

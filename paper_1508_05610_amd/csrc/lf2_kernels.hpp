@@ -493,12 +493,33 @@ __device__ __forceinline__ int bin_of(int64_t q, const int64_t *thresh, int nbin
     return b;
 }
 
-// The same bin for q, walking the thresholds from bin b (exact for any b).
-__device__ __forceinline__ int bin_step(int64_t q, int b, const int64_t *thresh, int nbins)
+// Bin edges (thresh[b], thresh[b + 1]) of bin b = 0..nbins as one 8-byte
+// LDS entry (hi = 2^32 - 1 past the last bin); thresholds are < 2^32.
+struct BinEdge {
+    uint32_t lo, hi;
+};
+
+// The same bin for q < 2^32 and nbins <= 4096 from the edge table: the FP32
+// estimate nbins sqrt(q / qmax) (cq = nbins^2 / qmax) is within 1e-3 of the
+// exact value, so one comparison each way against the estimated bin's
+// edges makes it exact.
+__device__ __forceinline__ int bin_edge(uint32_t q, int nbins, float cq, const BinEdge *edges)
 {
-    while (b + 1 < nbins && thresh[b + 1] <= q) ++b;
-    while (b > 0 && thresh[b] > q) --b;
-    return b;
+    int b = (int)__builtin_sqrtf((float)q * cq);  // 0..nbins
+    const BinEdge e = edges[b];
+    b += (q >= e.hi ? 1 : 0) - (q < e.lo ? 1 : 0);
+    return b < nbins - 1 ? b : nbins - 1;
+}
+
+// Zero the block's LDS histogram and fill its edge table.
+__device__ __forceinline__ void load_edges(const ModeTables &mt, double *hist, BinEdge *edges,
+                                           int tid, int nt)
+{
+    for (int i = tid; i <= mt.nbins; i += nt) {
+        hist[i] = 0.0;
+        edges[i] = BinEdge{(uint32_t)mt.thresh[i],
+                           i < mt.nbins ? (uint32_t)mt.thresh[i + 1] : 0xffffffffu};
+    }
 }
 
 // 1/d for d > 0 in FP64: hardware reciprocal refined by two Newton steps
@@ -511,10 +532,22 @@ __device__ __forceinline__ double rcp_f64(double d)
     return r;
 }
 
+// The thread index, hidden from the optimiser once per tile when OPAQUE: the
+// per-thread LDS and global offsets derived from it are then recomputed in
+// every tile instead of being hoisted out of the tile loop, where dozens of
+// them would stay live (and spill) across the fused pass.  The empty asm
+// statement emits no instruction.
+template <bool OPAQUE>
+__device__ __forceinline__ int opaque_tid(int tid)
+{
+    if constexpr (OPAQUE) asm volatile("" : "+v"(tid));
+    return tid;
+}
+
 // ============================================================ strided tiles
 // EPI = false: plain pass (no epilogue code, fewest registers);
 // EPI = true : last-axis pass with the binning / Poisson epilogue.
-// hist / thresh: LDS arrays of nbins + 1 entries (EPI with binning only);
+// hist / edges: LDS arrays of nbins + 1 entries (EPI with binning only);
 // the tile adds its w|F|^2 sums into hist.
 template <int L, int S, bool EPI, int NT, bool NTM = false>
 struct STile {
@@ -525,21 +558,21 @@ struct STile {
     static constexpr size_t O_BUF = 0, O_TW = al16(sizeof(c32) * L * B),
                             O_K2Z = al16(O_TW + sizeof(c32) * L),
                             O_QZ = O_K2Z + (EPI ? 8 * L : 0),
-                            BYTES = al16(O_QZ + (EPI ? 8 * L : 0));
+                            BYTES = al16(O_QZ + (EPI ? 4 * L : 0));
     static __device__ void tables(const SArgs &a, char *sm, int tid)
     {
         load_table((c32 *)(sm + O_TW), a.tw, L, tid, NT);
         if constexpr (EPI) {
             double *k2z = (double *)(sm + O_K2Z);
-            int64_t *qz = (int64_t *)(sm + O_QZ);
+            uint32_t *qz = (uint32_t *)(sm + O_QZ);  // q < 2^32 (checked at plan time)
             for (int i = tid; i < L; i += NT) {
                 if (a.epi & EPI_POISSON) k2z[i] = a.mt.k2[2][i];
-                if (a.epi & (EPI_PK | EPI_PK_AFTER)) qz[i] = a.mt.q[2][i];
+                if (a.epi & (EPI_PK | EPI_PK_AFTER)) qz[i] = (uint32_t)a.mt.q[2][i];
             }
         }
     }
     static __device__ void tile(const SArgs &a, int64_t t, char *sm, int tid, double *hist,
-                                const int64_t *thresh)
+                                const BinEdge *edges)
     {
         c32 *buf = (c32 *)(sm + O_BUF);
         const c32 *tw = (const c32 *)(sm + O_TW);
@@ -560,75 +593,123 @@ struct STile {
             col_fft<L, S, B, NT, true, true, 0, 1, NTM>(buf, gin, gout, a.stride, valid && store,
                                                          tw, tid);
         } else {
-            const bool pk = (a.epi & (EPI_PK | EPI_PK_AFTER)) != 0;
-            const int nb = a.mt.nbins;
-            const double inv_qmax = 1.0 / a.mt.qmax;
-            col_fft<L, S, B, NT, true, false, 0, 1, NTM>(buf, gin, nullptr, a.stride, valid, tw, tid);
-            // Epilogue on the last axis: thread (col, rg) walks a contiguous run
-            // of kz so that consecutive modes mostly share a bin.
-            constexpr int EP = (L + RPT - 1) / RPT;
-            const int kx = valid ? (int)(f % a.mt.nxk) : 0;
-            const int ky = valid ? (int)(f / a.mt.nxk) : 0;
-            const double wgt = (a.mt.half && !(kx == 0 || 2 * kx == a.mt.n0)) ? 2.0 : 1.0;
-            double k2xy = 0.0;
-            int64_t qxy = 0;
-            if (valid && (a.epi & EPI_POISSON)) k2xy = a.mt.k2[0][kx] + a.mt.k2[1][ky];
-            if (valid && pk) qxy = a.mt.q[0][kx] + a.mt.q[1][ky];
-            int cur = -1, bprev = -1;
-            double acc = 0.0;
-            for (int e = 0; e < EP; ++e) {
-                const int kz = rg * EP + e;
-                if (!valid || kz >= L) break;
-                c32 v = buf[kz * B + col];
-                const bool zero = (kx == 0 && ky == 0 && kz == 0);
-                int b = nb;
-                if (pk && !zero) {
-                    // consecutive kz move q a little: walk the thresholds from
-                    // the previous bin instead of a fresh estimate
-                    const int64_t q = qxy + ((const int64_t *)(sm + O_QZ))[kz];
-                    b = bprev < 0 ? bin_of(q, thresh, nb, inv_qmax) : bin_step(q, bprev, thresh, nb);
-                    bprev = b;
-                }
-                if (a.epi & EPI_PK) {
-                    const double p = wgt * ((double)v.x * v.x + (double)v.y * v.y);
-                    if (b != cur) {
-                        if (cur >= 0) atomicAdd(&hist[cur], acc);
-                        cur = b;
-                        acc = 0.0;
+            epilogue(a, sm, buf, tw, tid, col, rg, f, valid, store, gin, gout, hist, edges);
+        }
+        __syncthreads();
+    }
+
+    // Last-axis epilogue.  The forward transform stops with its last stage in
+    // registers: thread (col, j0) holds the modes kz = j + r QL of column col
+    // for its butterflies j.  The Poisson scale is applied there, and the
+    // backward transform runs its radices in reverse order, so that its first
+    // stage (radix RL, inputs at points j + r QL) starts from those same
+    // registers.  The P(k) sums need runs of consecutive kz (so that
+    // neighbouring modes share a bin): for them the modes are also written
+    // to LDS in natural order and thread (col, rg) walks kz in
+    // [rg EP, rg EP + EP).
+    static __device__ void epilogue(const SArgs &a, char *sm, c32 *buf, const c32 *tw, int tid,
+                                    int col, int rg, int64_t f, bool valid, bool store,
+                                    const c32 *gin, c32 *gout, double *hist,
+                                    const BinEdge *edges)
+    {
+        constexpr int NST = nstages(L);
+        constexpr int RL = NST == 0 ? 1 : radix_at(L, NST - 1);
+        constexpr int QL = L / RL;
+        constexpr int JS = NT / B;
+        constexpr int NB = col_nb(L, RL, B, NT);
+        const int j0 = tid / B;
+        c32 v[NB][RL];
+        if constexpr (NST <= 1) {
+            col_stage_in<L, RL, 1, S, B, NT, true, NTM>(buf, gin, a.stride, valid, tw, tid, v);
+        } else {
+            col_fft<L, S, B, NT, true, false, 0, 1, NTM, false, true>(buf, gin, nullptr, a.stride,
+                                                                      valid, tw, tid);
+            col_stage_in<L, RL, QL, S, B, NT, false>(buf, nullptr, 0, false, tw, tid, v);
+        }
+        const int kx = valid ? (int)(f % a.mt.nxk) : 0;
+        const int ky = valid ? (int)(f / a.mt.nxk) : 0;
+        const bool corner = kx == 0 && ky == 0;
+        if (a.epi & EPI_PK) {
+            col_stage_out<L, RL, QL, B, NT, false>(buf, nullptr, 0, false, tid, v);
+            bin_walk(a, sm, buf, col, rg, kx, ky, valid, hist, edges);
+        }
+        if (a.epi & EPI_POISSON) {
+            const double k2xy = valid ? a.mt.k2[0][kx] + a.mt.k2[1][ky] : 1.0;
+            const double *k2z = (const double *)(sm + O_K2Z);
+#pragma unroll
+            for (int i = 0; i < NB; ++i) {
+                const int j = j0 + i * JS;
+#pragma unroll
+                for (int r = 0; r < RL; ++r) {
+                    const int kz = j + r * QL;
+                    if (QL % JS == 0 || j < QL) {
+                        const double sc = (corner && kz == 0)
+                                              ? 0.0
+                                              : -a.mt.scale_n * rcp_f64(k2xy + k2z[kz]);
+                        v[i][r] = c32{(float)((double)v[i][r].x * sc),
+                                      (float)((double)v[i][r].y * sc)};
                     }
-                    acc += p;
                 }
-                if (a.epi & EPI_POISSON) {
-                    const double sc =
-                        zero ? 0.0 : -a.mt.scale_n * rcp_f64(k2xy + ((const double *)(sm + O_K2Z))[kz]);
-                    v = c32{(float)((double)v.x * sc), (float)((double)v.y * sc)};
-                    buf[kz * B + col] = v;
-                }
-                if (a.epi & EPI_PK_AFTER) {
-                    const double p = wgt * ((double)v.x * v.x + (double)v.y * v.y);
-                    if (b != cur) {
-                        if (cur >= 0) atomicAdd(&hist[cur], acc);
-                        cur = b;
-                        acc = 0.0;
-                    }
-                    acc += p;
-                }
-            }
-            if (cur >= 0) atomicAdd(&hist[cur], acc);
-            __syncthreads();
-            bool stored = false;
-            if constexpr (S < 0) {
-                if (a.epi & EPI_POISSON) {
-                    col_fft<L, +1, B, NT, false, true, 0, 1, NTM>(buf, nullptr, gout, a.stride,
-                                                                  valid && store, tw, tid);
-                    stored = true;
-                }
-            }
-            if (store && !stored && valid) {
-                for (int row = rg; row < L; row += RPT)
-                    gout[(int64_t)row * a.stride] = buf[row * B + col];
             }
         }
+        if (a.epi & EPI_PK_AFTER) {
+            col_stage_out<L, RL, QL, B, NT, false>(buf, nullptr, 0, false, tid, v);
+            bin_walk(a, sm, buf, col, rg, kx, ky, valid, hist, edges);
+        }
+        if constexpr (S < 0) {
+            if (a.epi & EPI_POISSON) {
+                // backward transform: first stage (radix RL, no twiddles) from
+                // the registers, the rest through LDS in reverse radix order
+#pragma unroll
+                for (int i = 0; i < NB; ++i) Dft<RL, +1>::run(v[i]);
+                if constexpr (NST <= 1) {
+                    col_stage_out<L, RL, 1, B, NT, true, NTM>(buf, gout, a.stride, valid && store,
+                                                              tid, v);
+                } else {
+                    col_stage_out<L, RL, 1, B, NT, false>(buf, nullptr, 0, false, tid, v);
+                    col_fft<L, +1, B, NT, false, true, 1, RL, NTM, true>(
+                        buf, nullptr, gout, a.stride, valid && store, tw, tid);
+                }
+                return;
+            }
+        }
+        if (store)  // spectrum out: the modes are still in registers
+            col_stage_out<L, RL, QL, B, NT, true, NTM>(buf, gout, a.stride, valid, tid, v);
+    }
+
+    // P(k) partial sums of the modes in LDS (natural order): thread (col, rg)
+    // walks its run of kz, computes each mode's exact bin and adds w |F|^2
+    // into the block's LDS histogram when the bin changes.  Ends at a
+    // barrier, so LDS may be rewritten afterwards.
+    static __device__ void bin_walk(const SArgs &a, char *sm, const c32 *buf, int col, int rg,
+                                    int kx, int ky, bool valid, double *hist,
+                                    const BinEdge *edges)
+    {
+        constexpr int EP = (L + RPT - 1) / RPT;
+        const int nb = a.mt.nbins;
+        const float cq = (float)((double)nb * nb / a.mt.qmax);
+        // the half-spectrum weight is the same for the whole column
+        const double wgt = (a.mt.half && !(kx == 0 || 2 * kx == a.mt.n0)) ? 2.0 : 1.0;
+        const uint32_t qxy = valid ? (uint32_t)(a.mt.q[0][kx] + a.mt.q[1][ky]) : 0u;
+        const uint32_t *qz = (const uint32_t *)(sm + O_QZ);
+        int cur = -1;
+        double acc = 0.0;
+#pragma unroll 4
+        for (int e = 0; e < EP; ++e) {
+            const int kz = rg * EP + e;
+            if (!valid || kz >= L) break;
+            const c32 v = buf[kz * B + col];
+            // slot nbins: the zero mode (kept for the Parseval sum)
+            const int b = (kx == 0 && ky == 0 && kz == 0) ? nb : bin_edge(qxy + qz[kz], nb, cq, edges);
+            const double p = (double)v.x * v.x + (double)v.y * v.y;
+            if (b != cur) {
+                if (cur >= 0) atomicAdd(&hist[cur], wgt * acc);
+                cur = b;
+                acc = 0.0;
+            }
+            acc += p;
+        }
+        if (cur >= 0) atomicAdd(&hist[cur], wgt * acc);
         __syncthreads();
     }
 };
@@ -778,19 +859,14 @@ __global__ __launch_bounds__(kSThreads) __attribute__((amdgpu_waves_per_eu(4))) 
     constexpr int NT = kSThreads;
     constexpr int B = T::B;
     __shared__ __align__(16) char sm[T::BYTES];
-    extern __shared__ double dyn[];  // hist[nbins + 1], thresh[nbins + 1]
+    extern __shared__ double dyn[];  // hist[nbins + 1], edges[nbins + 1]
     const int tid = threadIdx.x;
     T::tables(a, sm, tid);
     const bool pk = EPI && (a.epi & (EPI_PK | EPI_PK_AFTER)) != 0;
     const int nb = a.mt.nbins;
     double *hist = dyn;
-    int64_t *thresh = (int64_t *)(dyn + (nb + 1));
-    if (pk) {
-        for (int i = tid; i <= nb; i += NT) {
-            hist[i] = 0.0;
-            thresh[i] = a.mt.thresh[i];
-        }
-    }
+    BinEdge *edges = (BinEdge *)(dyn + (nb + 1));
+    if (pk) load_edges(a.mt, hist, edges, tid, NT);
     __syncthreads();
     const int64_t ntiles = (a.ncols + B - 1) / B;
     // XCD-aware walk over virtual block ids vb = blockIdx.x + i * G (G is a
@@ -805,7 +881,7 @@ __global__ __launch_bounds__(kSThreads) __attribute__((amdgpu_waves_per_eu(4))) 
         const int64_t lb = vb / 8;
         const int64_t t = ((lb / K) * 8 + (vb % 8)) * K + lb % K;
         if (t >= ntiles) continue;  // uniform over the block
-        T::tile(a, t, sm, tid, hist, thresh);
+        T::tile(a, t, sm, opaque_tid<EPI>(tid), hist, edges);
     }
     if (pk) {
         __syncthreads();
