@@ -1,7 +1,10 @@
 // lf2_batch.cpp -- batched Poisson solves (with optional fused power spectra)
 // on many lattices of different sizes.  Work items (field, tile) are grouped
-// by pass and line length; one launch per group, in pass order, plus one
-// finalize launch for the power spectra, all captured in one hipGraph.
+// by pass and line length; one launch per group plus one finalize launch for
+// the power spectra, all captured in one hipGraph.  A group waits only for
+// the groups of the previous pass that hold its fields, so groups of one
+// pass (disjoint fields) and groups of consecutive passes on unrelated
+// fields run concurrently and fill each other's tails.
 #include <stdio.h>
 #include <string.h>
 
@@ -18,6 +21,7 @@ using namespace lf2::host;
 namespace {
 struct Group {
     int pass, len, offset, count;
+    std::vector<int> fields;
 };
 }  // namespace
 
@@ -59,16 +63,61 @@ static void batch_free(lf2_batch b)
     delete b;
 }
 
-// Enqueue one execution: grouped launches in pass order, then the finalize.
-static hipError_t enqueue(lf2_batch b, hipStream_t s)
+// Capture one execution into b->graph from the origin stream cs: every group
+// on a stream of its own (joined into the capture through events) after the
+// groups of the previous pass that share a field with it; the finalize after
+// all fused z groups; the origin stream finally joins every group.
+static hipError_t capture(lf2_batch b, hipStream_t cs)
 {
-    for (const Group &g : b->groups) {
-        hipError_t e = batch_group_launch(g.pass, g.len, b->d_fields, b->d_items + g.offset,
-                                          g.count, b->nbins, s);
-        if (e != hipSuccess) return e;
+    const size_t ng = b->groups.size();
+    std::vector<hipStream_t> st(ng, nullptr);
+    std::vector<hipEvent_t> done(ng, nullptr);
+    hipEvent_t start = nullptr;
+    hipError_t e = hipEventCreateWithFlags(&start, hipEventDisableTiming);
+    for (size_t g = 0; g < ng && e == hipSuccess; ++g) {
+        e = hipStreamCreateWithFlags(&st[g], hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&done[g], hipEventDisableTiming);
     }
-    if (b->nbins > 0) return batch_finalize_launch(b->d_fields, b->nfields, s);
-    return hipSuccess;
+    bool capturing = false;
+    if (e == hipSuccess) e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    capturing = e == hipSuccess;
+    if (e == hipSuccess) e = hipEventRecord(start, cs);
+    // group of (pass, field), filled pass by pass
+    std::vector<int> owner((size_t)BP_COUNT * b->nfields, -1);
+    for (size_t g = 0; g < ng && e == hipSuccess; ++g) {
+        const Group &G = b->groups[g];
+        std::vector<int> deps;
+        for (int f : G.fields) {
+            owner[(size_t)G.pass * b->nfields + f] = (int)g;
+            const int h = G.pass > BP_XF ? owner[(size_t)(G.pass - 1) * b->nfields + f] : -1;
+            bool seen = false;
+            for (int d : deps) seen = seen || d == h;
+            if (!seen) deps.push_back(h);
+        }
+        for (int h : deps)
+            if (e == hipSuccess) e = hipStreamWaitEvent(st[g], h < 0 ? start : done[h], 0);
+        if (e == hipSuccess)
+            e = batch_group_launch(G.pass, G.len, b->d_fields, b->d_items + G.offset, G.count,
+                                   b->nbins, st[g]);
+        if (e == hipSuccess) e = hipEventRecord(done[g], st[g]);
+    }
+    if (b->nbins > 0) {
+        for (size_t g = 0; g < ng && e == hipSuccess; ++g)
+            if (b->groups[g].pass == BP_Z) e = hipStreamWaitEvent(cs, done[g], 0);
+        if (e == hipSuccess) e = batch_finalize_launch(b->d_fields, b->nfields, cs);
+    }
+    for (size_t g = 0; g < ng && e == hipSuccess; ++g) e = hipStreamWaitEvent(cs, done[g], 0);
+    if (capturing) {
+        const hipError_t e2 = hipStreamEndCapture(cs, &b->graph);
+        if (e == hipSuccess) e = e2;
+    }
+    // streams and events only shape the capture; the graph does not use them
+    for (size_t g = 0; g < ng; ++g) {
+        if (done[g]) (void)hipEventDestroy(done[g]);
+        if (st[g]) (void)hipStreamDestroy(st[g]);
+    }
+    if (start) (void)hipEventDestroy(start);
+    return e;
 }
 
 extern "C" {
@@ -221,7 +270,7 @@ lf2_status lf2_batch_plan(lf2_batch *out, int32_t nfields, const lf2_lattice *la
             by_len[len].push_back(f);
         }
         for (auto &kv : by_len) {
-            Group g{pass, kv.first, (int)items.size(), 0};
+            Group g{pass, kv.first, (int)items.size(), 0, kv.second};
             for (int f : kv.second)
                 for (int t = 0; t < tiles[f][pass]; ++t) items.push_back(BatchItem{f, t});
             g.count = (int)items.size() - g.offset;
@@ -244,12 +293,7 @@ lf2_status lf2_batch_plan(lf2_batch *out, int32_t nfields, const lf2_lattice *la
     // graph of the grouped launches
     hipStream_t cs = nullptr;
     e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
-    if (e == hipSuccess) e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
-    if (e == hipSuccess) {
-        hipError_t e1 = enqueue(b, cs);
-        e = hipStreamEndCapture(cs, &b->graph);
-        if (e == hipSuccess) e = e1;
-    }
+    if (e == hipSuccess) e = capture(b, cs);
     if (e == hipSuccess) e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0);
     if (cs) (void)hipStreamDestroy(cs);
     if (e != hipSuccess) {
