@@ -572,19 +572,23 @@ def main():
     table = _lib.profile_table()
     _lib.lf2_profile_enable(False)
 
-    # ---- per-op times (separate loop, events around each op)
-    per_op = {}
-    reps = max(3, args.steps)
+    # ---- per-op times (separate loop, events around each repetition):
+    # median, p10 and p90 over >= 20 repetitions
+    per_op, per_op_p10, per_op_p90 = {}, {}, {}
+    reps = max(20, args.steps)
     for name, fn, _ in ops:
-        a = torch.cuda.Event(enable_timing=True)
-        b = torch.cuda.Event(enable_timing=True)
+        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+               for _ in range(reps)]
         torch.cuda.synchronize()
-        a.record(stream)
-        for _ in range(reps):
+        for a, b in evs:
+            a.record(stream)
             fn()
-        b.record(stream)
+            b.record(stream)
         torch.cuda.synchronize()
-        per_op[name] = a.elapsed_time(b) / reps
+        t = np.array([a.elapsed_time(b) for a, b in evs])
+        per_op[name] = float(np.median(t))
+        per_op_p10[name] = float(np.percentile(t, 10))
+        per_op_p90[name] = float(np.percentile(t, 90))
 
     step_bytes = sum(v[2] for v in table.values()) / args.steps
     # group the per-pass records by kernel symbol (the part before the space)
@@ -626,6 +630,9 @@ def main():
         "plan_tuning": tuning,
         "gbps_algorithmic": round(step_bytes / (ms_step * 1e-3) / 1e9, 1),
         "ops_ms": {k: round(v, 4) for k, v in per_op.items()},
+        "ops_ms_p10": {k: round(v, 4) for k, v in per_op_p10.items()},
+        "ops_ms_p90": {k: round(v, 4) for k, v in per_op_p90.items()},
+        "ops_reps": reps,
         "roofline": {
             "bound": "hbm", "kernel": dname,
             "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -674,6 +681,19 @@ def main():
                 "sample": f"one r2c forward + one c2r backward of the {S}^3 field "
                           f"(2 of the {n_transforms} transforms of a step); "
                           f"{t1 - t0:.2f} s + {t2 - t1:.2f} s",
+            }
+            # the same oracle on one thread, r2c forward of a quarter-size cube
+            s1 = S // 2
+            nthreads = oracle.num_threads()
+            oracle.set_num_threads(1)
+            t3 = time.perf_counter()
+            oracle.r2c(f64[:s1, :s1, :s1].copy())
+            t4 = time.perf_counter()
+            oracle.set_num_threads(nthreads)
+            n1_ = s1 ** 3
+            res["cpu_baseline"]["single_thread"] = {
+                "value": round(5.0 * n1_ * math.log2(n1_) / (t4 - t3) / 1e9, 3), "unit": "GFLOP/s",
+                "cores": 1, "sample": f"one r2c forward of a {s1}^3 sub-cube: {t4 - t3:.2f} s",
             }
         if not args.no_errors:
             def rel_l2(a, b):

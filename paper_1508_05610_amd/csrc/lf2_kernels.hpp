@@ -505,7 +505,8 @@ struct BinEdge {
 // edges makes it exact.
 __device__ __forceinline__ int bin_edge(uint32_t q, int nbins, float cq, const BinEdge *edges)
 {
-    int b = (int)__builtin_sqrtf((float)q * cq);  // 0..nbins
+    // hardware square root (about 1 ulp; the correction below absorbs it)
+    int b = (int)__builtin_amdgcn_sqrtf((float)q * cq);  // 0..nbins
     const BinEdge e = edges[b];
     b += (q >= e.hi ? 1 : 0) - (q < e.lo ? 1 : 0);
     return b < nbins - 1 ? b : nbins - 1;
@@ -692,22 +693,39 @@ struct STile {
         const double wgt = (a.mt.half && !(kx == 0 || 2 * kx == a.mt.n0)) ? 2.0 : 1.0;
         const uint32_t qxy = valid ? (uint32_t)(a.mt.q[0][kx] + a.mt.q[1][ky]) : 0u;
         const uint32_t *qz = (const uint32_t *)(sm + O_QZ);
+        const bool corner = kx == 0 && ky == 0;
+        // every row group's run has EP modes when RPT EP = L; otherwise the
+        // last runs are shorter or empty (n <= 0)
+        constexpr bool EXACT = RPT * EP == L;
+        const int n = EXACT ? EP : (L - rg * EP < EP ? L - rg * EP : EP);
         int cur = -1;
         double acc = 0.0;
+        if (valid && n > 0) {
+            // selects, not branches, for the zero mode and the bin; the next
+            // mode's LDS reads are issued before this mode's work
+            int kz = rg * EP;
+            c32 v = buf[kz * B + col];
+            uint32_t q = qxy + qz[kz];
 #pragma unroll 4
-        for (int e = 0; e < EP; ++e) {
-            const int kz = rg * EP + e;
-            if (!valid || kz >= L) break;
-            const c32 v = buf[kz * B + col];
-            // slot nbins: the zero mode (kept for the Parseval sum)
-            const int b = (kx == 0 && ky == 0 && kz == 0) ? nb : bin_edge(qxy + qz[kz], nb, cq, edges);
-            const double p = (double)v.x * v.x + (double)v.y * v.y;
-            if (b != cur) {
-                if (cur >= 0) atomicAdd(&hist[cur], wgt * acc);
-                cur = b;
-                acc = 0.0;
+            for (int e = 0; e < EP; ++e) {
+                if (!EXACT && e >= n) break;
+                const int kzn = kz + 1 < L ? kz + 1 : kz;  // in bounds; unused past the run
+                const c32 vn = buf[kzn * B + col];
+                const uint32_t qn = qxy + qz[kzn];
+                const int bq = bin_edge(q, nb, cq, edges);
+                // slot nbins: the zero mode (kept for the Parseval sum)
+                const int b = (corner && kz == 0) ? nb : bq;
+                const double p = (double)v.x * v.x + (double)v.y * v.y;
+                v = vn;
+                q = qn;
+                kz = kzn;
+                if (b != cur) {
+                    if (cur >= 0) atomicAdd(&hist[cur], wgt * acc);
+                    cur = b;
+                    acc = 0.0;
+                }
+                acc += p;
             }
-            acc += p;
         }
         if (cur >= 0) atomicAdd(&hist[cur], wgt * acc);
         __syncthreads();
