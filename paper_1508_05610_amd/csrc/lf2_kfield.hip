@@ -87,13 +87,15 @@ hipError_t launch_update_halo(void *field, const int64_t n[3], int64_t h, int64_
 // out(x)[3 c + i] = (f(x + e_i) - f(x))[c] / dx.  The input's halo (width
 // h >= 1) supplies the neighbours across the upper faces; the output has
 // the same halo layout and only its interior is written.  A row of the
-// field is a run of N0 ncomp words (site-major, components inner); a block
-// covers 256 consecutive words of one row and marches through ZC planes,
-// carrying f(z + 1) over as the next plane's f(z).  Its x neighbour is the
-// word ncomp further on and its y neighbour the same word of the next row,
-// both loaded by this or a neighbouring block at the same time (cache
-// hits).  The three results of a word are staged through LDS so that every
-// store of a wave is contiguous.
+// field is a run of N0 ncomp words (site-major, components inner).  A block
+// covers 256 consecutive words of GY consecutive rows and marches through
+// ZC planes: per plane it reads GY + 1 rows of the following plane (the
+// extra row is the y neighbour of the group's last row), which later serve
+// as the current plane, so HBM sees each input row (GY + 1) / GY times.
+// Those reads run one plane ahead of the arithmetic.  The x neighbour is
+// the word ncomp further on (a cache hit: this or the next block reads it
+// in the same plane).  The three results of a word are staged through LDS
+// so that every store of a wave is contiguous.
 struct GradArgs {
     const float *in;
     float *out;
@@ -104,48 +106,67 @@ struct GradArgs {
 };
 
 constexpr int kGradThreads = 256;
+constexpr int kGradRows = 8;  // GY
 
 __global__ __launch_bounds__(kGradThreads) void k_gradient(GradArgs a)
 {
-    __shared__ float stage[3 * kGradThreads];
+    constexpr int GY = kGradRows;
+    __shared__ float stage[GY][3 * kGradThreads];
     const int tid = threadIdx.x;
     const int64_t rowwords = a.n0 * a.nc;
     const int64_t w0 = (int64_t)blockIdx.x * kGradThreads;
     const int64_t w = w0 + tid;
     const bool ok = w < rowwords;
-    const int64_t y = blockIdx.y;
+    const int64_t y0 = (int64_t)blockIdx.y * GY;
+    const int ny = (int)(a.n1 - y0 < GY ? a.n1 - y0 : GY);  // rows of this group
     const int64_t z0 = (int64_t)blockIdx.z * a.zc;
     const int64_t z1 = z0 + a.zc < a.n2 ? z0 + a.zc : a.n2;
     const int64_t sy = a.p0 * a.nc, sz = a.p1 * a.p0 * a.nc;  // input strides (words)
-    const int64_t osz = sz * 3;                                 // output plane stride
-    const int64_t ib = ((a.h + z0) * a.p1 + a.h + y) * sy + a.h * a.nc;
-    const int64_t ob = ((a.h + z0) * a.p1 + a.h + y) * (sy * 3) + a.h * a.nc * 3;
-    const float *f = a.in + ib + (ok ? w : 0);
-    float *o = a.out + ob + 3 * w0;
+    // input word w of interior row y0 + i of plane z0; rows past the group
+    // are read from row min(y0 + i, n1), which exists (upper halo row n1)
+    const float *f = a.in + ((a.h + z0) * a.p1 + a.h + y0) * sy + a.h * a.nc + (ok ? w : 0);
+    int64_t roff[GY + 1];
+#pragma unroll
+    for (int i = 0; i <= GY; ++i) roff[i] = (i <= ny ? i : ny) * sy;
+    // c: plane z, nx: plane z + 1 (both rows y0 .. y0 + GY); xn: x neighbours in plane z
+    float c[GY + 1], nx[GY + 1], xn[GY];
+#pragma unroll
+    for (int i = 0; i <= GY; ++i) {
+        c[i] = ok ? f[roff[i]] : 0.f;
+        nx[i] = ok ? f[sz + roff[i]] : 0.f;
+    }
+#pragma unroll
+    for (int i = 0; i < GY; ++i) xn[i] = ok ? f[roff[i] + a.nc] : 0.f;
     const int nst = (int)(3 * (rowwords - w0 < kGradThreads ? rowwords - w0 : kGradThreads));
-    float cur = ok ? f[0] : 0.f;
-    // the next plane's x and y neighbours are loaded one step ahead
-    float fx = ok ? f[a.nc] : 0.f, fy = ok ? f[sy] : 0.f;
+    float *o = a.out + ((a.h + z0) * a.p1 + a.h + y0) * (sy * 3) + a.h * a.nc * 3 + 3 * w0;
     for (int64_t z = z0; z < z1; ++z) {
-        float nxt = 0.f, fx2 = 0.f, fy2 = 0.f;
-        if (ok) {
-            nxt = f[sz];
-            if (z + 1 < z1) {
-                fx2 = f[sz + a.nc];
-                fy2 = f[sz + sy];
-            }
+        // the next step's planes, read only while z + 2 <= z1 <= n2 (the
+        // upper halo plane n2 exists)
+        float nn[GY + 1], xn2[GY];
+        const bool more = z + 1 < z1;
+#pragma unroll
+        for (int i = 0; i <= GY; ++i) nn[i] = (ok && more) ? f[2 * sz + roff[i]] : 0.f;
+#pragma unroll
+        for (int i = 0; i < GY; ++i) xn2[i] = (ok && more) ? f[sz + roff[i] + a.nc] : 0.f;
+#pragma unroll
+        for (int i = 0; i < GY; ++i) {
+            stage[i][3 * tid + 0] = (xn[i] - c[i]) * a.inv_dx;
+            stage[i][3 * tid + 1] = (c[i + 1] - c[i]) * a.inv_dx;
+            stage[i][3 * tid + 2] = (nx[i] - c[i]) * a.inv_dx;
         }
-        stage[3 * tid + 0] = (fx - cur) * a.inv_dx;
-        stage[3 * tid + 1] = (fy - cur) * a.inv_dx;
-        stage[3 * tid + 2] = (nxt - cur) * a.inv_dx;
         __syncthreads();
-        for (int j = tid; j < nst; j += kGradThreads) o[j] = stage[j];
+        for (int i = 0; i < ny; ++i)
+            for (int j = tid; j < nst; j += kGradThreads) o[i * (sy * 3) + j] = stage[i][j];
         __syncthreads();
-        cur = nxt;
-        fx = fx2;
-        fy = fy2;
+#pragma unroll
+        for (int i = 0; i <= GY; ++i) {
+            c[i] = nx[i];
+            nx[i] = nn[i];
+        }
+#pragma unroll
+        for (int i = 0; i < GY; ++i) xn[i] = xn2[i];
         f += sz;
-        o += osz;
+        o += sz * 3;
     }
 }
 
@@ -165,8 +186,8 @@ hipError_t launch_gradient(const float *in, float *out, const int64_t n[3], int6
     a.inv_dx = (float)(1.0 / dx);
     a.zc = 16;
     const int64_t rowwords = n[0] * nc;
-    dim3 grid((unsigned)((rowwords + kGradThreads - 1) / kGradThreads), (unsigned)n[1],
-              (unsigned)((n[2] + a.zc - 1) / a.zc));
+    dim3 grid((unsigned)((rowwords + kGradThreads - 1) / kGradThreads),
+              (unsigned)((n[1] + kGradRows - 1) / kGradRows), (unsigned)((n[2] + a.zc - 1) / a.zc));
     hipLaunchKernelGGL(k_gradient, grid, dim3(kGradThreads), 0, s, a);
     return hipGetLastError();
 }
