@@ -367,7 +367,9 @@ def bench_paper_shapes(args, torch, lf2):
     gen = torch.Generator(device=dev)
     gen.manual_seed(7)
     rows = []
-    cases = [(n, nc) for n in (512, 1024) for nc in (1, 2, 3, 6)] + [(2048, 1)]
+    sizes = [int(v) for v in args.paper_sizes.split(",")]
+    cases = [(n, nc) for n in (512, 1024) if n in sizes for nc in (1, 2, 3, 6)]
+    cases += [(2048, 1)] if 2048 in sizes else []
     for n, nc in cases:
         for kind in (lf2.LF2_R2C, lf2.LF2_C2C):
             if n == 2048 and kind == lf2.LF2_C2C:
@@ -443,6 +445,8 @@ def main():
     ap.add_argument("--paper-shapes", action="store_true",
                     help="also time the paper's FFT benchmark shapes (512^3 and 1024^3 x 1/2/3/6 "
                          "components, 2048^3 x 1)")
+    ap.add_argument("--paper-sizes", default="512,1024,2048",
+                    help="lattice sizes of --paper-shapes to run (comma-separated)")
     ap.add_argument("--serve-requests", type=int, default=1000)
     ap.add_argument("--tuning", default=None,
                     help="fixed strided-pass tuning instead of autotuning, e.g. "

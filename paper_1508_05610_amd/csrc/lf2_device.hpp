@@ -311,12 +311,34 @@ __device__ __forceinline__ void col_stage(c32 *buf, const c32 *gin, c32 *gout, i
 // memory, so the first stage's global loads (point j + r Q) and the last
 // stage's global stores are contiguous across a wave.  Only rows < nvalid
 // exist in memory.
+// PACK (real rows of the r2c / c2r x pass): the global side is a float
+// array with row offsets in floats, and point p of component c is the pair
+// (f[2p][c], f[2p + 1][c]) = floats (2p) NC + c and (2p + 1) NC + c, loaded
+// (first stage) or stored (last stage) as two floats.
 
 __host__ __device__ constexpr int lpad(int p) { return p + (p >> 4); }
 __host__ __device__ constexpr int row_pitch(int npoints) { return lpad(npoints - 1) + 1; }
 
+template <bool NTM>
+__device__ __forceinline__ float gloadf(const float *p)
+{
+    if constexpr (NTM)
+        return __builtin_nontemporal_load(p);
+    else
+        return *p;
+}
+
+template <bool NTM>
+__device__ __forceinline__ void gstoref(float *p, float v)
+{
+    if constexpr (NTM)
+        __builtin_nontemporal_store(v, p);
+    else
+        *p = v;
+}
+
 template <int L, int R, int NS, int S, int RB, int NC, int LP, int NT, bool SRC_G, bool DST_G,
-          bool NTM = false>
+          bool NTM = false, bool PACK = false>
 __device__ __forceinline__ void row_stage(c32 *buf, const c32 *gin, c32 *gout,
                                           const int64_t *rowoff_in, const int64_t *rowoff_out,
                                           int nvalid, const c32 *tw, int tid, double *ssq)
@@ -335,11 +357,16 @@ __device__ __forceinline__ void row_stage(c32 *buf, const c32 *gin, c32 *gout,
             const int l = q * NC + c;
 #pragma unroll
             for (int r = 0; r < R; ++r) {
-                if (SRC_G)
+                if (SRC_G && PACK) {
+                    const float *fp = (const float *)gin + rowoff_in[q] + 2 * (j + r * Q) * NC + c;
+                    v[i][r] = q < nvalid ? c32{gloadf<NTM>(fp), gloadf<NTM>(fp + NC)}
+                                         : c32{0.f, 0.f};
+                } else if (SRC_G) {
                     v[i][r] = q < nvalid ? gload<NTM>(gin + rowoff_in[q] + (j + r * Q) * NC + c)
                                          : c32{0.f, 0.f};
-                else
+                } else {
                     v[i][r] = buf[l * LP + lpad(j + r * Q)];
+                }
             }
             if (SRC_G && ssq) {
 #pragma unroll
@@ -366,7 +393,16 @@ __device__ __forceinline__ void row_stage(c32 *buf, const c32 *gin, c32 *gout,
                 }
             }
             Dft<R, S>::run(v[i]);
-            if (DST_G) {
+            if (DST_G && PACK) {
+                if (q < nvalid) {
+#pragma unroll
+                    for (int r = 0; r < R; ++r) {
+                        float *fp = (float *)gout + rowoff_out[q] + 2 * (j + r * Q) * NC + c;
+                        gstoref<NTM>(fp, v[i][r].x);
+                        gstoref<NTM>(fp + NC, v[i][r].y);
+                    }
+                }
+            } else if (DST_G) {
                 if (q < nvalid) {
 #pragma unroll
                     for (int r = 0; r < R; ++r)
@@ -384,7 +420,7 @@ __device__ __forceinline__ void row_stage(c32 *buf, const c32 *gin, c32 *gout,
 }
 
 template <int L, int S, int RB, int NC, int LP, int NT, bool SRC_G, bool DST_G, int ST = 0,
-          int NS = 1, bool NTM = false>
+          int NS = 1, bool NTM = false, bool PACK = false>
 __device__ __forceinline__ void row_fft(c32 *buf, const c32 *gin, c32 *gout,
                                         const int64_t *rowoff_in, const int64_t *rowoff_out,
                                         int nvalid, const c32 *tw, int tid, double *ssq = nullptr)
@@ -392,9 +428,21 @@ __device__ __forceinline__ void row_fft(c32 *buf, const c32 *gin, c32 *gout,
     if constexpr (L == 1) {
         for (int b = tid; b < RB * NC; b += NT) {
             const int c = b % NC, q = b / NC;
-            c32 v = SRC_G ? (q < nvalid ? gin[rowoff_in[q] + c] : c32{0.f, 0.f}) : buf[b * LP];
+            c32 v = buf[b * LP];
+            if (SRC_G && PACK) {
+                const float *fp = (const float *)gin + rowoff_in[q] + c;
+                v = q < nvalid ? c32{fp[0], fp[NC]} : c32{0.f, 0.f};
+            } else if (SRC_G) {
+                v = q < nvalid ? gin[rowoff_in[q] + c] : c32{0.f, 0.f};
+            }
             if (SRC_G && ssq) *ssq += (double)v.x * v.x + (double)v.y * v.y;
-            if (DST_G) {
+            if (DST_G && PACK) {
+                if (q < nvalid) {
+                    float *fp = (float *)gout + rowoff_out[q] + c;
+                    fp[0] = v.x;
+                    fp[NC] = v.y;
+                }
+            } else if (DST_G) {
                 if (q < nvalid) gout[rowoff_out[q] + c] = v;
             } else {
                 buf[b * LP] = v;
@@ -404,9 +452,9 @@ __device__ __forceinline__ void row_fft(c32 *buf, const c32 *gin, c32 *gout,
     } else if constexpr (NS < L) {
         constexpr int R = radix_at(L, ST);
         constexpr bool first = ST == 0, last = NS * R == L;
-        row_stage<L, R, NS, S, RB, NC, LP, NT, first && SRC_G, last && DST_G, NTM>(
+        row_stage<L, R, NS, S, RB, NC, LP, NT, first && SRC_G, last && DST_G, NTM, PACK>(
             buf, gin, gout, rowoff_in, rowoff_out, nvalid, tw, tid, ssq);
-        row_fft<L, S, RB, NC, LP, NT, SRC_G, DST_G, ST + 1, NS * R, NTM>(
+        row_fft<L, S, RB, NC, LP, NT, SRC_G, DST_G, ST + 1, NS * R, NTM, PACK>(
             buf, gin, gout, rowoff_in, rowoff_out, nvalid, tw, tid, ssq);
     }
 }

@@ -92,8 +92,9 @@ __device__ __forceinline__ void load_table(c32 *dst, const void *src, int n, int
 
 // =================================================================== x tiles
 
-// ---- general r2c: components de-interleaved through LDS (padded lines of
-// the row engine; complex point n of a line holds reals 2n and 2n + 1)
+// ---- general r2c (interleaved components, any float offsets): the first
+// stage loads component c's packed point n = (f[2n][c], f[2n + 1][c]) as two
+// floats straight from the row; one padded LDS line per (row, component)
 template <int M, int NC, int NT>
 struct XR2CGen {
     static constexpr int RB = x_rb(M, NC, NT), NL = RB * NC, N0 = 2 * M, LP = row_pitch(M),
@@ -116,46 +117,35 @@ struct XR2CGen {
         const int64_t r0 = blk * RB;
         row_bases<RB, NT>(ib, ob, a, r0, tid);
         __syncthreads();
-        const float *in = (const float *)a.in;
-        float *fb = (float *)buf;
+        const int nv = rows_valid<RB>(a, r0);
+        // the first stage reads each component's packed pairs straight from
+        // the real rows (two float loads per point; no alignment needed)
         double ss = 0.0;
-        constexpr int NE = RB * N0 * NC;
-#pragma unroll
-        for (int i = 0; i < (NE + NT - 1) / NT; ++i) {
-            const int idx = tid + i * NT;
-            if (idx < NE) {
-                const int row = idx / (N0 * NC);
-                const int rem = idx - row * (N0 * NC);
-                const int x = rem / NC;
-                const int c = rem - x * NC;
-                float v = 0.f;
-                if (r0 + row < a.nrows) v = in[ib[row] + rem];
-                fb[2 * ((row * NC + c) * LP + lpad(x >> 1)) + (x & 1)] = v;
-                ss += (double)v * (double)v;
-            }
-        }
+        row_fft<M, -1, RB, NC, LP, NT, true, false, 0, 1, true, true>(
+            buf, (const c32 *)a.in, nullptr, ib, nullptr, nv, tw, tid, sumsq ? &ss : nullptr);
         if (sumsq) block_sum_f64<NT>(ss, sumsq, (double *)(sm + O_RED));
-        __syncthreads();
-        row_fft<M, -1, RB, NC, LP, NT, false, false>(buf, nullptr, nullptr, nullptr, nullptr, RB,
-                                                     tw, tid);
+        // X[k] = fe + W^k fo and X[M-k] = conj(fe - W^k fo) per component;
+        // work item (row, k, component), component fastest
         c32 *out = (c32 *)a.out;
-        constexpr int NO = RB * NH * NC;
+        constexpr int HALF = M / 2 + 1;
+        constexpr int NI = RB * HALF * NC;
 #pragma unroll
-        for (int i = 0; i < (NO + NT - 1) / NT; ++i) {
+        for (int i = 0; i < (NI + NT - 1) / NT; ++i) {
             const int idx = tid + i * NT;
-            if (idx < NO) {
-                const int row = idx / (NH * NC);
-                const int rem = idx - row * (NH * NC);
-                const int k = rem / NC;
-                const int c = rem - k * NC;
-                if (r0 + row < a.nrows) {
-                    const c32 *line = buf + (row * NC + c) * LP;
-                    const c32 z = line[lpad(k == M ? 0 : k)];
+            if (idx < NI) {
+                const int c = idx % NC, t = idx / NC;
+                const int k = t % HALF, l = t / HALF;
+                if (l < nv) {
+                    const c32 *line = buf + (l * NC + c) * LP;
+                    const c32 z = line[lpad(k)];
                     const c32 zc = conjg(line[lpad(k == 0 ? 0 : M - k)]);
                     const c32 fe = scl(add(z, zc), 0.5f);
                     const c32 d = sub(z, zc);
                     const c32 fo = c32{0.5f * d.y, -0.5f * d.x};  // (z - zc) / (2i)
-                    out[ob[row] + rem] = add(fe, mul(twp[k], fo));
+                    const c32 wf = mul(twp[k], fo);
+                    c32 *orow = out + ob[l] + c;
+                    gstore<true>(orow + k * NC, add(fe, wf));
+                    if (2 * k != M) gstore<true>(orow + (M - k) * NC, conjg(sub(fe, wf)));
                 }
             }
         }
@@ -163,11 +153,11 @@ struct XR2CGen {
     }
 };
 
-// ---- general c2r
+// ---- general c2r (interleaved components, any float offsets): bins through
+// LDS, and the last stage stores each packed point as two floats
 template <int M, int NC, int NT>
 struct XC2RGen {
-    static constexpr int RB = x_rb(M, NC, NT), NL = RB * NC, N0 = 2 * M, LP = row_pitch(M + 1),
-                         NH = M + 1;
+    static constexpr int RB = x_rb(M, NC, NT), NL = RB * NC, LP = row_pitch(M + 1), NH = M + 1;
     static constexpr size_t O_BUF = 0, O_TW = al16(O_BUF + sizeof(c32) * NL * LP),
                             O_TWP = al16(O_TW + sizeof(c32) * M),
                             O_IB = al16(O_TWP + sizeof(c32) * NH), O_OB = O_IB + 8 * RB,
@@ -176,6 +166,38 @@ struct XC2RGen {
     {
         load_table((c32 *)(sm + O_TW), a.tw, M, tid, NT);
         load_table((c32 *)(sm + O_TWP), a.tw_post, NH, tid, NT);
+    }
+    // Whole output rows leave as 16-byte nontemporal stores when every row
+    // starts 16-byte aligned and holds a multiple of 4 floats.
+    static __device__ bool vec_out(const XArgs &a)
+    {
+        return (2 * M * NC) % 4 == 0 && ((uintptr_t)a.out & 15) == 0 && a.out_off % 4 == 0 &&
+               a.out_row % 4 == 0 && a.out_plane % 4 == 0;
+    }
+    // Real rows from the LDS lines: float x NC + c of row l is part x & 1 of
+    // point x >> 1 of line l NC + c.
+    static __device__ void store_rows(const XArgs &a, const c32 *buf, const int64_t *ob, int nv,
+                                      int tid)
+    {
+        typedef float nf4 __attribute__((ext_vector_type(4)));
+        constexpr int W4 = 2 * M * NC / 4;  // 16-byte words per row
+        const float *fb = (const float *)buf;
+        float *out = (float *)a.out;
+        for (int e = tid; e < nv * W4; e += NT) {
+            const int l = e / W4, f0 = 4 * (e - l * W4);
+            float w[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int f = f0 + u, x = f / NC, c = f - x * NC;
+                w[u] = fb[2 * ((l * NC + c) * LP + lpad(x >> 1)) + (x & 1)];
+            }
+            nf4 v;
+            v.x = w[0];
+            v.y = w[1];
+            v.z = w[2];
+            v.w = w[3];
+            __builtin_nontemporal_store(v, (nf4 *)(out + ob[l]) + (e - l * W4));
+        }
     }
     static __device__ void tile(const XArgs &a, int64_t blk, char *sm, int tid)
     {
@@ -187,71 +209,116 @@ struct XC2RGen {
         __syncthreads();
         const c32 *in = (const c32 *)a.in;
         constexpr int NI = RB * NH * NC;
+        const int nv = rows_valid<RB>(a, r0);
+        // value e of the tile's rows (row-major, component fastest) -> LDS
+        auto put = [&](int e, c32 v) {
+            const int row = e / (NH * NC), rem = e - row * (NH * NC);
+            const int k = rem / NC, c = rem - k * NC;
+            buf[(row * NC + c) * LP + lpad(k)] = v;
+        };
+        const c32 *src = in + ib[0];
+        if (a.in_row == NH * NC && a.in_plane == (int64_t)a.n1 * NH * NC &&
+            ((uintptr_t)src & 7) == 0) {
+            // dense half spectrum: the tile's rows are one contiguous run,
+            // read with 16-byte loads from the first 16-byte boundary on
+            typedef float nf4 __attribute__((ext_vector_type(4)));
+            const int e0 = ((uintptr_t)src & 15) ? 1 : 0;
+            const nf4 *s4 = (const nf4 *)(src + e0);
+            const int cnt = nv * NH * NC;
+            const int np = (cnt - e0) / 2;
+            for (int e = tid; e < np; e += NT) {
+                const nf4 w = __builtin_nontemporal_load(s4 + e);
+                put(e0 + 2 * e, c32{w.x, w.y});
+                put(e0 + 2 * e + 1, c32{w.z, w.w});
+            }
+            if (tid == 0 && e0 && cnt > 0) put(0, src[0]);
+            if (tid == 0 && e0 + 2 * np < cnt) put(cnt - 1, src[cnt - 1]);
+            for (int e = cnt + tid; e < NI; e += NT) put(e, c32{0.f, 0.f});
+        } else {
 #pragma unroll
-        for (int i = 0; i < (NI + NT - 1) / NT; ++i) {
-            const int idx = tid + i * NT;
-            if (idx < NI) {
-                const int row = idx / (NH * NC);
-                const int rem = idx - row * (NH * NC);
-                const int k = rem / NC;
-                const int c = rem - k * NC;
-                c32 v = c32{0.f, 0.f};
-                if (r0 + row < a.nrows) v = in[ib[row] + rem];
-                buf[(row * NC + c) * LP + lpad(k)] = v;
+            for (int i = 0; i < (NI + NT - 1) / NT; ++i) {
+                const int idx = tid + i * NT;
+                if (idx < NI) {
+                    const int row = idx / (NH * NC);
+                    put(idx, row < nv ? gload<true>(in + ib[row] + (idx - row * (NH * NC)))
+                                      : c32{0.f, 0.f});
+                }
             }
         }
         __syncthreads();
         // Z[k] = (X[k] + conj X[M-k]) + i W^{-k} (X[k] - conj X[M-k]), k < M,
         // with the imaginary parts of X[0] and X[M] dropped.
-        constexpr int NZ = NL * M;
-        constexpr int NZT = (NZ + NT - 1) / NT;
-        c32 zv[NZT];
+        auto zval = [&](const c32 *line, int k) {
+            c32 xk = line[lpad(k)], xm = line[lpad(M - k)];
+            if (k == 0) {
+                xk.y = 0.f;
+                xm.y = 0.f;
+            }
+            const c32 xmc = conjg(xm);
+            const c32 sm_ = add(xk, xmc);
+            const c32 d = mul(conjg(twp[k]), sub(xk, xmc));
+            return c32{sm_.x - d.y, sm_.y + d.x};  // s + i d
+        };
+        if constexpr (nstages(M) >= 2) {
+            // the first inverse stage forms its inputs Z[k] from the bins in
+            // LDS as it reads them (butterfly b: component b % NC, then j,
+            // then row, as in the row engine), then the remaining stages
+            constexpr int R = radix_at(M, 0), Q = M / R;
+            constexpr int NBF = NL * Q, NB = (NBF + NT - 1) / NT;
+            c32 v[NB][R];
 #pragma unroll
-        for (int i = 0; i < NZT; ++i) {
-            const int idx = tid + i * NT;
-            if (idx < NZ) {
-                const int l = idx / M;
-                const int k = idx - l * M;
-                const c32 *line = buf + l * LP;
-                c32 xk = line[lpad(k)];
-                c32 xm = line[lpad(M - k)];
-                if (k == 0) {
-                    xk.y = 0.f;
-                    xm.y = 0.f;
+            for (int i = 0; i < NB; ++i) {
+                const int b = tid + i * NT;
+                if (NBF % NT == 0 || b < NBF) {
+                    const int c = b % NC, t = b / NC;
+                    const int j = t % Q, q = t / Q;
+                    const c32 *line = buf + (q * NC + c) * LP;
+#pragma unroll
+                    for (int r = 0; r < R; ++r) v[i][r] = zval(line, j + r * Q);
                 }
-                const c32 xmc = conjg(xm);
-                const c32 s = add(xk, xmc);
-                const c32 d = mul(conjg(twp[k]), sub(xk, xmc));
-                zv[i] = c32{s.x - d.y, s.y + d.x};  // s + i d
             }
-        }
-        __syncthreads();
+            __syncthreads();
 #pragma unroll
-        for (int i = 0; i < NZT; ++i) {
-            const int idx = tid + i * NT;
-            if (idx < NZ) {
-                const int l = idx / M;
-                const int k = idx - l * M;
-                buf[l * LP + lpad(k)] = zv[i];
-            }
-        }
-        __syncthreads();
-        row_fft<M, +1, RB, NC, LP, NT, false, false>(buf, nullptr, nullptr, nullptr, nullptr, RB,
-                                                     tw, tid);
-        float *out = (float *)a.out;
-        const float *fb = (const float *)buf;
-        constexpr int NE = RB * N0 * NC;
+            for (int i = 0; i < NB; ++i) {
+                const int b = tid + i * NT;
+                if (NBF % NT == 0 || b < NBF) {
+                    const int c = b % NC, t = b / NC;
+                    const int j = t % Q, q = t / Q;
+                    Dft<R, +1>::run(v[i]);
+                    c32 *dst = buf + (q * NC + c) * LP;
 #pragma unroll
-        for (int i = 0; i < (NE + NT - 1) / NT; ++i) {
-            const int idx = tid + i * NT;
-            if (idx < NE) {
-                const int row = idx / (N0 * NC);
-                const int rem = idx - row * (N0 * NC);
-                const int x = rem / NC;
-                const int c = rem - x * NC;
-                if (r0 + row < a.nrows)
-                    out[ob[row] + rem] = fb[2 * ((row * NC + c) * LP + lpad(x >> 1)) + (x & 1)];
+                    for (int r = 0; r < R; ++r) dst[lpad(j * R + r)] = v[i][r];
+                }
             }
+            __syncthreads();
+            if (vec_out(a)) {
+                // remaining stages in LDS, then whole rows out as 16-byte stores
+                row_fft<M, +1, RB, NC, LP, NT, false, false, 1, R>(buf, nullptr, nullptr, nullptr,
+                                                                   nullptr, nv, tw, tid);
+                store_rows(a, buf, ob, nv, tid);
+            } else {
+                // the last stage stores each component's pairs straight to the rows
+                row_fft<M, +1, RB, NC, LP, NT, false, true, 1, R, true, true>(
+                    buf, nullptr, (c32 *)a.out, nullptr, ob, nv, tw, tid);
+            }
+        } else {
+            constexpr int NZ = NL * M;
+            constexpr int NZT = (NZ + NT - 1) / NT;
+            c32 zv[NZT];
+#pragma unroll
+            for (int i = 0; i < NZT; ++i) {
+                const int idx = tid + i * NT;
+                if (idx < NZ) zv[i] = zval(buf + (idx / M) * LP, idx % M);
+            }
+            __syncthreads();
+#pragma unroll
+            for (int i = 0; i < NZT; ++i) {
+                const int idx = tid + i * NT;
+                if (idx < NZ) buf[(idx / M) * LP + lpad(idx % M)] = zv[i];
+            }
+            __syncthreads();
+            row_fft<M, +1, RB, NC, LP, NT, false, true, 0, 1, true, true>(
+                buf, nullptr, (c32 *)a.out, nullptr, ob, nv, tw, tid);
         }
         __syncthreads();
     }

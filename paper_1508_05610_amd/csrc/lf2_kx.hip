@@ -4,7 +4,8 @@
 // One-component rows with 8-byte aligned element offsets take the fast
 // kernels (complex loads/stores straight into/out of the Stockham stages);
 // everything else (components interleaved, odd halo offsets) takes the
-// general kernels that de-interleave through LDS.
+// general kernels, which load or store each component's packed pairs as
+// floats.
 #include <stdint.h>
 
 #include "lf2_kernels.hpp"
