@@ -126,3 +126,30 @@ def test_grf_spectrum_256(lf2):
     assert np.array_equal(ct.cpu().numpy(), oct_)
     for e in (e1, e2, e3, e4):
         assert e <= tol(shape)
+
+
+@pytest.mark.parametrize("shape,nbins", [((64, 48, 40), 4096), ((160, 96, 64), 4096),
+                                         ((96, 160, 192), 1000)])
+def test_many_bins_every_bin(lf2, shape, nbins):
+    """Up to the 4096-bin maximum, on lattices whose lcm makes q large: the
+    fused pass's bin of every mode must be the exact integer rule's, so each
+    bin's power is compared on its own (a mode put into a neighbouring bin
+    would move a whole |F|^2 / count there)."""
+    print(f"case many bins {shape} nbins={nbins}", flush=True)
+    dense, _ = real_field(shape, seed=15)
+    f = dense[..., 0]
+    f64 = f.astype(np.float64)
+    plan = lf2.Plan(shape, lf2.LF2_R2C)
+    x = torch.from_numpy(f).to(dev())
+    pk, km, ct = plan.power_spectrum(x, nbins)
+    phi, pk2, km2, ct2 = plan.poisson(x, nbins=nbins)
+    torch.cuda.synchronize()
+    opk, okm, oct_ = oracle.power_spectrum(oracle.r2c(f64), shape, nbins)
+    assert np.array_equal(ct.cpu().numpy(), oct_) and np.array_equal(ct2.cpu().numpy(), oct_)
+    scale = float(np.mean(opk[oct_ > 0]))
+    for got in (pk.cpu().numpy(), pk2.cpu().numpy()):
+        err = np.abs(got - opk)
+        worst = float(np.max(err / (scale + np.abs(opk))))
+        print(f"  worst per-bin error {worst:.2e}", flush=True)
+        assert worst <= 1e-5
+    assert rel_l2(phi.cpu().numpy(), oracle.poisson(f64)) <= tol(shape)
