@@ -93,9 +93,10 @@ hipError_t launch_update_halo(void *field, const int64_t n[3], int64_t h, int64_
 // extra row is the y neighbour of the group's last row), which later serve
 // as the current plane, so HBM sees each input row (GY + 1) / GY times.
 // Those reads run one plane ahead of the arithmetic.  The x neighbour is
-// the word ncomp further on (a cache hit: this or the next block reads it
-// in the same plane).  The three results of a word are staged through LDS
-// so that every store of a wave is contiguous.
+// the word ncomp further on: the current plane's rows go through LDS (plus
+// the ncomp words past the block's end, read from memory), so it is not
+// read again.  The three results of a word are staged through LDS so that
+// every store of a wave is contiguous.
 struct GradArgs {
     const float *in;
     float *out;
@@ -106,17 +107,21 @@ struct GradArgs {
 };
 
 constexpr int kGradThreads = 256;
-constexpr int kGradRows = 8;  // GY
+constexpr int kGradRows = 8;     // GY
+constexpr int kGradMaxComp = 64;  // largest ncomp
 
 __global__ __launch_bounds__(kGradThreads) void k_gradient(GradArgs a)
 {
     constexpr int GY = kGradRows;
     __shared__ float stage[GY][3 * kGradThreads];
+    __shared__ float cur[GY][kGradThreads + kGradMaxComp];
     const int tid = threadIdx.x;
     const int64_t rowwords = a.n0 * a.nc;
     const int64_t w0 = (int64_t)blockIdx.x * kGradThreads;
     const int64_t w = w0 + tid;
-    const bool ok = w < rowwords;
+    // words up to rowwords + ncomp - 1 (the upper halo site) are read: the
+    // last interior words take their x neighbours from them
+    const bool ld = w < rowwords + a.nc;
     const int64_t y0 = (int64_t)blockIdx.y * GY;
     const int ny = (int)(a.n1 - y0 < GY ? a.n1 - y0 : GY);  // rows of this group
     const int64_t z0 = (int64_t)blockIdx.z * a.zc;
@@ -124,33 +129,41 @@ __global__ __launch_bounds__(kGradThreads) void k_gradient(GradArgs a)
     const int64_t sy = a.p0 * a.nc, sz = a.p1 * a.p0 * a.nc;  // input strides (words)
     // input word w of interior row y0 + i of plane z0; rows past the group
     // are read from row min(y0 + i, n1), which exists (upper halo row n1)
-    const float *f = a.in + ((a.h + z0) * a.p1 + a.h + y0) * sy + a.h * a.nc + (ok ? w : 0);
+    const float *f = a.in + ((a.h + z0) * a.p1 + a.h + y0) * sy + a.h * a.nc + (ld ? w : 0);
     int64_t roff[GY + 1];
 #pragma unroll
     for (int i = 0; i <= GY; ++i) roff[i] = (i <= ny ? i : ny) * sy;
-    // c: plane z, nx: plane z + 1 (both rows y0 .. y0 + GY); xn: x neighbours in plane z
-    float c[GY + 1], nx[GY + 1], xn[GY];
+    // c: plane z, nx: plane z + 1 (both rows y0 .. y0 + GY)
+    float c[GY + 1], nx[GY + 1];
 #pragma unroll
     for (int i = 0; i <= GY; ++i) {
-        c[i] = ok ? f[roff[i]] : 0.f;
-        nx[i] = ok ? f[sz + roff[i]] : 0.f;
+        c[i] = ld ? f[roff[i]] : 0.f;
+        nx[i] = ld ? f[sz + roff[i]] : 0.f;
     }
-#pragma unroll
-    for (int i = 0; i < GY; ++i) xn[i] = ok ? f[roff[i] + a.nc] : 0.f;
+    // words w0 + 256 + t (t < ncomp) hold the last threads' x neighbours;
+    // they exist while w0 + 256 + t < rowwords + ncomp (upper halo site)
+    const bool extra = tid < a.nc && w0 + kGradThreads + tid < rowwords + a.nc;
+    const float *fe = a.in + ((a.h + z0) * a.p1 + a.h + y0) * sy + a.h * a.nc +
+                      (extra ? w0 + kGradThreads + tid : 0);
     const int nst = (int)(3 * (rowwords - w0 < kGradThreads ? rowwords - w0 : kGradThreads));
     float *o = a.out + ((a.h + z0) * a.p1 + a.h + y0) * (sy * 3) + a.h * a.nc * 3 + 3 * w0;
     for (int64_t z = z0; z < z1; ++z) {
         // the next step's planes, read only while z + 2 <= z1 <= n2 (the
         // upper halo plane n2 exists)
-        float nn[GY + 1], xn2[GY];
+        float nn[GY + 1];
         const bool more = z + 1 < z1;
 #pragma unroll
-        for (int i = 0; i <= GY; ++i) nn[i] = (ok && more) ? f[2 * sz + roff[i]] : 0.f;
-#pragma unroll
-        for (int i = 0; i < GY; ++i) xn2[i] = (ok && more) ? f[sz + roff[i] + a.nc] : 0.f;
+        for (int i = 0; i <= GY; ++i) nn[i] = (ld && more) ? f[2 * sz + roff[i]] : 0.f;
 #pragma unroll
         for (int i = 0; i < GY; ++i) {
-            stage[i][3 * tid + 0] = (xn[i] - c[i]) * a.inv_dx;
+            cur[i][tid] = c[i];
+            if (extra) cur[i][kGradThreads + tid] = fe[roff[i]];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < GY; ++i) {
+            const float xn = cur[i][tid + a.nc];
+            stage[i][3 * tid + 0] = (xn - c[i]) * a.inv_dx;
             stage[i][3 * tid + 1] = (c[i + 1] - c[i]) * a.inv_dx;
             stage[i][3 * tid + 2] = (nx[i] - c[i]) * a.inv_dx;
         }
@@ -163,9 +176,8 @@ __global__ __launch_bounds__(kGradThreads) void k_gradient(GradArgs a)
             c[i] = nx[i];
             nx[i] = nn[i];
         }
-#pragma unroll
-        for (int i = 0; i < GY; ++i) xn[i] = xn2[i];
         f += sz;
+        fe += sz;
         o += sz * 3;
     }
 }
