@@ -221,15 +221,26 @@ struct XC2RGen {
             ((uintptr_t)src & 7) == 0) {
             // dense half spectrum: the tile's rows are one contiguous run,
             // read with 16-byte loads from the first 16-byte boundary on
+            // (all of a thread's loads are issued before the first LDS write)
             typedef float nf4 __attribute__((ext_vector_type(4)));
+            constexpr int NW = (NI / 2 + NT - 1) / NT;
             const int e0 = ((uintptr_t)src & 15) ? 1 : 0;
             const nf4 *s4 = (const nf4 *)(src + e0);
             const int cnt = nv * NH * NC;
             const int np = (cnt - e0) / 2;
-            for (int e = tid; e < np; e += NT) {
-                const nf4 w = __builtin_nontemporal_load(s4 + e);
-                put(e0 + 2 * e, c32{w.x, w.y});
-                put(e0 + 2 * e + 1, c32{w.z, w.w});
+            nf4 w[NW];
+#pragma unroll
+            for (int i = 0; i < NW; ++i) {
+                const int e = tid + i * NT;
+                if (e < np) w[i] = __builtin_nontemporal_load(s4 + e);
+            }
+#pragma unroll
+            for (int i = 0; i < NW; ++i) {
+                const int e = tid + i * NT;
+                if (e < np) {
+                    put(e0 + 2 * e, c32{w[i].x, w[i].y});
+                    put(e0 + 2 * e + 1, c32{w[i].z, w[i].w});
+                }
             }
             if (tid == 0 && e0 && cnt > 0) put(0, src[0]);
             if (tid == 0 && e0 + 2 * np < cnt) put(cnt - 1, src[cnt - 1]);
@@ -417,12 +428,23 @@ struct XC2RV {
                 buf[l * LP + lpad(k)] = v;
             };
             if (((uintptr_t)src & 15) == 0) {
+                // all of a thread's loads are issued before the first LDS write
                 typedef float nf4 __attribute__((ext_vector_type(4)));
+                constexpr int NW = (RB * NH / 2 + NT - 1) / NT;
                 const nf4 *s4 = (const nf4 *)src;
-                for (int e = tid; e < cnt / 2; e += NT) {
-                    const nf4 w = __builtin_nontemporal_load(s4 + e);
-                    put(2 * e, c32{w.x, w.y});
-                    put(2 * e + 1, c32{w.z, w.w});
+                nf4 w[NW];
+#pragma unroll
+                for (int i = 0; i < NW; ++i) {
+                    const int e = tid + i * NT;
+                    if (e < cnt / 2) w[i] = __builtin_nontemporal_load(s4 + e);
+                }
+#pragma unroll
+                for (int i = 0; i < NW; ++i) {
+                    const int e = tid + i * NT;
+                    if (e < cnt / 2) {
+                        put(2 * e, c32{w[i].x, w[i].y});
+                        put(2 * e + 1, c32{w[i].z, w[i].w});
+                    }
                 }
                 if ((cnt & 1) && tid == 0) put(cnt - 1, src[cnt - 1]);
             } else {
