@@ -716,8 +716,16 @@ def main():
             bg = back.cpu().numpy()
             errors["c2r_bwd_chain"] = {"rel_l2": rel_l2(bg, bo), "max": rel_max(bg, bo)}
             opk, okm, oct_ = oracle.power_spectrum(Fo, n, nb)
-            errors["pk"] = {"rel_l2": rel_l2(pk.cpu().numpy(), opk),
+            pkg = pk.cpu().numpy()
+            errors["pk"] = {"rel_l2": rel_l2(pkg, opk), "max": rel_max(pkg, opk),
                             "counts_exact": bool(np.array_equal(ct.cpu().numpy(), oct_))}
+            phio = oracle.poisson(f64)
+            phig = phi.cpu().numpy()
+            errors["poisson_phi"] = {"rel_l2": rel_l2(phig, phio), "max": rel_max(phig, phio)}
+            pvg = pv.cpu().numpy()
+            sumsq = float(np.sum(f64 * f64))
+            errors["parseval"] = {"sum_f2_rel": abs(float(pvg[0]) - sumsq) / sumsq,
+                                  "sum_wF2_over_N_rel": abs(float(pvg[1]) - sumsq) / sumsq}
             # c2c 3-comp: sampled modes, each evaluated from the definition
             Zg = Z.cpu().numpy()
             zz = z.cpu().numpy()

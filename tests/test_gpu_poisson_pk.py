@@ -153,3 +153,25 @@ def test_many_bins_every_bin(lf2, shape, nbins):
         print(f"  worst per-bin error {worst:.2e}", flush=True)
         assert worst <= 1e-5
     assert rel_l2(phi.cpu().numpy(), oracle.poisson(f64)) <= tol(shape)
+
+
+@pytest.mark.parametrize("shape", [(8, 4, 1), (4, 6, 2), (6, 10, 3), (10, 5, 12), (12, 20, 5),
+                                   (2, 2, 2), (16, 3, 6), (40, 24, 20)])
+def test_poisson_pk_short_last_axis(lf2, shape):
+    """Last-axis lengths with no or one Stockham stage (1, 2, 3, 5, 6, 12, 20):
+    the fused pass's register hand-off between its forward and backward
+    transforms degenerates there (no LDS stages, or a single radix-3/5 stage)."""
+    print(f"case short last axis {shape}", flush=True)
+    dense, _ = real_field(shape, seed=16)
+    f = dense[..., 0]
+    f64 = f.astype(np.float64)
+    plan = lf2.Plan(shape, lf2.LF2_R2C)
+    x = torch.from_numpy(f).to(dev())
+    phi, pk, km, ct = plan.poisson(x, nbins=4)
+    pk2, km2, ct2 = plan.power_spectrum(x, 4)
+    torch.cuda.synchronize()
+    assert rel_l2(phi.cpu().numpy(), oracle.poisson(f64)) <= tol(shape)
+    opk, okm, oct_ = oracle.power_spectrum(oracle.r2c(f64), shape, 4)
+    for p_, c_ in ((pk, ct), (pk2, ct2)):
+        assert np.array_equal(c_.cpu().numpy(), oct_)
+        assert rel_l2(p_.cpu().numpy(), opk) <= tol(shape)
