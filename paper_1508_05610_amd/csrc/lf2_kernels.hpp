@@ -358,12 +358,49 @@ struct XR2CV {
         const int64_t r0 = blk * RB;
         row_bases<RB, NT>(ib, ob, a, r0, tid);
         __syncthreads();
-        for (int i = tid; i < RB; i += NT) ib[i] >>= 1;  // float offset -> complex offset
-        __syncthreads();
         const int nv = rows_valid<RB>(a, r0);
         double ss = 0.0;
-        row_fft<M, -1, RB, 1, LP, NT, true, false, 0, 1, true>(buf, (const c32 *)a.in, nullptr, ib, nullptr,
-                                                   nv, tw, tid, sumsq ? &ss : nullptr);
+        const float *src = (const float *)a.in + ib[0];
+        if (M % 2 == 0 && a.in_row == 2 * M && a.in_plane == (int64_t)a.n1 * 2 * M &&
+            ((uintptr_t)src & 15) == 0) {
+            // Dense rows: the tile is one contiguous run of nv N0 reals, read
+            // with 16-byte loads (all of a thread's loads issued first) into
+            // the padded LDS lines, then transformed there.
+            typedef float nf4 __attribute__((ext_vector_type(4)));
+            constexpr int NW = (RB * M / 2 + NT - 1) / NT;
+            const nf4 *s4 = (const nf4 *)src;
+            const int np = nv * M / 2;
+            auto put = [&](int e, c32 v) {
+                const int l = e / M, k = e - l * M;
+                buf[l * LP + lpad(k)] = v;
+            };
+            nf4 w[NW];
+#pragma unroll
+            for (int i = 0; i < NW; ++i) {
+                const int e = tid + i * NT;
+                if (e < np) w[i] = __builtin_nontemporal_load(s4 + e);
+            }
+#pragma unroll
+            for (int i = 0; i < NW; ++i) {
+                const int e = tid + i * NT;
+                if (e < np) {
+                    put(2 * e, c32{w[i].x, w[i].y});
+                    put(2 * e + 1, c32{w[i].z, w[i].w});
+                    if (sumsq)
+                        ss += ((double)w[i].x * w[i].x + (double)w[i].y * w[i].y) +
+                              ((double)w[i].z * w[i].z + (double)w[i].w * w[i].w);
+                }
+            }
+            for (int e = nv * M + tid; e < RB * M; e += NT) put(e, c32{0.f, 0.f});
+            __syncthreads();
+            row_fft<M, -1, RB, 1, LP, NT, false, false>(buf, nullptr, nullptr, nullptr, nullptr, nv,
+                                                        tw, tid);
+        } else {
+            for (int i = tid; i < RB; i += NT) ib[i] >>= 1;  // float offset -> complex offset
+            __syncthreads();
+            row_fft<M, -1, RB, 1, LP, NT, true, false, 0, 1, true>(
+                buf, (const c32 *)a.in, nullptr, ib, nullptr, nv, tw, tid, sumsq ? &ss : nullptr);
+        }
         if (sumsq) block_sum_f64<NT>(ss, sumsq, (double *)(sm + O_RED));
         c32 *out = (c32 *)a.out;
         constexpr int NI = RB * HALF;
