@@ -180,8 +180,7 @@ def test_round_trip(lf2):
     assert rel_l2(back.cpu().numpy(), dense[..., 0]) <= tol(shape)
 
 
-# lines of 256..2048 points along y or z take either tile variant (wide
-# tiles of 1024- and 2048-point lines exchange through LDS half by half)
+# lines of 256..2048 points along y or z take either tile variant
 WIDE_CASES = [((16, 256, 384), 0, 1), ((32, 64, 512), 0, 1), ((8, 24, 1024), 0, 1),
               ((40, 320, 96), 0, 1), ((12, 96, 768), 0, 1), ((6, 640, 16), 0, 1),
               ((16, 512, 256), 1, 3), ((10, 16, 512), 1, 1), ((4, 2048, 8), 0, 1),
