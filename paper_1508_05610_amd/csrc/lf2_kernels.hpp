@@ -6,12 +6,13 @@
 // functions over the tiles of many fields, one launch per (pass, length).
 //
 // x pass  : lines along dimension 0 are contiguous in memory.  A tile is RB
-//           rows (all components of each row).  One-component rows with
-//           even element offsets are read as complex values straight into
-//           the first Stockham stage (r2c packs N0 reals as N0/2 complex
-//           values, transforms and splits the result into Nh bins; c2r does
-//           the reverse).  Other layouts (interleaved components of real
-//           fields, odd halo offsets) de-interleave through LDS.
+//           rows (all components of each row).  r2c packs N0 reals as N0/2
+//           complex values, transforms and splits the result into Nh bins;
+//           c2r does the reverse.  Dense tiles are read as one run of
+//           16-byte loads into LDS; other one-component rows with even
+//           element offsets go as complex values straight into the first
+//           Stockham stage, and interleaved components of real fields (or
+//           odd halo offsets) as float pairs.
 // strided : lines along dimension 1 or 2 have a large stride; consecutive
 //           columns are adjacent in memory.  A tile is B adjacent columns x
 //           L points: loaded row by row (B * 8 bytes contiguous per row)
@@ -97,7 +98,7 @@ __device__ __forceinline__ void load_table(c32 *dst, const void *src, int n, int
 // floats straight from the row; one padded LDS line per (row, component)
 template <int M, int NC, int NT>
 struct XR2CGen {
-    static constexpr int RB = x_rb(M, NC, NT), NL = RB * NC, N0 = 2 * M, LP = row_pitch(M),
+    static constexpr int RB = x_rb(M, NC, NT), NL = RB * NC, LP = row_pitch(M),
                          NH = M + 1;
     static constexpr size_t O_BUF = 0, O_TW = al16(O_BUF + sizeof(c32) * NL * LP),
                             O_TWP = al16(O_TW + sizeof(c32) * M),
@@ -996,8 +997,12 @@ __global__ __launch_bounds__(kXThreads) void k_x_c2c_v(XArgs a)
 }
 
 // Strided pass: persistent-style walk over tiles.
+// Occupancy target: four waves per SIMD (two blocks per CU) except where the
+// fused pass's LDS tables leave room for one block (lines of 1024 points and
+// more), where two waves per SIMD are all it can reach.
 template <int L, int S, bool EPI, bool NTM = false>
-__global__ __launch_bounds__(kSThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_strided(SArgs a)
+__global__ __launch_bounds__(kSThreads)
+    __attribute__((amdgpu_waves_per_eu(EPI && L >= 1024 ? 2 : 4))) void k_strided(SArgs a)
 {
     using T = STile<L, S, EPI, kSThreads, NTM>;
     constexpr int NT = kSThreads;
