@@ -156,11 +156,13 @@ def test_many_bins_every_bin(lf2, shape, nbins):
 
 
 @pytest.mark.parametrize("shape", [(8, 4, 1), (4, 6, 2), (6, 10, 3), (10, 5, 12), (12, 20, 5),
-                                   (2, 2, 2), (16, 3, 6), (40, 24, 20)])
+                                   (2, 2, 2), (16, 3, 6), (40, 24, 20), (8, 6, 1024), (4, 4, 2048),
+                                   (6, 10, 768), (4, 8, 640)])
 def test_poisson_pk_short_last_axis(lf2, shape):
     """Last-axis lengths with no or one Stockham stage (1, 2, 3, 5, 6, 12, 20):
     the fused pass's register hand-off between its forward and backward
-    transforms degenerates there (no LDS stages, or a single radix-3/5 stage)."""
+    transforms degenerates there (no LDS stages, or a single radix-3/5 stage);
+    and the longest lines (640..2048), whose fused tiles fit one per CU."""
     print(f"case short last axis {shape}", flush=True)
     dense, _ = real_field(shape, seed=16)
     f = dense[..., 0]
