@@ -199,11 +199,13 @@ lf2_status lf2_plan_destroy(lf2_plan p);
 
 /*
  * Batched Poisson solves on many lattices of different sizes.  The work of
- * all fields is grouped by pass and line length: one launch per group, in
- * pass order (x r2c, y, z Poisson [+ binning], y backward, x c2r), each
- * block taking one (field, tile) item, then one launch that finalizes every
- * field's power spectrum; the sequence is captured once in a hipGraph and
- * replayed by lf2_batch_execute.  Each field gives the same result as
+ * all fields is grouped by pass and line length: one launch per group
+ * (passes x r2c, y, z Poisson [+ binning], y backward, x c2r), each block
+ * taking one (field, tile) item, then one launch that finalizes every
+ * field's power spectrum.  The launches are captured once in a hipGraph in
+ * which each group depends only on the previous pass's groups that hold one
+ * of its fields (the finalize on the z groups), so independent groups run
+ * concurrently; lf2_batch_execute replays the graph.  Each field gives the same result as
  * lf2_poisson_solve on it alone (power spectra within FP64 summation
  * order).
  *
