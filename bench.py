@@ -672,19 +672,26 @@ def main():
     if not args.no_cpu_baseline or not args.no_errors:
         import oracle
         f64 = f32.astype(np.float64)
-        t0 = time.perf_counter()
-        Fo = oracle.r2c(f64)
-        t1 = time.perf_counter()
-        bo = oracle.c2r(Fo, S)
-        t2 = time.perf_counter()
-        cpu_s = t2 - t0
+        # one warm-up, then the median of three timed r2c + c2r pairs (one
+        # pair only when the baseline is not asked for: errors need one)
+        runs = []
+        for rep in range(4 if not args.no_cpu_baseline else 1):
+            t0 = time.perf_counter()
+            Fo = oracle.r2c(f64)
+            t1 = time.perf_counter()
+            bo = oracle.c2r(Fo, S)
+            t2 = time.perf_counter()
+            if rep > 0 or args.no_cpu_baseline:
+                runs.append((t2 - t0, t1 - t0, t2 - t1))
+        runs.sort()
+        cpu_s, t_r2c, t_c2r = runs[len(runs) // 2]
         if not args.no_cpu_baseline:
             res["cpu_baseline"] = {
                 "value": round(2 * flops_fft / cpu_s / 1e9, 3), "unit": "GFLOP/s",
                 "cores": oracle.num_threads(), "kind": "oracle",
                 "sample": f"one r2c forward + one c2r backward of the {S}^3 field "
-                          f"(2 of the {n_transforms} transforms of a step); "
-                          f"{t1 - t0:.2f} s + {t2 - t1:.2f} s",
+                          f"(2 of the {n_transforms} transforms of a step), median of 3 after "
+                          f"one warm-up: {t_r2c:.2f} s + {t_c2r:.2f} s",
             }
             # the same oracle on one thread, r2c forward of a quarter-size cube
             s1 = S // 2
