@@ -160,3 +160,29 @@ def test_batch_config_48_uneven_grf(lf2):
         assert e <= tol(s), (i, s, e)
         assert epk <= tol(s), (i, s, epk)
     print(f"  worst error / tolerance {worst:.3e}", flush=True)
+
+
+@pytest.mark.parametrize("discrete,dx", [(0, 0.5), (1, 1.0), (1, 0.25)])
+def test_batch_without_pk_flags_and_dx(lf2, discrete, dx):
+    """Poisson-only batches (no binning epilogue, no finalize launch) with the
+    discrete-Laplacian k^2 and a lattice spacing: every field against the
+    oracle and against its solo solve with the same settings."""
+    print(f"case batch no pk discrete={discrete} dx={dx}", flush=True)
+    flags = lf2.LF2_POISSON_DISCRETE_K2 if discrete else 0
+    fs = fields_for(SMALL, seed=33)
+    b = lf2.Batch(SMALL, nbins=0, dx=dx, poisson_flags=flags)
+    bp = lf2.Batch(SMALL, nbins=8, dx=dx, poisson_flags=flags)
+    assert b.launches + 1 == bp.launches  # the finalize only with binning
+    bp.close()
+    rhos = [torch.from_numpy(f).to(dev()) for f in fs]
+    phis = [torch.zeros_like(r) for r in rhos]
+    b.run(rhos, phis)
+    torch.cuda.synchronize()
+    assert b.error() == 0
+    for i, (s, f) in enumerate(zip(SMALL, fs)):
+        ref = oracle.poisson(f.astype(np.float64), dx=dx, k2mode=discrete)
+        assert rel_l2(phis[i].cpu().numpy(), ref) <= tol(s)
+        plan = lf2.Plan(s, lf2.LF2_R2C)
+        solo = plan.poisson(rhos[i], dx=dx, flags=flags)
+        torch.cuda.synchronize()
+        assert rel_l2(solo.cpu().numpy(), phis[i].cpu().numpy()) <= 1e-6
