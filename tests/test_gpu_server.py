@@ -117,3 +117,30 @@ def test_discrete_k2_and_pk_of_phi(lf2):
     torch.cuda.synchronize()
     assert rel_l2(phi.cpu().numpy(), solo.cpu().numpy()) <= 1e-6
     assert rel_l2(pk.cpu().numpy(), spk.cpu().numpy()) <= 1e-6
+
+
+def test_serving_config_sizes_against_oracle(lf2):
+    """One request of each cubic size of the serving workload (N in {32, 64,
+    128, 256, 384}, 64 bins, 8 GiB budget), the largest at full size, each
+    served result against the oracle."""
+    nb = 64
+    sizes = [(n, n, n) for n in (384, 32, 256, 64, 128)]
+    print("case serving config sizes 32..384 vs oracle", flush=True)
+    srv = lf2.Server(8 << 30, max_slots=16, nstreams=4)
+    reqs = make_inputs(sizes, seed=6, nb=nb)
+    tickets = []
+    for (f, rho, phi, pk, cnt) in reqs:
+        st, t = srv.submit(rho, phi, nbins=nb, pk=pk, count=cnt)
+        assert st == lf2.LF2_OK
+        tickets.append(t)
+    res = [srv.poll(t) for t in tickets]
+    srv.close()
+    assert all(r[0] == lf2.LF2_OK for r in res), res
+    for s, (f, rho, phi, pk, cnt) in zip(sizes, reqs):
+        f64 = f.astype(np.float64)
+        e = rel_l2(phi.cpu().numpy(), oracle.poisson(f64))
+        opk, _, oct_ = oracle.power_spectrum(oracle.r2c(f64), s, nb)
+        epk = rel_l2(pk.cpu().numpy(), opk)
+        print(f"  {s}: phi {e:.2e} pk {epk:.2e}", flush=True)
+        assert e <= tol(s) and epk <= tol(s)
+        assert np.array_equal(cnt.cpu().numpy(), oct_)
