@@ -131,7 +131,7 @@ lf2_status lf2_fft_kspace(lf2_plan p, int64_t ksize[3], int64_t kstride[3]);
  * once).  chunk = consecutive tiles given to one XCD in the tile order
  * (1..1024, default 16).  Every setting computes the same transform bit for
  * bit.  The fused Poisson / power-spectrum pass always uses narrow tiles,
- * normal accesses and chunk 16.  get reports the setting and, after
+ * nontemporal accesses and chunk 16.  get reports the setting and, after
  * LF2_PLAN_AUTOTUNE, the measured microseconds of the default setting
  * (variant 0, chunk 16) and of the chosen one (-1 if not measured); null
  * outputs are skipped.  set overrides the setting (LF2_ERR_UNSUPPORTED for
@@ -154,7 +154,8 @@ lf2_status lf2_plan_set_workspace(lf2_plan p, void *dev_ptr, size_t bytes);
  *   r2c plan, LF2_FORWARD : in = real field, out = half spectrum
  *   r2c plan, LF2_BACKWARD: in = half spectrum (not modified), out = real field
  *   c2c plan, either      : in = complex field / spectrum, out = spectrum / field
- * in and out must not overlap.  Pointers must be 8-byte aligned.
+ * in and out must not overlap, except in == out on a plan made with
+ * LF2_IN_PLACE.  Pointers must be 8-byte aligned.
  */
 lf2_status lf2_fft_execute(lf2_plan p, lf2_direction dir, const void *in, void *out,
                            void *stream);
