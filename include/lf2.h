@@ -166,7 +166,8 @@ lf2_status lf2_fft_execute(lf2_plan p, lf2_direction dir, const void *in, void *
  *   phi_hat = -rho_hat / k^2 (k != 0), phi_hat(0) = 0, phi = c2r(phi_hat)/N,
  * with the FP64 factor -1/(N k^2) applied in one pass between the forward
  * and backward transforms along dimension 2.  r2c plan with ncomp = 1.
- * rho and phi are real fields (halo as in the plan) and must not overlap.
+ * rho and phi are real fields (halo as in the plan) and must not overlap,
+ * except rho == phi on a plan made with LF2_IN_PLACE.
  * dx > 0 is the lattice spacing.
  * If nbins > 0, the power spectrum of rho (or of phi with LF2_PK_OF_PHI) is
  * binned as in lf2_power_spectrum into d_pk, d_kmean, d_count (device
