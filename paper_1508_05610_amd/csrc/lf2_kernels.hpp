@@ -650,14 +650,13 @@ __device__ __forceinline__ void load_edges(const ModeTables &mt, double *hist, B
     }
 }
 
-// 1/d for d > 0 in FP64: hardware reciprocal refined by two Newton steps
-// (relative error near one FP64 ulp; the scale it feeds is rounded to FP32).
+// 1/d for d > 0 in FP64: the hardware reciprocal refined by one Newton step,
+// which squares the estimate's relative error; the scale it feeds multiplies
+// FP32 modes in FP64 and is rounded to FP32 with the product.
 __device__ __forceinline__ double rcp_f64(double d)
 {
     double r = __builtin_amdgcn_rcp(d);
-    r = fma(fma(-d, r, 1.0), r, r);
-    r = fma(fma(-d, r, 1.0), r, r);
-    return r;
+    return fma(fma(-d, r, 1.0), r, r);
 }
 
 // The thread index, hidden from the optimiser once per tile when OPAQUE: the
