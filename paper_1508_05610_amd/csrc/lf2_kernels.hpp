@@ -341,7 +341,8 @@ struct XC2RGen {
 // fe = (Z[k] + conj Z[M-k]) / 2, fo = (Z[k] - conj Z[M-k]) / (2i).
 template <int M, int NT>
 struct XR2CV {
-    static constexpr int RB = x_rb(M, 1, NT), LP = row_pitch(M), NH = M + 1, HALF = M / 2 + 1;
+    // LDS lines hold the M packed points, then the NH = M + 1 output bins
+    static constexpr int RB = x_rb(M, 1, NT), LP = row_pitch(M + 1), NH = M + 1, HALF = M / 2 + 1;
     static constexpr size_t O_BUF = 0, O_TW = al16(O_BUF + sizeof(c32) * RB * LP),
                             O_TWP = al16(O_TW + sizeof(c32) * M),
                             O_IB = al16(O_TWP + sizeof(c32) * NH), O_OB = O_IB + 8 * RB,
@@ -403,7 +404,8 @@ struct XR2CV {
                 buf, (const c32 *)a.in, nullptr, ib, nullptr, nv, tw, tid, sumsq ? &ss : nullptr);
         }
         if (sumsq) block_sum_f64<NT>(ss, sumsq, (double *)(sm + O_RED));
-        c32 *out = (c32 *)a.out;
+        // bins of every line in place: the thread of pair (k, M - k) reads
+        // and writes only those two slots (k = 0 writes X[M] to slot M)
         constexpr int NI = RB * HALF;
 #pragma unroll
         for (int i = 0; i < (NI + NT - 1) / NT; ++i) {
@@ -412,17 +414,49 @@ struct XR2CV {
                 const int l = idx / HALF;
                 const int k = idx - l * HALF;
                 if (l < nv) {
-                    const c32 *line = buf + l * LP;
+                    c32 *line = buf + l * LP;
                     const c32 z = line[lpad(k)];
                     const c32 zc = conjg(line[lpad(k == 0 ? 0 : M - k)]);
                     const c32 fe = scl(add(z, zc), 0.5f);
                     const c32 d = sub(z, zc);
                     const c32 fo = c32{0.5f * d.y, -0.5f * d.x};
                     const c32 wf = mul(twp[k], fo);
-                    c32 *orow = out + ob[l];
-                    gstore<true>(orow + k, add(fe, wf));
-                    if (2 * k != M) gstore<true>(orow + (M - k), conjg(sub(fe, wf)));
+                    line[lpad(k)] = add(fe, wf);
+                    if (2 * k != M) line[lpad(M - k)] = conjg(sub(fe, wf));
                 }
+            }
+        }
+        __syncthreads();
+        c32 *out = (c32 *)a.out;
+        auto bin = [&](int e) {  // value e of the tile's output rows, row-major
+            const int l = e / NH;
+            return buf[l * LP + lpad(e - l * NH)];
+        };
+        if (a.out_row == NH && a.out_plane == (int64_t)a.n1 * NH) {
+            // dense half spectrum: the tile's rows are one contiguous run,
+            // written with 16-byte nontemporal stores from the first 16-byte
+            // boundary on
+            typedef float nf4 __attribute__((ext_vector_type(4)));
+            c32 *dst = out + ob[0];
+            const int cnt = nv * NH;
+            const int e0 = ((uintptr_t)dst & 15) ? 1 : 0;
+            const int np = (cnt - e0) / 2;
+            nf4 *d4 = (nf4 *)(dst + e0);
+            for (int e = tid; e < np; e += NT) {
+                const c32 u = bin(e0 + 2 * e), w = bin(e0 + 2 * e + 1);
+                nf4 v;
+                v.x = u.x;
+                v.y = u.y;
+                v.z = w.x;
+                v.w = w.y;
+                __builtin_nontemporal_store(v, d4 + e);
+            }
+            if (tid == 0 && e0 && cnt > 0) gstore<true>(dst, bin(0));
+            if (tid == 0 && e0 + 2 * np < cnt) gstore<true>(dst + (cnt - 1), bin(cnt - 1));
+        } else {
+            for (int e = tid; e < nv * NH; e += NT) {
+                const int l = e / NH;
+                gstore<true>(out + ob[l] + (e - l * NH), bin(e));
             }
         }
         __syncthreads();
