@@ -276,6 +276,9 @@ ModeTables base_tables(const lf2_plan_s *p)
     mt.nbins = 0;
     mt.qmax = (double)p->qmax;
     mt.scale_n = 1.0 / (double)p->ntot;
+    // below 2^32 whenever N2 > 1 (it is then at most qmax); unused for N2 = 1
+    const int64_t uz = p->lcm / p->n[2];
+    mt.qz_unit = (uint32_t)(uz * uz);
     return mt;
 }
 

@@ -29,6 +29,7 @@ struct ModeTables {
     int nbins;
     double qmax;
     double scale_n;        // Poisson: factor 1/N applied with -1/k^2
+    uint32_t qz_unit;      // (lcm / N2)^2: q[2][i] = qz_unit * min(i, N2 - i)^2
 };
 
 struct XArgs {

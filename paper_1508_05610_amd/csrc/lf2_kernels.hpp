@@ -664,13 +664,20 @@ struct BinEdge {
 // estimate nbins sqrt(q / qmax) (cq = nbins^2 / qmax) is within 1e-3 of the
 // exact value, so one comparison each way against the estimated bin's
 // edges makes it exact.
-__device__ __forceinline__ int bin_edge(uint32_t q, int nbins, float cq, const BinEdge *edges)
+__device__ __forceinline__ int bin_est(uint32_t q, float cq)
 {
-    // hardware square root (about 1 ulp; the correction below absorbs it)
-    int b = (int)__builtin_amdgcn_sqrtf((float)q * cq);  // 0..nbins
-    const BinEdge e = edges[b];
+    // hardware square root (about 1 ulp; the correction absorbs it)
+    return (int)__builtin_amdgcn_sqrtf((float)q * cq);  // 0..nbins
+}
+__device__ __forceinline__ int bin_fix(uint32_t q, int b, BinEdge e, int nbins)
+{
     b += (q >= e.hi ? 1 : 0) - (q < e.lo ? 1 : 0);
     return b < nbins - 1 ? b : nbins - 1;
+}
+__device__ __forceinline__ int bin_edge(uint32_t q, int nbins, float cq, const BinEdge *edges)
+{
+    const int b = bin_est(q, cq);
+    return bin_fix(q, b, edges[b], nbins);
 }
 
 // Zero the block's LDS histogram and fill its edge table.
@@ -714,22 +721,18 @@ template <int L, int S, bool EPI, int NT, bool NTM = false>
 struct STile {
     static constexpr int B = s_b(L);
     static constexpr int RPT = NT / B;  // row groups in the epilogue
-    // EPI tiles also keep the last axis' k^2 and q tables in LDS (read once
-    // per mode in the epilogue)
+    // EPI tiles also keep the last axis' k^2 table in LDS (read once per
+    // mode in the epilogue)
     static constexpr size_t O_BUF = 0, O_TW = al16(sizeof(c32) * L * B),
                             O_K2Z = al16(O_TW + sizeof(c32) * L),
-                            O_QZ = O_K2Z + (EPI ? 8 * L : 0),
-                            BYTES = al16(O_QZ + (EPI ? 4 * L : 0));
+                            BYTES = al16(O_K2Z + (EPI ? 8 * L : 0));
     static __device__ void tables(const SArgs &a, char *sm, int tid)
     {
         load_table((c32 *)(sm + O_TW), a.tw, L, tid, NT);
         if constexpr (EPI) {
             double *k2z = (double *)(sm + O_K2Z);
-            uint32_t *qz = (uint32_t *)(sm + O_QZ);  // q < 2^32 (checked at plan time)
-            for (int i = tid; i < L; i += NT) {
-                if (a.epi & EPI_POISSON) k2z[i] = a.mt.k2[2][i];
-                if (a.epi & (EPI_PK | EPI_PK_AFTER)) qz[i] = (uint32_t)a.mt.q[2][i];
-            }
+            if (a.epi & EPI_POISSON)
+                for (int i = tid; i < L; i += NT) k2z[i] = a.mt.k2[2][i];
         }
     }
     static __device__ void tile(const SArgs &a, int64_t t, char *sm, int tid, double *hist,
@@ -851,8 +854,13 @@ struct STile {
         const float cq = (float)((double)nb * nb / a.mt.qmax);
         // the half-spectrum weight is the same for the whole column
         const double wgt = (a.mt.half && !(kx == 0 || 2 * kx == a.mt.n0)) ? 2.0 : 1.0;
+        // q < 2^32 (checked at plan time); the last axis' part from |n_z|
         const uint32_t qxy = valid ? (uint32_t)(a.mt.q[0][kx] + a.mt.q[1][ky]) : 0u;
-        const uint32_t *qz = (const uint32_t *)(sm + O_QZ);
+        const uint32_t qu = a.mt.qz_unit;
+        auto qof = [&](int k) {
+            const uint32_t m = (uint32_t)(2 * k < L ? k : L - k);
+            return qxy + m * m * qu;
+        };
         const bool corner = kx == 0 && ky == 0;
         // every row group's run has EP modes when RPT EP = L; otherwise the
         // last runs are shorter or empty (n <= 0)
@@ -862,22 +870,29 @@ struct STile {
         double acc = 0.0;
         if (valid && n > 0) {
             // selects, not branches, for the zero mode and the bin; the next
-            // mode's LDS reads are issued before this mode's work
+            // mode's value and bin-edge LDS reads are issued before this
+            // mode's work
             int kz = rg * EP;
             c32 v = buf[kz * B + col];
-            uint32_t q = qxy + qz[kz];
+            uint32_t q = qof(kz);
+            int be = bin_est(q, cq);
+            BinEdge ed = edges[be];
 #pragma unroll 4
             for (int e = 0; e < EP; ++e) {
                 if (!EXACT && e >= n) break;
                 const int kzn = kz + 1 < L ? kz + 1 : kz;  // in bounds; unused past the run
                 const c32 vn = buf[kzn * B + col];
-                const uint32_t qn = qxy + qz[kzn];
-                const int bq = bin_edge(q, nb, cq, edges);
+                const uint32_t qn = qof(kzn);
+                const int ben = bin_est(qn, cq);
+                const BinEdge edn = edges[ben];
+                const int bq = bin_fix(q, be, ed, nb);
                 // slot nbins: the zero mode (kept for the Parseval sum)
                 const int b = (corner && kz == 0) ? nb : bq;
                 const double p = (double)v.x * v.x + (double)v.y * v.y;
                 v = vn;
                 q = qn;
+                be = ben;
+                ed = edn;
                 kz = kzn;
                 if (b != cur) {
                     if (cur >= 0) atomicAdd(&hist[cur], wgt * acc);
