@@ -177,3 +177,24 @@ def test_poisson_pk_short_last_axis(lf2, shape):
     for p_, c_ in ((pk, ct), (pk2, ct2)):
         assert np.array_equal(c_.cpu().numpy(), oct_)
         assert rel_l2(p_.cpu().numpy(), opk) <= tol(shape)
+
+
+def test_poisson_repeatable(lf2):
+    """Repeated solves: phi and the real-space sum of squares are bitwise
+    equal; the binned sums (P(k), the k-space Parseval sum) come from LDS
+    histograms that waves add into in scheduling order, so they agree to
+    FP64 rounding only."""
+    shape = (128, 96, 80)
+    f = real_field(shape, seed=19)[0][..., 0]
+    plan = lf2.Plan(shape, lf2.LF2_R2C)
+    x = torch.from_numpy(f).to(dev())
+    runs = [plan.poisson(x, nbins=48, parseval=True) for _ in range(3)]
+    torch.cuda.synchronize()
+    phi0, pk0, km0, ct0, pv0 = [t.cpu().numpy() for t in runs[0]]
+    for r in runs[1:]:
+        phi, pk, km, ct, pv = [t.cpu().numpy() for t in r]
+        assert np.array_equal(phi, phi0)
+        assert np.array_equal(ct, ct0) and np.array_equal(km, km0)
+        assert pv[0] == pv0[0]
+        assert abs(pv[1] - pv0[1]) <= 1e-13 * pv0[1]
+        assert np.all(np.abs(pk - pk0) <= 1e-13 * np.abs(pk0))
