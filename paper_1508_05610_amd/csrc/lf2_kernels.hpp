@@ -795,7 +795,7 @@ struct STile {
         const bool corner = kx == 0 && ky == 0;
         if (a.epi & EPI_PK) {
             col_stage_out<L, RL, QL, B, NT, false>(buf, nullptr, 0, false, tid, v);
-            bin_walk(a, sm, buf, col, rg, kx, ky, valid, hist, edges);
+            bin_walk(a, buf, col, rg, kx, ky, valid, hist, edges);
         }
         if (a.epi & EPI_POISSON) {
             const double k2xy = valid ? a.mt.k2[0][kx] + a.mt.k2[1][ky] : 1.0;
@@ -818,7 +818,7 @@ struct STile {
         }
         if (a.epi & EPI_PK_AFTER) {
             col_stage_out<L, RL, QL, B, NT, false>(buf, nullptr, 0, false, tid, v);
-            bin_walk(a, sm, buf, col, rg, kx, ky, valid, hist, edges);
+            bin_walk(a, buf, col, rg, kx, ky, valid, hist, edges);
         }
         if constexpr (S < 0) {
             if (a.epi & EPI_POISSON) {
@@ -845,9 +845,8 @@ struct STile {
     // walks its run of kz, computes each mode's exact bin and adds w |F|^2
     // into the block's LDS histogram when the bin changes.  Ends at a
     // barrier, so LDS may be rewritten afterwards.
-    static __device__ void bin_walk(const SArgs &a, char *sm, const c32 *buf, int col, int rg,
-                                    int kx, int ky, bool valid, double *hist,
-                                    const BinEdge *edges)
+    static __device__ void bin_walk(const SArgs &a, const c32 *buf, int col, int rg, int kx,
+                                    int ky, bool valid, double *hist, const BinEdge *edges)
     {
         constexpr int EP = (L + RPT - 1) / RPT;
         const int nb = a.mt.nbins;
