@@ -98,21 +98,31 @@ __global__ __launch_bounds__(kSThreads) __attribute__((amdgpu_waves_per_eu(4))) 
 
 // One block per field: fixed-order reduction of the z tiles' bin rows, then
 // pk = norm * S_b / count_b and kmean = kscale * sumk_b / count_b.
-__global__ __launch_bounds__(512) void k_bfin(const BatchField *fields)
+constexpr int kBFinThreads = 1024;
+__global__ __launch_bounds__(kBFinThreads) void k_bfin(const BatchField *fields)
 {
-    constexpr int NT = 512;
+    constexpr int NT = kBFinThreads;
     __shared__ double red[NT];
     const int tid = threadIdx.x;
     const BatchField &F = fields[blockIdx.x];
     if (F.nbins <= 0) return;  // uniform over the block
     const int nbr = F.nbins + 1;
-    const int G = NT / nbr;  // >= 1 because nbins <= kBatchMaxBins
+    const int G = NT / nbr;  // >= 2 because nbins <= kBatchMaxBins
     const int nt = F.ntiles[BP_Z];
     if (tid < G * nbr) {
+        // group g sums tiles g, g + G, ... of bin b with four running sums
+        // (four loads in flight), combined in a fixed order
         const int b = tid % nbr, g = tid / nbr;
-        double s = 0.0;
-        for (int t = g; t < nt; t += G) s += F.partial[(int64_t)t * nbr + b];
-        red[tid] = s;
+        double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+        int t = g;
+        for (; t + 3 * G < nt; t += 4 * G) {
+            s0 += F.partial[(int64_t)t * nbr + b];
+            s1 += F.partial[(int64_t)(t + G) * nbr + b];
+            s2 += F.partial[(int64_t)(t + 2 * G) * nbr + b];
+            s3 += F.partial[(int64_t)(t + 3 * G) * nbr + b];
+        }
+        for (; t < nt; t += G) s0 += F.partial[(int64_t)t * nbr + b];
+        red[tid] = (s0 + s1) + (s2 + s3);
     }
     __syncthreads();
     if (tid < F.nbins) {
@@ -167,7 +177,7 @@ hipError_t batch_group_launch(int pass, int len, const BatchField *fields,
 
 hipError_t batch_finalize_launch(const BatchField *fields, int nfields, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_bfin, dim3(nfields), dim3(512), 0, s, fields);
+    hipLaunchKernelGGL(k_bfin, dim3(nfields), dim3(kBFinThreads), 0, s, fields);
     return hipGetLastError();
 }
 

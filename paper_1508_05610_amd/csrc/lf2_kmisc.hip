@@ -136,28 +136,40 @@ hipError_t launch_shell_partials(const ModeTables &mt, int n1, int n2, double /*
 }
 
 // Fixed-order column sums: out[b] = sum over g of partial[g * width + b].
-// One block per column; thread t sums g = t, t + 256, ... in order, then a
-// fixed tree combines the 256 thread sums, so the result is reproducible.
-__global__ __launch_bounds__(256) void k_reduce_cols(const double *partial, int64_t grid,
-                                                     int width, double *out)
+// One block per column; thread t keeps four running sums over the rows
+// g = t + kRedThreads (4 i + j), j = 0..3 (four loads in flight instead of a
+// chain of dependent ones), adds them in a fixed order, then a fixed tree
+// combines the thread sums, so the result is reproducible.
+constexpr int kRedThreads = 1024;
+__global__ __launch_bounds__(kRedThreads) void k_reduce_cols(const double *partial, int64_t grid,
+                                                             int width, double *out)
 {
-    __shared__ double red[256];
+    __shared__ double red[kRedThreads];
     const int b = blockIdx.x;
-    double s = 0.0;
-    for (int64_t g = threadIdx.x; g < grid; g += 256) s += partial[g * width + b];
-    red[threadIdx.x] = s;
+    const int t = threadIdx.x;
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    int64_t g = t;
+    for (; g + 3 * kRedThreads < grid; g += 4 * kRedThreads) {
+        s0 += partial[g * width + b];
+        s1 += partial[(g + kRedThreads) * width + b];
+        s2 += partial[(g + 2 * kRedThreads) * width + b];
+        s3 += partial[(g + 3 * kRedThreads) * width + b];
+    }
+    for (; g < grid; g += kRedThreads) s0 += partial[g * width + b];
+    red[t] = (s0 + s1) + (s2 + s3);
     __syncthreads();
-    for (int h = 128; h > 0; h >>= 1) {
-        if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+    for (int h = kRedThreads / 2; h > 0; h >>= 1) {
+        if (t < h) red[t] += red[t + h];
         __syncthreads();
     }
-    if (threadIdx.x == 0) out[b] = red[0];
+    if (t == 0) out[b] = red[0];
 }
 
 hipError_t launch_reduce_cols(const double *partial, int64_t grid, int width, double *out,
                               hipStream_t s)
 {
-    hipLaunchKernelGGL(k_reduce_cols, dim3(width), dim3(256), 0, s, partial, grid, width, out);
+    hipLaunchKernelGGL(k_reduce_cols, dim3(width), dim3(kRedThreads), 0, s, partial, grid, width,
+                       out);
     return hipGetLastError();
 }
 
@@ -225,22 +237,35 @@ hipError_t launch_pk_kspace(const void *F, int n1, int n2, int64_t sx, int64_t s
 // shell table: pk = norm * vscale * S_b / count_b, kmean = kscale * sumk_b /
 // count_b (0 for empty bins); parseval = { *sumsq, inv_n * vscale *
 // sum_b S_b including the zero mode }.
-__global__ void k_pk_finalize(const double *S, int nbins, const double *count, const double *sumk,
-                              double norm, double vscale, double kscale, double *pk,
-                              double *kmean, double *count_out, double *parseval,
-                              const double *sumsq, double inv_n)
+constexpr int kFinThreads = 256;
+__global__ __launch_bounds__(kFinThreads) void k_pk_finalize(
+    const double *S, int nbins, const double *count, const double *sumk, double norm,
+    double vscale, double kscale, double *pk, double *kmean, double *count_out, double *parseval,
+    const double *sumsq, double inv_n)
 {
-    for (int b = threadIdx.x; b < nbins; b += blockDim.x) {
+    const int t = threadIdx.x;
+    for (int b = t; b < nbins; b += kFinThreads) {
         const double c = count[b];
         if (pk) pk[b] = c > 0 ? norm * vscale * S[b] / c : 0.0;
         if (kmean) kmean[b] = c > 0 ? kscale * sumk[b] / c : 0.0;
         if (count_out) count_out[b] = c;
     }
-    if (parseval && threadIdx.x == 0) {
-        double t = 0.0;
-        for (int b = 0; b <= nbins; ++b) t += S[b];
-        parseval[0] = sumsq ? *sumsq : 0.0;
-        parseval[1] = inv_n * vscale * t;
+    if (parseval) {  // uniform over the block
+        // sum of all nbins + 1 slots (the zero mode included): per-thread
+        // strided sums, then a fixed tree
+        __shared__ double red[kFinThreads];
+        double a = 0.0;
+        for (int b = t; b <= nbins; b += kFinThreads) a += S[b];
+        red[t] = a;
+        __syncthreads();
+        for (int h = kFinThreads / 2; h > 0; h >>= 1) {
+            if (t < h) red[t] += red[t + h];
+            __syncthreads();
+        }
+        if (t == 0) {
+            parseval[0] = sumsq ? *sumsq : 0.0;
+            parseval[1] = inv_n * vscale * red[0];
+        }
     }
 }
 
@@ -249,7 +274,7 @@ hipError_t launch_pk_finalize(const double *S, int nbins, const double *count, c
                               double *kmean, double *count_out, double *parseval,
                               const double *sumsq, double inv_n, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_pk_finalize, dim3(1), dim3(256), 0, s, S, nbins, count, sumk, norm,
+    hipLaunchKernelGGL(k_pk_finalize, dim3(1), dim3(kFinThreads), 0, s, S, nbins, count, sumk, norm,
                        vscale, kscale, pk, kmean, count_out, parseval, sumsq, inv_n);
     return hipGetLastError();
 }
