@@ -503,12 +503,17 @@ lf2_status run_x(const lf2_plan_s *p, int which, int sign, const XArgs &a, hipSt
 }
 
 // Binning tail: reduce partials, finalize into the caller's arrays.
+// sq_part (nullable): sq_rows per-block sums of squares of the real field,
+// reduced into *sq_total in the same launch as the bin partials.
 lf2_status pk_tail(lf2_plan p, const ShellEntry &sh, double *part, int grid, double *sums,
                    double dx, double vscale, double *d_pk, double *d_kmean, double *d_count,
-                   double *d_parseval, const double *sumsq_total, hipStream_t s)
+                   double *d_parseval, const double *sq_part, int64_t sq_rows, double *sq_total,
+                   hipStream_t s)
 {
     const int nb = sh.nbins;
-    LF2_HIP(launch_reduce_cols(part, grid, nb + 1, sums, s));
+    LF2_HIP(launch_reduce_cols2(part, grid, nb + 1, sums, sq_part, sq_rows, sq_part ? 1 : 0,
+                                sq_total, s));
+    const double *sumsq_total = sq_part ? sq_total : nullptr;
     const double norm = dx * dx * dx / (double)p->ntot;
     const double kscale = 6.283185307179586476925286766559 / ((double)p->lcm * dx);
     LF2_HIP(launch_pk_finalize(sums, nb, sh.count, sh.sumk, norm, vscale, kscale, d_pk, d_kmean,
@@ -972,16 +977,14 @@ lf2_status poisson_impl(lf2_plan p, const float *rho, float *phi, double dx, uin
     if ((st = run_strided(p, 1, +1, s_args(p, 1, W, W, EPI_STORE), kStridedGridCap, s, nullptr))) return st;
     if ((st = run_x(p, 1, +1, x_args(p, W, phi, false, true, true), s))) return st;
     if (nb > 0) {
-        double *sqt = nullptr;
-        if (parseval) {
-            sqt = (double *)(ws + L.sqt);
-            LF2_HIP(launch_reduce_cols((double *)(ws + L.sq), x_grid_blocks(p), 1, sqt, s));
-        }
         const double vscale = (flags & LF2_PK_OF_PHI) ? (double)p->ntot * (double)p->ntot : 1.0;
         const bool user_bins = nbins > 0;
         if ((st = pk_tail(p, sh, (double *)(ws + L.part), grid, (double *)(ws + L.sums), dx, vscale,
                           user_bins ? d_pk : nullptr, user_bins ? d_kmean : nullptr,
-                          user_bins ? d_count : nullptr, d_parseval, sqt, s)))
+                          user_bins ? d_count : nullptr, d_parseval,
+                          parseval ? (const double *)(ws + L.sq) : nullptr,
+                          parseval ? x_grid_blocks(p) : 0,
+                          parseval ? (double *)(ws + L.sqt) : nullptr, s)))
             return st;
     }
     return LF2_OK;
@@ -1047,7 +1050,7 @@ lf2_status lf2_power_spectrum(lf2_plan p, const void *field, int32_t field_is_ks
         if ((st = run_strided(p, 2, -1, za, kPkGrid, s, &grid))) return st;
     }
     return pk_tail(p, sh, part, grid, (double *)(ws + L.sums), dx, 1.0, d_pk, d_kmean, d_count,
-                   nullptr, nullptr, s);
+                   nullptr, nullptr, 0, nullptr, s);
 }
 
 }  // extern "C"

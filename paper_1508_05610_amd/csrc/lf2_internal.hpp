@@ -98,6 +98,10 @@ hipError_t launch_shell_partials(const ModeTables &mt, int n1, int n2, double ls
 // out[b] = sum_g partial[g * width + b] in a fixed order, b < width.
 hipError_t launch_reduce_cols(const double *partial, int64_t grid, int width, double *out,
                               hipStream_t s);
+// the same for two arrays in one launch (width2 = 0: the second is unused)
+hipError_t launch_reduce_cols2(const double *partial1, int64_t grid1, int width1, double *out1,
+                               const double *partial2, int64_t grid2, int width2, double *out2,
+                               hipStream_t s);
 hipError_t launch_pk_kspace(const void *F, int n1, int n2, int64_t sx, int64_t sy, int64_t sz,
                             const ModeTables &mt, double *partial, int grid, hipStream_t s);
 hipError_t launch_pk_finalize(const double *S, int nbins, const double *count, const double *sumk,

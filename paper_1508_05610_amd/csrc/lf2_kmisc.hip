@@ -136,16 +136,22 @@ hipError_t launch_shell_partials(const ModeTables &mt, int n1, int n2, double /*
 }
 
 // Fixed-order column sums: out[b] = sum over g of partial[g * width + b].
-// One block per column; thread t keeps four running sums over the rows
-// g = t + kRedThreads (4 i + j), j = 0..3 (four loads in flight instead of a
-// chain of dependent ones), adds them in a fixed order, then a fixed tree
-// combines the thread sums, so the result is reproducible.
+// One block per column (blocks width1.. serve an optional second array, so
+// that two reductions share a launch); thread t keeps four running sums
+// over the rows g = t + kRedThreads (4 i + j), j = 0..3 (four loads in
+// flight instead of a chain of dependent ones), adds them in a fixed order,
+// then a fixed tree combines the thread sums, so the result is reproducible.
 constexpr int kRedThreads = 1024;
-__global__ __launch_bounds__(kRedThreads) void k_reduce_cols(const double *partial, int64_t grid,
-                                                             int width, double *out)
+__global__ __launch_bounds__(kRedThreads) void k_reduce_cols(
+    const double *partial1, int64_t grid1, int width1, double *out1, const double *partial2,
+    int64_t grid2, int width2, double *out2)
 {
     __shared__ double red[kRedThreads];
-    const int b = blockIdx.x;
+    const bool first = (int)blockIdx.x < width1;
+    const double *partial = first ? partial1 : partial2;
+    const int64_t grid = first ? grid1 : grid2;
+    const int width = first ? width1 : width2;
+    const int b = first ? (int)blockIdx.x : (int)blockIdx.x - width1;
     const int t = threadIdx.x;
     double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
     int64_t g = t;
@@ -162,15 +168,23 @@ __global__ __launch_bounds__(kRedThreads) void k_reduce_cols(const double *parti
         if (t < h) red[t] += red[t + h];
         __syncthreads();
     }
-    if (t == 0) out[b] = red[0];
+    if (t == 0) (first ? out1 : out2)[b] = red[0];
+}
+
+hipError_t launch_reduce_cols2(const double *partial1, int64_t grid1, int width1, double *out1,
+                               const double *partial2, int64_t grid2, int width2, double *out2,
+                               hipStream_t s)
+{
+    if (width1 + width2 <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_reduce_cols, dim3(width1 + width2), dim3(kRedThreads), 0, s, partial1,
+                       grid1, width1, out1, partial2, grid2, width2, out2);
+    return hipGetLastError();
 }
 
 hipError_t launch_reduce_cols(const double *partial, int64_t grid, int width, double *out,
                               hipStream_t s)
 {
-    hipLaunchKernelGGL(k_reduce_cols, dim3(width), dim3(kRedThreads), 0, s, partial, grid, width,
-                       out);
-    return hipGetLastError();
+    return launch_reduce_cols2(partial, grid, width, out, nullptr, 0, 0, nullptr, s);
 }
 
 // Power spectrum of a spectrum already in k space ([n2][n1][nxk], ncomp 1).
