@@ -198,3 +198,24 @@ def test_poisson_repeatable(lf2):
         assert pv[0] == pv0[0]
         assert abs(pv[1] - pv0[1]) <= 1e-13 * pv0[1]
         assert np.all(np.abs(pk - pk0) <= 1e-13 * np.abs(pk0))
+
+
+def test_parseval_many_x_blocks(lf2):
+    """Parseval partials from 5120 x-pass blocks (512 x 256 x 320, 16 rows a
+    block): the fixed-order reduction runs its four-loads-in-flight loop and
+    its tail, and must give the FP64 sum of squares and the k-space sum."""
+    shape = (512, 256, 320)
+    print("case parseval, 5120 x blocks", flush=True)
+    f = real_field(shape, seed=20)[0][..., 0]
+    f64 = f.astype(np.float64)
+    plan = lf2.Plan(shape, lf2.LF2_R2C)
+    phi, pk, km, ct, pv = plan.poisson(torch.from_numpy(f).to(dev()), nbins=16, parseval=True)
+    torch.cuda.synchronize()
+    pv = pv.cpu().numpy()
+    s2 = float(np.sum(f64 * f64))
+    assert abs(pv[0] - s2) <= 1e-12 * s2
+    assert abs(pv[1] - pv[0]) <= tol(shape) * pv[0]
+    opk, okm, oct_ = oracle.power_spectrum(oracle.r2c(f64), shape, 16)
+    assert np.array_equal(ct.cpu().numpy(), oct_)
+    assert rel_l2(pk.cpu().numpy(), opk) <= tol(shape)
+    assert rel_l2(phi.cpu().numpy(), oracle.poisson(f64)) <= tol(shape)
