@@ -189,50 +189,71 @@ hipError_t launch_reduce_cols(const double *partial, int64_t grid, int width, do
 
 // Power spectrum of a spectrum already in k space ([n2][n1][nxk], ncomp 1).
 // Tile of 64 adjacent (kx, ky) columns; thread (col, rg) walks a contiguous
-// run of kz, flushing its running bin sum to the LDS histogram when the bin
-// changes.  Partials [grid][nbins + 1] (slot nbins = zero mode).
-__global__ __launch_bounds__(256) void k_pk_kspace(const c32 *F, int n1, int n2, int64_t sx,
-                                                   int64_t sy, int64_t sz, ModeTables mt,
-                                                   double *partial)
+// run of kz, U modes at a time, the next U loads issued before the current
+// U modes are binned (one wave reads 64 adjacent modes per load), flushing
+// its running bin sum to the LDS histogram when the bin changes.  The bin is the exact integer rule's,
+// from the square-root estimate and the LDS edge table as in the fused
+// pass.  Partials [grid][nbins + 1] (slot nbins = zero mode).
+constexpr int kPkThreads = 512;
+__global__ __launch_bounds__(kPkThreads) void k_pk_kspace(const c32 *F, int n1, int n2, int64_t sx,
+                                                          int64_t sy, int64_t sz, ModeTables mt,
+                                                          double *partial)
 {
-    constexpr int B = 64, NT = 256, RG = NT / B;
+    constexpr int B = 64, NT = kPkThreads, RG = NT / B, U = 8;
     extern __shared__ double sh[];
     const int nb = mt.nbins;
     double *hist = sh;
-    int64_t *th = (int64_t *)(sh + nb + 1);
-    for (int i = threadIdx.x; i <= nb; i += NT) {
-        hist[i] = 0.0;
-        th[i] = mt.thresh[i];
-    }
+    BinEdge *edges = (BinEdge *)(sh + nb + 1);
+    load_edges(mt, hist, edges, threadIdx.x, NT);
     __syncthreads();
-    const double inv_qmax = 1.0 / mt.qmax;
+    const float cq = (float)((double)nb * nb / mt.qmax);
+    const uint32_t qu = mt.qz_unit;
     const int64_t ncols = (int64_t)mt.nxk * n1;
     const int64_t ntiles = (ncols + B - 1) / B;
     const int col = threadIdx.x % B, rg = threadIdx.x / B;
     const int ep = (n2 + RG - 1) / RG;
+    const int k0 = rg * ep;
+    const int k1 = k0 + ep < n2 ? k0 + ep : n2;  // this thread's run [k0, k1)
     for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
         const int64_t f = t * B + col;
         if (f >= ncols) continue;
         const int kx = (int)(f % mt.nxk), ky = (int)(f / mt.nxk);
+        // the half-spectrum weight (1 or 2, exact) is applied at each flush
         const double w = (mt.half && !(kx == 0 || 2 * kx == mt.n0)) ? 2.0 : 1.0;
-        const int64_t qxy = mt.q[0][kx] + mt.q[1][ky];
+        const uint32_t qxy = (uint32_t)(mt.q[0][kx] + mt.q[1][ky]);  // q < 2^32 (plan check)
+        const c32 *src = F + (int64_t)ky * sy + (int64_t)kx * sx;
         int cur = -1;
         double acc = 0.0;
-        for (int e = 0; e < ep; ++e) {
-            const int kz = rg * ep + e;
-            if (kz >= n2) break;
-            const c32 v = F[(int64_t)kz * sz + (int64_t)ky * sy + (int64_t)kx * sx];
-            const bool zero = (kx == 0 && ky == 0 && kz == 0);
-            const int b = zero ? nb : bin_of(qxy + mt.q[2][kz], th, nb, inv_qmax);
-            const double p = w * ((double)v.x * v.x + (double)v.y * v.y);
-            if (b != cur) {
-                if (cur >= 0) atomicAdd(&hist[cur], acc);
-                cur = b;
-                acc = 0.0;
+        c32 vv[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            vv[u] = k0 + u < k1 ? src[(int64_t)(k0 + u) * sz] : c32{0.f, 0.f};
+        for (int kb = k0; kb < k1; kb += U) {
+            c32 vn[U];  // the next batch (no loads past the run)
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                vn[u] = kb + U + u < k1 ? src[(int64_t)(kb + U + u) * sz] : c32{0.f, 0.f};
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int kz = kb + u;
+                if (kz < k1) {
+                    const uint32_t m = (uint32_t)(2 * kz < n2 ? kz : n2 - kz);
+                    const uint32_t q = qxy + m * m * qu;
+                    const bool zero = kx == 0 && ky == 0 && kz == 0;
+                    const int b = zero ? nb : bin_edge(q, nb, cq, edges);
+                    const double p = (double)vv[u].x * vv[u].x + (double)vv[u].y * vv[u].y;
+                    if (b != cur) {
+                        if (cur >= 0) atomicAdd(&hist[cur], w * acc);
+                        cur = b;
+                        acc = 0.0;
+                    }
+                    acc += p;
+                }
             }
-            acc += p;
+#pragma unroll
+            for (int u = 0; u < U; ++u) vv[u] = vn[u];
         }
-        if (cur >= 0) atomicAdd(&hist[cur], acc);
+        if (cur >= 0) atomicAdd(&hist[cur], w * acc);
     }
     __syncthreads();
     for (int i = threadIdx.x; i <= nb; i += NT) partial[(int64_t)blockIdx.x * (nb + 1) + i] = hist[i];
@@ -242,8 +263,8 @@ hipError_t launch_pk_kspace(const void *F, int n1, int n2, int64_t sx, int64_t s
                             const ModeTables &mt, double *partial, int grid, hipStream_t s)
 {
     const size_t shm = (size_t)(mt.nbins + 1) * 16;
-    hipLaunchKernelGGL(k_pk_kspace, dim3(grid), dim3(256), shm, s, (const c32 *)F, n1, n2, sx, sy,
-                       sz, mt, partial);
+    hipLaunchKernelGGL(k_pk_kspace, dim3(grid), dim3(kPkThreads), shm, s, (const c32 *)F, n1, n2,
+                       sx, sy, sz, mt, partial);
     return hipGetLastError();
 }
 
