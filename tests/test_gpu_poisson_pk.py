@@ -143,11 +143,14 @@ def test_many_bins_every_bin(lf2, shape, nbins):
     x = torch.from_numpy(f).to(dev())
     pk, km, ct = plan.power_spectrum(x, nbins)
     phi, pk2, km2, ct2 = plan.poisson(x, nbins=nbins)
+    # and from the resident spectrum (k-space kernel, its own histogram)
+    pk3, km3, ct3 = plan.power_spectrum(plan.forward(x), nbins, field_is_kspace=True)
     torch.cuda.synchronize()
     opk, okm, oct_ = oracle.power_spectrum(oracle.r2c(f64), shape, nbins)
     assert np.array_equal(ct.cpu().numpy(), oct_) and np.array_equal(ct2.cpu().numpy(), oct_)
+    assert np.array_equal(ct3.cpu().numpy(), oct_)
     scale = float(np.mean(opk[oct_ > 0]))
-    for got in (pk.cpu().numpy(), pk2.cpu().numpy()):
+    for got in (pk.cpu().numpy(), pk2.cpu().numpy(), pk3.cpu().numpy()):
         err = np.abs(got - opk)
         worst = float(np.max(err / (scale + np.abs(opk))))
         print(f"  worst per-bin error {worst:.2e}", flush=True)
