@@ -643,16 +643,9 @@ struct XC2CV {
 
 // ================================================================ binning
 // Exact bin of integer squared radius q: max{b <= nbins-1 : thresh[b] <= q},
-// thresh[b] = ceil(b^2 qmax / nbins^2).  The FP64 estimate is corrected by
-// integer comparisons, so the result never depends on rounding.
-__device__ __forceinline__ int bin_of(int64_t q, const int64_t *thresh, int nbins, double inv_qmax)
-{
-    int b = (int)((double)nbins * sqrt((double)q * inv_qmax));
-    b = b < 0 ? 0 : (b > nbins - 1 ? nbins - 1 : b);
-    while (b + 1 < nbins && thresh[b + 1] <= q) ++b;
-    while (b > 0 && thresh[b] > q) --b;
-    return b;
-}
+// thresh[b] = ceil(b^2 qmax / nbins^2), from an estimate corrected by
+// integer comparisons against the bin's edges, so the result never depends
+// on rounding.
 
 // Bin edges (thresh[b], thresh[b + 1]) of bin b = 0..nbins as one 8-byte
 // LDS entry (hi = 2^32 - 1 past the last bin); thresholds are < 2^32.
@@ -660,7 +653,7 @@ struct BinEdge {
     uint32_t lo, hi;
 };
 
-// The same bin for q < 2^32 and nbins <= 4096 from the edge table: the FP32
+// That bin for q < 2^32 and nbins <= 4096 from the edge table: the FP32
 // estimate nbins sqrt(q / qmax) (cq = nbins^2 / qmax) is within 1e-3 of the
 // exact value, so one comparison each way against the estimated bin's
 // edges makes it exact.

@@ -89,38 +89,69 @@ hipError_t launch_thresholds(int64_t *dst, int nbins, int64_t qmax, hipStream_t 
     return hipGetLastError();
 }
 
-// Lattice-only shell sums: sum w and sum w sqrt(q) per bin over all modes
-// except the zero mode, as per-block partials.
-__global__ void k_shell_partials(ModeTables mt, int n1, int n2, double *pc, double *pkk)
+// Shell table of the lattice: per bin, the weighted mode count sum w and
+// sum w sqrt(q) over the half (r2c) or full spectrum, zero mode excluded.
+// Thread (col, rg) walks a run of kz of one (kx, ky) column (64 adjacent
+// columns per tile), keeps the run's sums while the bin stays the same and
+// adds them to the block's LDS histograms when it changes (the bin rule and
+// edge table of the fused pass).  Partials [grid][nbins] of each.
+__global__ __launch_bounds__(256) void k_shell_partials(ModeTables mt, int n1, int n2, double *pc,
+                                                        double *pkk)
 {
+    constexpr int B = 64, NT = 256, RG = NT / B;
     extern __shared__ double sh[];
     const int nb = mt.nbins;
     double *hc = sh;
     double *hk = sh + nb;
-    int64_t *th = (int64_t *)(sh + 2 * nb);
-    for (int i = threadIdx.x; i < nb; i += blockDim.x) {
+    BinEdge *edges = (BinEdge *)(sh + 2 * nb);
+    for (int i = threadIdx.x; i < nb; i += NT) {
         hc[i] = 0.0;
         hk[i] = 0.0;
     }
-    for (int i = threadIdx.x; i <= nb; i += blockDim.x) th[i] = mt.thresh[i];
+    for (int i = threadIdx.x; i <= nb; i += NT)
+        edges[i] = BinEdge{(uint32_t)mt.thresh[i], i < nb ? (uint32_t)mt.thresh[i + 1] : 0xffffffffu};
     __syncthreads();
-    const double inv_qmax = 1.0 / mt.qmax;
-    const int64_t total = (int64_t)mt.nxk * n1 * n2;
-    for (int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; m < total;
-         m += (int64_t)gridDim.x * blockDim.x) {
-        if (m == 0) continue;
-        const int kx = (int)(m % mt.nxk);
-        const int64_t r = m / mt.nxk;
-        const int ky = (int)(r % n1);
-        const int kz = (int)(r / n1);
-        const int64_t q = mt.q[0][kx] + mt.q[1][ky] + mt.q[2][kz];
-        const int b = bin_of(q, th, nb, inv_qmax);
+    const float cq = (float)((double)nb * nb / mt.qmax);
+    const uint32_t qu = mt.qz_unit;
+    const int64_t ncols = (int64_t)mt.nxk * n1;
+    const int64_t ntiles = (ncols + B - 1) / B;
+    const int col = threadIdx.x % B, rg = threadIdx.x / B;
+    const int ep = (n2 + RG - 1) / RG;
+    const int k0 = rg * ep;
+    const int k1 = k0 + ep < n2 ? k0 + ep : n2;  // this thread's run [k0, k1)
+    for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        const int64_t f = t * B + col;
+        if (f >= ncols) continue;
+        const int kx = (int)(f % mt.nxk), ky = (int)(f / mt.nxk);
+        // the half-spectrum weight (1 or 2, exact) is applied at each flush
         const double w = (mt.half && !(kx == 0 || 2 * kx == mt.n0)) ? 2.0 : 1.0;
-        atomicAdd(&hc[b], w);
-        atomicAdd(&hk[b], w * sqrt((double)q));
+        const uint32_t qxy = (uint32_t)(mt.q[0][kx] + mt.q[1][ky]);  // q < 2^32 (plan check)
+        int cur = -1;
+        double cnt = 0.0, sk = 0.0;
+        for (int kz = k0; kz < k1; ++kz) {
+            if (kx == 0 && ky == 0 && kz == 0) continue;  // the zero mode is in no bin
+            const uint32_t m = (uint32_t)(2 * kz < n2 ? kz : n2 - kz);
+            const uint32_t q = qxy + m * m * qu;
+            const int b = bin_edge(q, nb, cq, edges);
+            if (b != cur) {
+                if (cur >= 0) {
+                    atomicAdd(&hc[cur], w * cnt);
+                    atomicAdd(&hk[cur], w * sk);
+                }
+                cur = b;
+                cnt = 0.0;
+                sk = 0.0;
+            }
+            cnt += 1.0;
+            sk += sqrt((double)q);
+        }
+        if (cur >= 0) {
+            atomicAdd(&hc[cur], w * cnt);
+            atomicAdd(&hk[cur], w * sk);
+        }
     }
     __syncthreads();
-    for (int i = threadIdx.x; i < nb; i += blockDim.x) {
+    for (int i = threadIdx.x; i < nb; i += NT) {
         pc[(int64_t)blockIdx.x * nb + i] = hc[i];
         pkk[(int64_t)blockIdx.x * nb + i] = hk[i];
     }
