@@ -10,53 +10,64 @@
 
 namespace lf2 {
 
-// Periodic halo update.  The halo sites of the padded box are enumerated in
-// three slabs so that no thread visits an interior site: the 2h z-planes
-// (all y, x), the 2h y-rows of the interior planes (all x), and the 2h
-// x-sites of the interior rows.  Thread = (halo site, 4-byte word of the
-// site), words fastest, so rows copy contiguously.
+// Periodic halo update.  The halo sites of the padded box are enumerated so
+// that no thread visits an interior site: whole padded rows for the 2h
+// z-planes (all y) and for the 2h y-rows of the interior planes, one block
+// per row with the row's source computed once and 4-byte words walked
+// contiguously; then the 2h x-sites at both ends of every interior row,
+// one thread per (row, site, word).  Every source is the interior site at
+// the coordinates taken modulo the extents (any h, also h > n).
 struct HaloArgs {
     uint32_t *f;
     int64_t n0, n1, n2, h;
-    int64_t p0, p1;  // padded extents of x and y
-    int64_t words;   // 4-byte words per site
-    int64_t nz, ny, nx, total;  // sites in the three slabs and their sum
+    int64_t p0, p1;    // padded extents of x and y
+    int64_t words;     // 4-byte words per site
+    int64_t rows_z;    // 2h p1 rows of the z slabs
+    int64_t rows;      // rows_z + n2 2h rows of the y slabs (one block each)
+    int64_t xwork;     // n2 n1 2h words threads of the x slabs
 };
+
+__device__ __forceinline__ int64_t halo_wrap(int64_t c, int64_t h, int64_t n)
+{
+    return h + ((c - h) % n + n) % n;
+}
 
 __global__ __launch_bounds__(256) void k_update_halo(HaloArgs a)
 {
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < a.total * a.words;
-         t += stride) {
-        const int64_t s = t / a.words, w = t - s * a.words;
-        int64_t x, y, z;
-        if (s < a.nz) {  // z slabs: 2h planes of p1 x p0 sites
-            const int64_t pl = s / (a.p1 * a.p0), r = s - pl * (a.p1 * a.p0);
-            z = pl < a.h ? pl : a.n2 + pl;  // [0, h) then [n2 + h, n2 + 2h)
-            y = r / a.p0;
-            x = r - y * a.p0;
-        } else if (s < a.nz + a.ny) {  // y slabs: n2 planes x 2h rows x p0
-            const int64_t u = s - a.nz;
-            const int64_t pl = u / (2 * a.h * a.p0), r = u - pl * (2 * a.h * a.p0);
-            const int64_t row = r / a.p0;
+    const int words = (int)a.words, p0 = (int)a.p0, h = (int)a.h, n0 = (int)a.n0;
+    const int64_t rowwords = a.p0 * a.words;
+    if ((int64_t)blockIdx.x < a.rows) {
+        const int64_t r = blockIdx.x;
+        int64_t z, y;
+        if (r < a.rows_z) {  // z slabs: planes [0, h) and [n2 + h, n2 + 2h), all rows
+            const int64_t pl = r / a.p1;
+            y = r - pl * a.p1;
+            z = pl < a.h ? pl : a.n2 + pl;
+        } else {  // y slabs of the interior planes
+            const int64_t u = r - a.rows_z, pl = u / (2 * a.h), row = u - pl * (2 * a.h);
             z = a.h + pl;
             y = row < a.h ? row : a.n1 + row;
-            x = r - row * a.p0;
-        } else {  // x slabs: n2 x n1 interior rows x 2h sites
-            const int64_t u = s - a.nz - a.ny;
-            const int64_t rowi = u / (2 * a.h), c = u - rowi * (2 * a.h);
-            z = a.h + rowi / a.n1;
-            y = a.h + rowi % a.n1;
-            x = c < a.h ? c : a.n0 + c;
         }
-        // source: the interior site at the coordinates modulo the extents
-        const int64_t sz = a.h + ((z - a.h) % a.n2 + a.n2) % a.n2;
-        const int64_t sy = a.h + ((y - a.h) % a.n1 + a.n1) % a.n1;
-        const int64_t sx = a.h + ((x - a.h) % a.n0 + a.n0) % a.n0;
-        const int64_t dst = ((z * a.p1 + y) * a.p0 + x) * a.words + w;
-        const int64_t src = ((sz * a.p1 + sy) * a.p0 + sx) * a.words + w;
-        a.f[dst] = a.f[src];
+        const uint32_t *src =
+            a.f + (halo_wrap(z, a.h, a.n2) * a.p1 + halo_wrap(y, a.h, a.n1)) * rowwords;
+        uint32_t *dst = a.f + (z * a.p1 + y) * rowwords;
+        for (int i = threadIdx.x; i < p0 * words; i += 256) {
+            const int x = i / words, w = i - x * words;
+            const int sx = (x >= h && x < h + n0) ? x : h + ((x - h) % n0 + n0) % n0;
+            dst[i] = src[sx * words + w];
+        }
+        return;
     }
+    const int64_t e = ((int64_t)blockIdx.x - a.rows) * 256 + threadIdx.x;
+    if (e >= a.xwork) return;
+    const int per = 2 * h * words;  // words of the x halo of one row
+    const int64_t row = e / per;
+    const int c = (int)(e - row * per), k = c / words, w = c - k * words;
+    const int64_t zi = row / a.n1, yi = row - zi * a.n1;
+    const int x = k < h ? k : n0 + k;
+    const int sx = h + ((x - h) % n0 + n0) % n0;
+    uint32_t *base = a.f + ((a.h + zi) * a.p1 + a.h + yi) * rowwords;
+    base[x * words + w] = base[sx * words + w];
 }
 
 hipError_t launch_update_halo(void *field, const int64_t n[3], int64_t h, int64_t site_words,
@@ -72,14 +83,12 @@ hipError_t launch_update_halo(void *field, const int64_t n[3], int64_t h, int64_
     a.p0 = n[0] + 2 * h;
     a.p1 = n[1] + 2 * h;
     a.words = site_words;
-    a.nz = 2 * h * a.p1 * a.p0;
-    a.ny = n[2] * 2 * h * a.p0;
-    a.nx = n[2] * n[1] * 2 * h;
-    a.total = a.nz + a.ny + a.nx;
-    const int64_t work = a.total * a.words;
-    const int64_t blocks = (work + 255) / 256;
-    const unsigned grid = (unsigned)(blocks < 65536 ? blocks : 65536);
-    hipLaunchKernelGGL(k_update_halo, dim3(grid), dim3(256), 0, s, a);
+    a.rows_z = 2 * h * a.p1;
+    a.rows = a.rows_z + n[2] * 2 * h;
+    a.xwork = n[2] * n[1] * 2 * h * site_words;
+    const int64_t blocks = a.rows + (a.xwork + 255) / 256;
+    if (blocks > 0x7fffffff || a.p0 * site_words > 0x7fffffff) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_update_halo, dim3((unsigned)blocks), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 

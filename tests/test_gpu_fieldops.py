@@ -36,7 +36,8 @@ def padded_field(shape, h, nc, seed, complex_values=False):
 
 @pytest.mark.parametrize("shape,h,nc,cplx", [((16, 12, 10), 1, 1, False), ((8, 6, 4), 2, 3, False),
                                              ((10, 8, 6), 1, 2, True), ((5, 7, 3), 3, 1, False),
-                                             ((64, 2, 1), 1, 6, False)])
+                                             ((64, 2, 1), 1, 6, False), ((96, 80, 64), 1, 3, False),
+                                             ((300, 4, 5), 2, 1, True)])
 def test_update_halo_bitwise(lf2, shape, h, nc, cplx):
     print(f"case halo {shape} h={h} nc={nc} complex={cplx}", flush=True)
     a = padded_field(shape, h, nc, seed=20, complex_values=cplx)
