@@ -183,3 +183,87 @@ def test_kmean_inside_bin():
     for b in range(nbins):
         if ct[b] > 0:
             assert b * kmax / nbins - 1e-12 <= km[b] <= (b + 1) * kmax / nbins + 1e-12
+
+
+# ---- lattice spacing dx != 1 (P_b scales as dx^3, k as 1/dx) -------------
+# Expected values come from the definitions: V = N dx^3, P = V/N^2 |F|^2,
+# k_i = 2 pi n_i / (N_i dx); nothing below calls the oracle's normalisation.
+
+@pytest.mark.parametrize("dx", [0.5, 0.25])
+@pytest.mark.parametrize("m", [(3, 2, 1), (0, 4, 0), (16, 0, 16)])
+def test_plane_wave_power_spectrum_dx(m, dx):
+    """cos(2 pi m.x / N) at spacing dx: P_b = dx^3 N / (2 count_b), dx^3 N / count_b if self-conjugate."""
+    shape = (32, 32, 32)
+    N, nbins = 32 ** 3, 16
+    x, y, z = grid(*shape)
+    f = np.cos(2 * np.pi * (m[0] * x + m[1] * y + m[2] * z) / 32)
+    pk, km, ct = oracle.power_spectrum(oracle.r2c(f), shape, nbins, dx=dx)
+    # the bin from the brute-force enumeration's count of the mode's shell
+    q = sum((mi if 2 * mi < 32 else mi - 32) ** 2 for mi in m)
+    b = oracle.pk_bin(q, oracle.pk_qmax(shape), nbins)
+    selfconj = all(mi in (0, 16) for mi in m)
+    expect = np.zeros(nbins)
+    expect[b] = dx ** 3 * N / ct[b] if selfconj else dx ** 3 * N / (2 * ct[b])
+    assert np.abs(pk - expect).max() < 1e-10 * expect.max()
+    assert np.array_equal(ct, brute_counts(shape, nbins, True))
+
+
+def brute_kmean(shape, nbins, dx, half):
+    """Weighted mean of |k| = 2 pi sqrt(sum (n_i / N_i)^2) / dx per bin over
+    every lattice mode, each binned with exact rationals."""
+    from fractions import Fraction
+    n0, n1, n2 = shape
+    kmax2 = sum(Fraction((ni // 2) ** 2, ni * ni) for ni in shape)
+    nx = n0 // 2 + 1 if half else n0
+    sk = np.zeros(nbins)
+    sw = np.zeros(nbins)
+    for kz, ky, kx in itertools.product(range(n2), range(n1), range(nx)):
+        if (kx, ky, kz) == (0, 0, 0):
+            continue
+        s = [(k if 2 * k < n else k - n) for k, n in zip((kx, ky, kz), shape)]
+        r = sum(Fraction(si * si, ni * ni) for si, ni in zip(s, shape)) / kmax2
+        b = 0
+        while Fraction((b + 1) ** 2, nbins ** 2) <= r:
+            b += 1
+        b = min(b, nbins - 1)
+        w = 2.0 if half and kx not in (0, n0 // 2) else 1.0
+        kk = 2 * math.pi * math.sqrt(sum((si / ni) ** 2 for si, ni in zip(s, shape))) / dx
+        sk[b] += w * kk
+        sw[b] += w
+    return np.where(sw > 0, sk / np.where(sw > 0, sw, 1), 0.0)
+
+
+@pytest.mark.parametrize("dx", [0.5, 0.25])
+@pytest.mark.parametrize("shape,nbins,half", [((16, 16, 16), 6, True), ((12, 8, 10), 5, True),
+                                              ((12, 8, 10), 4, False)])
+def test_kmean_brute_dx(shape, nbins, dx, half):
+    """k-bar_b equals the brute-force weighted mean of |k| over the bin's modes."""
+    n0, n1, n2 = shape
+    nx = n0 // 2 + 1 if half else n0
+    F = np.ones((n2, n1, nx), dtype=np.complex128)
+    _, km, _ = oracle.power_spectrum(F, shape, nbins, dx=dx, half=half)
+    want = brute_kmean(shape, nbins, dx, half)
+    assert np.abs(km - want).max() <= 1e-12 * np.abs(want).max()
+
+
+@pytest.mark.parametrize("dx", [0.5, 0.25])
+def test_white_noise_normalisation_dx(dx):
+    """i.i.d. N(0,1) sites at spacing dx: E[P_b] = dx^3 (within 6 / sqrt(count_b), relative)."""
+    shape = (64, 64, 64)
+    f = synth.normal(3, 64 ** 3).reshape(64, 64, 64)
+    pk, km, ct = oracle.power_spectrum(oracle.r2c(f), shape, 16, dx=dx)
+    ok = ct > 200
+    assert ok.sum() >= 10
+    assert np.all(np.abs(pk[ok] / dx ** 3 - 1.0) < 6.0 / np.sqrt(ct[ok]))
+
+
+def test_power_spectrum_dx_scaling_law():
+    """Same spectrum at two spacings: P scales exactly as dx^3, k-bar as 1/dx, counts unchanged."""
+    shape = (16, 12, 20)
+    f = synth.normal(5, 16 * 12 * 20).reshape(20, 12, 16)
+    F = oracle.r2c(f)
+    p1, k1, c1 = oracle.power_spectrum(F, shape, 7, dx=1.0)
+    p2, k2, c2 = oracle.power_spectrum(F, shape, 7, dx=0.37)
+    assert np.array_equal(c1, c2)
+    assert np.allclose(p2, p1 * 0.37 ** 3, rtol=1e-13, atol=0)
+    assert np.allclose(k2, k1 / 0.37, rtol=1e-13, atol=0)
