@@ -54,3 +54,18 @@ def grf_field(shape, alpha, seed):
     f64, scale = oracle.grf(shape, alpha, u)
     f32 = f64.astype(np.float32)
     return f32, f32.astype(np.float64), scale
+
+
+def assert_close(got, ref, shape, what: str = "") -> tuple[float, float]:
+    """Gate a GPU result against the oracle on rel-L2 AND on max error.
+
+    Both must be within 1e-5 * log2(N).  The max gate (max|a - b| / max|b|)
+    catches a localized fault that the L2 norm dilutes: at 512^3 one fully
+    wrong mode of a half spectrum moves rel-L2 by only ~1e-4."""
+    t = tol(shape)
+    e, em = rel_l2(got, ref), rel_max(got, ref)
+    if what:
+        print(f"  [{what}] rel-L2 {e:.3e} max {em:.3e} tol {t:.2e}", flush=True)
+    assert e <= t, f"{what}: rel-L2 {e:.3e} above {t:.3e}"
+    assert em <= t, f"{what}: max error {em:.3e} above {t:.3e}"
+    return e, em

@@ -6,7 +6,7 @@ import numpy as np
 import pytest
 
 import oracle
-from gpu_helpers import real_field, complex_field, rel_l2, rel_max, tol
+from gpu_helpers import assert_close, real_field, complex_field, rel_l2, rel_max, tol
 
 pytestmark = pytest.mark.gpu
 
@@ -40,10 +40,8 @@ def test_r2c_paper_layout_forward_backward(lf2, shape):
     back = p.backward(F)
     torch.cuda.synchronize()
     ref = oracle.to_paper_layout(oracle.r2c(f.astype(np.float64)), "r2c")
-    e = rel_l2(F.cpu().numpy(), ref)
-    print(f"  fwd rel-L2 {e:.2e} max {rel_max(F.cpu().numpy(), ref):.2e}", flush=True)
-    assert e <= tol(shape)
-    assert rel_l2(back.cpu().numpy() / np.prod(shape), f) <= tol(shape)
+    assert_close(F.cpu().numpy(), ref, shape, "fwd")
+    assert_close(back.cpu().numpy() / np.prod(shape), f, shape)
 
 
 def test_r2c_paper_layout_components(lf2):
@@ -55,7 +53,7 @@ def test_r2c_paper_layout_components(lf2):
     Fg = F.cpu().numpy()
     for c in range(3):
         ref = oracle.to_paper_layout(oracle.r2c(dense[..., c].astype(np.float64)), "r2c")
-        assert rel_l2(Fg[..., c], ref) <= tol(shape)
+        assert_close(Fg[..., c], ref, shape)
 
 
 @pytest.mark.parametrize("shape", [(32, 24, 16), (64, 64, 64)])
@@ -73,11 +71,11 @@ def test_poisson_and_pk_paper_layout(lf2, shape):
     pk2, _, ct2 = pp.power_spectrum(F, nb, field_is_kspace=True)
     torch.cuda.synchronize()
     f64 = f.astype(np.float64)
-    assert rel_l2(phi.cpu().numpy(), oracle.poisson(f64)) <= tol(shape)
+    assert_close(phi.cpu().numpy(), oracle.poisson(f64), shape)
     opk, _, oct_ = oracle.power_spectrum(oracle.r2c(f64), shape, nb)
-    assert rel_l2(pk.cpu().numpy(), opk) <= tol(shape)
+    assert_close(pk.cpu().numpy(), opk, shape)
     assert np.array_equal(ct.cpu().numpy(), oct_)
-    assert rel_l2(pk2.cpu().numpy(), opk) <= tol(shape)
+    assert_close(pk2.cpu().numpy(), opk, shape)
     assert np.array_equal(ct2.cpu().numpy(), oct_)
     assert rel_l2(phi.cpu().numpy(), phin.cpu().numpy()) <= 1e-6
 
@@ -97,10 +95,10 @@ def test_r2c_in_place(lf2, shape, paper):
     ref = oracle.r2c(f.astype(np.float64))
     if paper:
         ref = oracle.to_paper_layout(ref, "r2c")
-    assert rel_l2(k.cpu().numpy(), ref) <= tol(shape)
+    assert_close(k.cpu().numpy(), ref, shape)
     back = p.backward_(k)
     torch.cuda.synchronize()
-    assert rel_l2(back[..., :n0].cpu().numpy() / np.prod(shape), f) <= tol(shape)
+    assert_close(back[..., :n0].cpu().numpy() / np.prod(shape), f, shape)
 
 
 @pytest.mark.parametrize("shape,ncomp", [((32, 24, 16), 1), ((16, 12, 10), 3), ((4, 4, 512), 1)])
@@ -120,10 +118,10 @@ def test_c2c_in_place(lf2, shape, ncomp):
     if ncomp == 1:
         got = got[..., None]
     for c in range(ncomp):
-        assert rel_l2(got[..., c], oracle.c2c(z[..., c].astype(np.complex128), -1)) <= tol(shape)
+        assert_close(got[..., c], oracle.c2c(z[..., c].astype(np.complex128), -1), shape)
     b = p.backward_(k)
     torch.cuda.synchronize()
-    assert rel_l2(b.cpu().numpy() / np.prod(shape), zz) <= tol(shape)
+    assert_close(b.cpu().numpy() / np.prod(shape), zz, shape)
 
 
 def test_poisson_in_place(lf2):
@@ -135,7 +133,7 @@ def test_poisson_in_place(lf2):
     x[..., :n0] = torch.from_numpy(f).to(dev())
     p.poisson(x, phi=x)
     torch.cuda.synchronize()
-    assert rel_l2(x[..., :n0].cpu().numpy(), oracle.poisson(f.astype(np.float64))) <= tol(shape)
+    assert_close(x[..., :n0].cpu().numpy(), oracle.poisson(f.astype(np.float64)), shape)
 
 
 @pytest.mark.parametrize("shape,ncomp", [((32, 24, 16), 1), ((16, 12, 10), 3), ((8, 6, 512), 1),
@@ -155,9 +153,8 @@ def test_c2c_paper_layout(lf2, shape, ncomp):
         Fg = Fg[..., None]
     for c in range(ncomp):
         ref = oracle.to_paper_layout(oracle.c2c(z[..., c].astype(np.complex128), -1), "c2c")
-        e = rel_l2(Fg[..., c], ref)
-        assert e <= tol(shape), (c, e)
-    assert rel_l2(back.cpu().numpy() / np.prod(shape), zz) <= tol(shape)
+        assert_close(Fg[..., c], ref, shape, f"comp {c}")
+    assert_close(back.cpu().numpy() / np.prod(shape), zz, shape)
     # in place, and the power spectrum of a spectrum in this order
     if ncomp == 1:
         q = lf2.Plan(shape, lf2.LF2_C2C, in_place=True, paper_layout=True)
@@ -168,5 +165,5 @@ def test_c2c_paper_layout(lf2, shape, ncomp):
         assert rel_l2(k.cpu().numpy(), F.cpu().numpy()) <= 1e-6
         opk, _, oct_ = oracle.power_spectrum(oracle.c2c(z[..., 0].astype(np.complex128), -1), shape,
                                              8, half=False)
-        assert rel_l2(pk.cpu().numpy(), opk) <= tol(shape)
+        assert_close(pk.cpu().numpy(), opk, shape)
         assert np.array_equal(ct.cpu().numpy(), oct_)

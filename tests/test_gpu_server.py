@@ -6,7 +6,7 @@ import pytest
 
 import oracle
 import synth
-from gpu_helpers import rel_l2, tol
+from gpu_helpers import assert_close, rel_l2, tol
 
 pytestmark = pytest.mark.gpu
 
@@ -69,9 +69,9 @@ def test_served_equals_solo_and_oracle(lf2):
         assert torch.equal(cnt, scnt)
         if s[0] * s[1] * s[2] <= 128 ** 3:
             f64 = f.astype(np.float64)
-            assert rel_l2(phi.cpu().numpy(), oracle.poisson(f64)) <= tol(s)
+            assert_close(phi.cpu().numpy(), oracle.poisson(f64), s)
             opk, _, oct_ = oracle.power_spectrum(oracle.r2c(f64), s, nb)
-            assert rel_l2(pk.cpu().numpy(), opk) <= tol(s)
+            assert_close(pk.cpu().numpy(), opk, s)
             assert np.array_equal(cnt.cpu().numpy(), oct_)
 
 
@@ -91,7 +91,7 @@ def test_budget_queues_and_pool_reuse(lf2):
         assert all(r[0] == lf2.LF2_OK for r in res)
         for s, (f, rho, phi, pk, _) in zip(sizes, reqs):
             f64 = f.astype(np.float64)
-            assert rel_l2(phi.cpu().numpy(), oracle.poisson(f64)) <= tol(s)
+            assert_close(phi.cpu().numpy(), oracle.poisson(f64), s)
         print(f"  wave {wave} ok", flush=True)
     stats = srv.stats()
     srv.close()
@@ -138,9 +138,7 @@ def test_serving_config_sizes_against_oracle(lf2):
     assert all(r[0] == lf2.LF2_OK for r in res), res
     for s, (f, rho, phi, pk, cnt) in zip(sizes, reqs):
         f64 = f.astype(np.float64)
-        e = rel_l2(phi.cpu().numpy(), oracle.poisson(f64))
         opk, _, oct_ = oracle.power_spectrum(oracle.r2c(f64), s, nb)
-        epk = rel_l2(pk.cpu().numpy(), opk)
-        print(f"  {s}: phi {e:.2e} pk {epk:.2e}", flush=True)
-        assert e <= tol(s) and epk <= tol(s)
+        assert_close(phi.cpu().numpy(), oracle.poisson(f64), s, f"{s} phi")
+        assert_close(pk.cpu().numpy(), opk, s, f"{s} pk")
         assert np.array_equal(cnt.cpu().numpy(), oct_)
