@@ -179,6 +179,33 @@ lf2_status lf2_poisson_solve(lf2_plan p, const float *rho, float *phi, double dx
                              double *d_parseval, void *stream);
 
 /*
+ * lf2_poisson_solve for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same solve with the same arguments, layouts and results,
+ * but it calls no hipMalloc, hipFree or other allocating routine.  Its
+ * workspace is a static device array of LF2_NOALLOC_SCRATCH_BYTES per GPU,
+ * held by the library from its first use on that GPU until the process
+ * ends.
+ *   - A solve whose workspace (the half spectrum, 8 (N0/2 + 1) N1 N2 bytes,
+ *     plus 8 KiB (nbins + 1) of bin partials) exceeds the array is
+ *     LF2_ERR_UNSUPPORTED (a 256^3 solve fits with up to 4096 bins).
+ *   - The plan's k^2 table for (dx, k^2 kind) and shell table for nbins must
+ *     already exist: an earlier lf2_poisson_solve (or lf2_power_spectrum for
+ *     the shell table) with the same values builds them; otherwise
+ *     LF2_ERR_NOT_READY and nothing is enqueued.
+ *   - Every call on one GPU shares that GPU's array, which keeps what the
+ *     last call left there: calls that overlap on one GPU (several streams
+ *     or host threads at once) race and give wrong results; serialise them.
+ *     Nothing in the array needs to start at zero.
+ *   - Kernel timing (lf2_profile_enable) does not record these launches.
+ */
+#define LF2_NOALLOC_SCRATCH_BYTES ((size_t)128 << 20)
+lf2_status lf2_poisson_solve_noalloc(lf2_plan p, const float *rho, float *phi, double dx,
+                                     uint32_t flags, int32_t nbins, double *d_pk,
+                                     double *d_kmean, double *d_count, double *d_parseval,
+                                     void *stream);
+
+/*
  * Spherical-shell power spectrum (spectral analysis, section 1).  For
  * every mode n != 0 with integer squared radius q = sum_i (nt_i L/N_i)^2,
  * L = lcm(N0, N1, N2), q_max = sum_i (floor(N_i/2) L/N_i)^2, the bin is

@@ -33,6 +33,7 @@ LF2_KLAYOUT_PAPER = 0x2
 LF2_POISSON_CONTINUOUS_K2 = 0
 LF2_POISSON_DISCRETE_K2 = 1
 LF2_PK_OF_PHI = 2
+LF2_NOALLOC_SCRATCH_BYTES = 128 << 20  # static workspace of lf2_poisson_solve_noalloc
 
 
 class lf2_lattice(ctypes.Structure):
@@ -80,6 +81,8 @@ _SIGS = {
     "lf2_plan_set_workspace": (_i32, [_vp, _vp, ctypes.c_size_t]),
     "lf2_fft_execute": (_i32, [_vp, _i32, _vp, _vp, _vp]),
     "lf2_poisson_solve": (_i32, [_vp, _vp, _vp, _f64, _u32, _i32, _vp, _vp, _vp, _vp, _vp]),
+    "lf2_poisson_solve_noalloc": (_i32, [_vp, _vp, _vp, _f64, _u32, _i32, _vp, _vp, _vp, _vp,
+                                         _vp]),
     "lf2_power_spectrum": (_i32, [_vp, _vp, _i32, _i32, _f64, _vp, _vp, _vp, _vp]),
     "lf2_plan_destroy": (_i32, [_vp]),
     "lf2_batch_plan": (_i32, [ctypes.POINTER(_vp), _i32, ctypes.POINTER(lf2_lattice), _u32, _i32,

@@ -112,9 +112,14 @@ hipEvent_t take()
     return e;
 }
 
+// Set while a call that must not allocate runs on this thread: its launches
+// are not recorded (recording may create events).
+thread_local bool t_quiet = false;
+
 // Returns a record index, or -1 when timing is off.
 int begin(const std::string &name, double bytes, hipStream_t s)
 {
+    if (t_quiet) return -1;
     std::lock_guard<std::mutex> lk(mu);
     if (!on) return -1;
     int id = -1;
@@ -282,13 +287,18 @@ ModeTables base_tables(const lf2_plan_s *p)
     return mt;
 }
 
-lf2_status get_k2(lf2_plan p, double dx, int discrete, hipStream_t s, const double *out[3])
+lf2_status get_k2(lf2_plan p, double dx, int discrete, hipStream_t s, const double *out[3],
+                  bool lookup_only)
 {
     for (auto &e : p->k2)
         if (e.dx == dx && e.discrete == discrete) {
             for (int i = 0; i < 3; ++i) out[i] = e.tab[i];
             return LF2_OK;
         }
+    if (lookup_only)
+        return fail(LF2_ERR_NOT_READY,
+                    "no k^2 table for dx = %g (%s) on this plan yet: an allocating call with "
+                    "these arguments builds it", dx, discrete ? "discrete" : "continuous");
     K2Entry e{dx, discrete, {nullptr, nullptr, nullptr}};
     const int64_t cnt[3] = {p->nxk, p->n[1], p->n[2]};
     for (int i = 0; i < 3; ++i) {
@@ -303,13 +313,17 @@ lf2_status get_k2(lf2_plan p, double dx, int discrete, hipStream_t s, const doub
     return LF2_OK;
 }
 
-lf2_status get_shell(lf2_plan p, int nbins, hipStream_t s, ShellEntry *out)
+lf2_status get_shell(lf2_plan p, int nbins, hipStream_t s, ShellEntry *out, bool lookup_only)
 {
     for (auto &e : p->shells)
         if (e.nbins == nbins) {
             *out = e;
             return LF2_OK;
         }
+    if (lookup_only)
+        return fail(LF2_ERR_NOT_READY,
+                    "no %d-bin shell table on this plan yet: an allocating call with this bin "
+                    "count builds it", nbins);
     ShellEntry e{nbins, nullptr, nullptr, nullptr};
     void *ptr;
     lf2_status st = plan_alloc(p, &ptr, (size_t)(nbins + 1) * 8);
@@ -924,7 +938,7 @@ size_t poisson_ws_bytes(const lf2_plan_s *p, int32_t nbins, bool parseval)
 lf2_status poisson_impl(lf2_plan p, const float *rho, float *phi, double dx, uint32_t flags,
                         int32_t nbins, double *d_pk, double *d_kmean, double *d_count,
                         double *d_parseval, hipStream_t stream, char *ws_given,
-                        size_t ws_given_bytes)
+                        size_t ws_given_bytes, bool noalloc)
 {
     if (!p) return fail(LF2_ERR_INVALID_ARG, "plan is NULL");
     if (p->kind != LF2_R2C || p->nc != 1)
@@ -947,17 +961,19 @@ lf2_status poisson_impl(lf2_plan p, const float *rho, float *phi, double dx, uin
     char *ws;
     if (ws_given) {
         if (ws_given_bytes < L.total)
-            return fail(LF2_ERR_INVALID_ARG, "workspace of %zu bytes < %zu needed", ws_given_bytes,
-                        L.total);
+            return fail(noalloc ? LF2_ERR_UNSUPPORTED : LF2_ERR_INVALID_ARG,
+                        "workspace of %zu bytes < %zu needed", ws_given_bytes, L.total);
         ws = ws_given;
+    } else if (noalloc) {
+        return fail(LF2_ERR_INVALID_ARG, "no workspace for a call that must not allocate");
     } else if ((st = get_workspace(p, L.total, &ws))) {
         return st;
     }
     void *W = ws + L.w;
     const double *k2[3];
-    if ((st = get_k2(p, dx, (flags & LF2_POISSON_DISCRETE_K2) ? 1 : 0, s, k2))) return st;
+    if ((st = get_k2(p, dx, (flags & LF2_POISSON_DISCRETE_K2) ? 1 : 0, s, k2, noalloc))) return st;
     ShellEntry sh{};
-    if (nb > 0 && (st = get_shell(p, nb, s, &sh))) return st;
+    if (nb > 0 && (st = get_shell(p, nb, s, &sh, noalloc))) return st;
 
     XArgs xa = x_args(p, rho, W, true, false, true);
     if (parseval) xa.sumsq = (double *)(ws + L.sq);
@@ -1001,6 +1017,55 @@ lf2_status lf2_poisson_solve(lf2_plan p, const float *rho, float *phi, double dx
 {
     return poisson_impl(p, rho, phi, dx, flags, nbins, d_pk, d_kmean, d_count, d_parseval,
                         (hipStream_t)stream, nullptr, 0);
+}
+
+}  // extern "C"
+
+// ------------------------------------------------ static scratch (no allocation)
+// Workspace of lf2_poisson_solve_noalloc: one array per device, held by the
+// code object for the life of the process.  In host code `scratch` names a
+// host-side stand-in, not device memory: only the address that
+// hipGetSymbolAddress returns on a device is used (kernel arguments), and it
+// is looked up once per device with that device current.
+static __device__ __align__(256) char scratch[LF2_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+std::mutex g_scratch_mu;
+char *g_scratch_ptr[kMaxDevices] = {};
+
+lf2_status scratch_on(int dev, char **out)
+{
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr)
+            return fail(LF2_ERR_DEVICE, "hipGetSymbolAddress(scratch) on device %d: %s", dev,
+                        hipGetErrorString(e));
+        g_scratch_ptr[dev] = (char *)ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return LF2_OK;
+}
+}  // namespace
+
+extern "C" {
+
+lf2_status lf2_poisson_solve_noalloc(lf2_plan p, const float *rho, float *phi, double dx,
+                                     uint32_t flags, int32_t nbins, double *d_pk,
+                                     double *d_kmean, double *d_count, double *d_parseval,
+                                     void *stream)
+{
+    if (!p) return fail(LF2_ERR_INVALID_ARG, "plan is NULL");
+    lf2_status st;
+    if ((st = check_device(p))) return st;
+    char *ws = nullptr;
+    if ((st = scratch_on(p->device, &ws))) return st;
+    prof::t_quiet = true;
+    st = poisson_impl(p, rho, phi, dx, flags, nbins, d_pk, d_kmean, d_count, d_parseval,
+                      (hipStream_t)stream, ws, LF2_NOALLOC_SCRATCH_BYTES, true);
+    prof::t_quiet = false;
+    return st;
 }
 
 lf2_status lf2_power_spectrum(lf2_plan p, const void *field, int32_t field_is_kspace, int32_t nbins,

@@ -77,8 +77,12 @@ void end(int idx, hipStream_t s);
 lf2_status plan_alloc(lf2_plan p, void **dst, size_t bytes);
 size_t spectrum_bytes(const lf2_plan_s *p);
 ModeTables base_tables(const lf2_plan_s *p);
-lf2_status get_k2(lf2_plan p, double dx, int discrete, hipStream_t s, const double *out[3]);
-lf2_status get_shell(lf2_plan p, int nbins, hipStream_t s, ShellEntry *out);
+// Tables of a plan, built on first use (lookup_only: never build; a
+// missing table is LF2_ERR_NOT_READY).
+lf2_status get_k2(lf2_plan p, double dx, int discrete, hipStream_t s, const double *out[3],
+                  bool lookup_only = false);
+lf2_status get_shell(lf2_plan p, int nbins, hipStream_t s, ShellEntry *out,
+                     bool lookup_only = false);
 lf2_status check_device(const lf2_plan_s *p);
 lf2_status check_ptr(const void *ptr, const char *what, size_t align);
 XArgs x_args(const lf2_plan_s *p, const void *in, void *out, bool in_is_x, bool out_is_x,
@@ -87,10 +91,12 @@ SArgs s_args(const lf2_plan_s *p, int axis, const void *in, void *out, int epi);
 lf2_status check_bins(const lf2_plan_s *p, int32_t nbins);
 
 size_t poisson_ws_bytes(const lf2_plan_s *p, int32_t nbins, bool parseval);
+// noalloc: use only tables that already exist (LF2_ERR_NOT_READY otherwise)
+// and make no allocation; ws_given must then be given.
 lf2_status poisson_impl(lf2_plan p, const float *rho, float *phi, double dx, uint32_t flags,
                         int32_t nbins, double *d_pk, double *d_kmean, double *d_count,
                         double *d_parseval, hipStream_t stream, char *ws_given,
-                        size_t ws_given_bytes);
+                        size_t ws_given_bytes, bool noalloc = false);
 
 }  // namespace host
 }  // namespace lf2
