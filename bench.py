@@ -85,8 +85,9 @@ def parse_tuning(spec: str) -> dict:
 def bench_batch(args, torch, np, lf2, stream):
     """48 Poisson solves with fused 32-bin P(k) on uneven lattices (extents per
     axis from {64, 96, 128, 160, 192, 256}, field 0 = 128x192x256): one
-    set of grouped launches replayed from a hipGraph against 48 plain
-    lf2_poisson_solve calls.
+    persistent launch replayed from a hipGraph, against the grouped launches
+    (one per pass and line length) and against 48 plain lf2_poisson_solve
+    calls.
     Inputs are seeded N(0,1) fields (run time does not depend on values; the
     random-field parity of the same workload is in the tests)."""
     import synth
@@ -103,6 +104,8 @@ def bench_batch(args, torch, np, lf2, stream):
     kms = [torch.empty(nb, dtype=torch.float64, device=dev) for _ in sizes]
     cts = [torch.empty(nb, dtype=torch.float64, device=dev) for _ in sizes]
     batch = lf2.Batch(sizes, nbins=nb)
+    one_q = lf2.Batch(sizes, nbins=nb, one_queue=True)
+    grouped = lf2.Batch(sizes, nbins=nb, grouped=True)
     plans = {}
     for s in sizes:
         if s not in plans:
@@ -111,6 +114,12 @@ def bench_batch(args, torch, np, lf2, stream):
 
     def run_batch():
         batch.run(rhos, phis, pks, kms, cts, stream=stream)
+
+    def run_grouped():
+        grouped.run(rhos, phis, pks, kms, cts, stream=stream)
+
+    def run_one_queue():
+        one_q.run(rhos, phis, pks, kms, cts, stream=stream)
 
     def run_plain():
         for s, r, p, a, b, c in zip(sizes, rhos, phis, pks, kms, cts):
@@ -133,11 +142,18 @@ def bench_batch(args, torch, np, lf2, stream):
     reps = max(3, args.steps)
     t_batch = timed(run_batch, reps)
     err = batch.error()
+    t_grouped = timed(run_grouped, reps)
+    t_one_q = timed(run_one_queue, reps)
+    err |= one_q.error()
     t_plain = timed(run_plain, reps)
     points = sum(a * b * c for a, b, c in sizes)
     alg = sum(8.0 * a * b * c + 64.0 * (a // 2 + 1) * b * c for a, b, c in sizes)
     nitems, launches, wsb = batch.nitems, batch.launches, batch.workspace_bytes
+    g_launches = grouped.launches
+    queues, per_xcd = batch.queues, batch.per_xcd
     batch.close()
+    grouped.close()
+    one_q.close()
     return {
         "workload": "48 Poisson + 32-bin P(k) solves, extents per axis from {64..256}, "
                     "field 0 = 128x192x256",
@@ -146,6 +162,9 @@ def bench_batch(args, torch, np, lf2, stream):
         "batch_gbps_algorithmic": round(alg / (t_batch * 1e-3) / 1e9, 1),
         "plain_gbps_algorithmic": round(alg / (t_plain * 1e-3) / 1e9, 1),
         "work_items": nitems, "launches_per_run": launches, "plain_launches_per_run": 48 * 7,
+        "queues": queues, "queue_per_xcd": per_xcd,
+        "one_queue_ms": round(t_one_q, 4),
+        "grouped_ms": round(t_grouped, 4), "grouped_launches_per_run": g_launches,
         "error_bits": err,
     }
 

@@ -103,12 +103,15 @@ typedef struct lf2_plan_s *lf2_plan;
 
 /*
  * Create a plan for a 3-D transform on `lat` with `ncomp` components
- * (PlanFFT, section 3.6).  Extents must factor into 2, 3 and 5 with at
- * most one factor 3 or 5 per extent (LF2_ERR_UNSUPPORTED otherwise); r2c
- * needs an even N0.  Compiled line lengths: 1..1024 along x (N0/2 for
- * r2c), 1..2048 along y and z; ncomp 1, 2, 3 or 6.  The plan is bound to the current HIP device; its
- * twiddles (generated in FP64 on the device, rounded once to FP32) stay
- * resident until lf2_plan_destroy.  Synchronises the device once.
+ * (PlanFFT, section 3.6).  Extents must factor into 2, 3 and 5
+ * (LF2_ERR_UNSUPPORTED otherwise); r2c needs an even N0.  Line lengths
+ * (N0/2 for r2c along x) with compiled kernels: 2^a, 3 2^a and 5 2^a up to
+ * 1024 along x with ncomp 1, 2, 3 or 6, and up to 2048 along y and z; every
+ * other 2^a 3^b 5^c line up to 8192 points (and any ncomp) runs kernels
+ * with a run-time radix schedule (lf2_plan_get_schedule), as long as a tile
+ * of one line fits the device's LDS.  The plan is bound to the current HIP
+ * device; its twiddles (generated in FP64 on the device, rounded once to
+ * FP32) stay resident until lf2_plan_destroy.  Synchronises the device once.
  */
 lf2_status lf2_fft_plan(lf2_plan *out, const lf2_lattice *lat, int32_t ncomp, lf2_fft_kind kind,
                         uint32_t flags);
@@ -134,12 +137,33 @@ lf2_status lf2_fft_kspace(lf2_plan p, int64_t ksize[3], int64_t kstride[3]);
  * nontemporal accesses and chunk 16.  get reports the setting and, after
  * LF2_PLAN_AUTOTUNE, the measured microseconds of the default setting
  * (variant 0, chunk 16) and of the chosen one (-1 if not measured); null
- * outputs are skipped.  set overrides the setting (LF2_ERR_UNSUPPORTED for
- * wide tiles on a length without them).
+ * outputs are skipped; variant -1 means the axis runs a run-time radix
+ * schedule (lf2_plan_get_schedule).  set overrides the setting and returns
+ * the axis to its compiled kernels (LF2_ERR_UNSUPPORTED for wide tiles on a
+ * length without them, or for a length without compiled kernels).
  */
 lf2_status lf2_plan_get_tuning(lf2_plan p, int32_t axis, int32_t *variant, int32_t *chunk,
                                double *us_default, double *us_tuned);
 lf2_status lf2_plan_set_tuning(lf2_plan p, int32_t axis, int32_t variant, int32_t chunk);
+
+/*
+ * Radix schedule (the radices of the Stockham stages, in order; their
+ * product is the line length) of the passes along `axis` (0 = x, 1 = y,
+ * 2 = z).  Line lengths with compiled kernels use a schedule fixed at
+ * compile time; any other 2^a 3^b 5^c length, and any pass for which a
+ * schedule is set, runs kernels that take the schedule at run time (*runtime
+ * = 1).  LF2_PLAN_AUTOTUNE times the candidate schedules of every such axis,
+ * and of the y and z passes against their compiled kernels, and keeps the
+ * fastest.  get: radices[0 .. *nstages - 1] (the rest 0); any output may be
+ * NULL.  set: each radix 2, 3, 4, 5, 8 or 16 with product the line length;
+ * the fused Poisson / power-spectrum pass of a compiled length keeps its
+ * compiled kernel; the x pass of a compiled length cannot be set
+ * (LF2_ERR_UNSUPPORTED).  Every schedule computes the same transform up to
+ * FP32 rounding.
+ */
+lf2_status lf2_plan_get_schedule(lf2_plan p, int32_t axis, int32_t radices[15], int32_t *nstages,
+                                 int32_t *runtime);
+lf2_status lf2_plan_set_schedule(lf2_plan p, int32_t axis, const int32_t *radices, int32_t nstages);
 
 /* Bytes of shared workspace an execute call on this plan may use. */
 lf2_status lf2_plan_workspace_bytes(lf2_plan p, size_t *bytes);
@@ -227,27 +251,45 @@ lf2_status lf2_power_spectrum(lf2_plan p, const void *field, int32_t field_is_ks
 lf2_status lf2_plan_destroy(lf2_plan p);
 
 /*
- * Batched Poisson solves on many lattices of different sizes.  The work of
- * all fields is grouped by pass and line length: one launch per group
- * (passes x r2c, y, z Poisson [+ binning], y backward, x c2r), each block
- * taking one (field, tile) item, then one launch that finalizes every
- * field's power spectrum.  The launches are captured once in a hipGraph in
- * which each group depends only on the previous pass's groups that hold one
- * of its fields (the finalize on the z groups), so independent groups run
- * concurrently; lf2_batch_execute replays the graph.  Each field gives the same result as
- * lf2_poisson_solve on it alone (power spectra within FP64 summation
- * order).
+ * Batched Poisson solves on many lattices of different sizes.
+ *
+ * By default the whole batch -- x r2c, y, z Poisson [+ binning], y backward
+ * and x c2r passes of every field, and the finalize of every field's power
+ * spectrum -- runs as ONE launch of a persistent kernel, captured once in a
+ * hipGraph that lf2_batch_execute replays.  Its blocks take (field, pass,
+ * tile) work items from work queues in an order in which every item comes
+ * after the items it depends on (one atomic ticket per queue), wait on
+ * per-(field, pass) completion counters, and publish their own; the last
+ * block to finish resets the queues for the next run.  When the fields
+ * spread evenly over the XCDs (greedy by bytes, the largest XCD share at
+ * most 1.25x the mean) there is one queue per XCD holding whole fields, and
+ * each block serves the queue of the XCD it runs on, so every tile is
+ * written and read through one L2; otherwise, or with LF2_BATCH_ONE_QUEUE,
+ * one queue serves the whole chip (each item then writes back and
+ * invalidates the L2 around its wait and its publication).  Every wait is
+ * bounded: a wait that gives up (about a quarter of a second) sets bit 0 of
+ * the batch's error word, after which no block of that run waits and the
+ * launch ends; a queue left with unclaimed items sets bit 1.
+ * With LF2_BATCH_GROUPED the items are instead grouped by pass and line
+ * length: one launch per group plus one finalize launch, captured in a
+ * hipGraph in which each group depends only on the previous pass's groups
+ * that hold one of its fields.
+ * Each field gives the same result as lf2_poisson_solve on it alone (power
+ * spectra within FP64 summation order).
  *
  * lats: nfields dense lattices (halo 0) whose N0/2, N1 and N2 are each one
  *   of 16, 32, 48, 64, 80, 96, 128, 160, 192, 256, 384.
  * ops: LF2_BATCH_POISSON, optionally | LF2_BATCH_PK for the fused
- *   power spectrum of each rho with nbins bins (1..511).
+ *   power spectrum of each rho with nbins bins (1..511), optionally
+ *   | LF2_BATCH_GROUPED or | LF2_BATCH_ONE_QUEUE.
  * poisson_flags: 0 or LF2_POISSON_DISCRETE_K2.
  * The batch owns the spectra of all fields (lf2_batch_info).  Plan creation
  * synchronises the device.
  */
 #define LF2_BATCH_POISSON 1u
 #define LF2_BATCH_PK 2u
+#define LF2_BATCH_GROUPED 4u
+#define LF2_BATCH_ONE_QUEUE 8u
 typedef struct lf2_batch_s *lf2_batch;
 
 lf2_status lf2_batch_plan(lf2_batch *out, int32_t nfields, const lf2_lattice *lats, uint32_t ops,
@@ -265,9 +307,17 @@ lf2_status lf2_batch_execute(lf2_batch b, const float *const *rho, float *const 
                              double *const *d_pk, double *const *d_kmean, double *const *d_count,
                              void *stream);
 
-/* Synchronise the device; *err = 0, or LF2_ERR_DEVICE if a HIP error is
- * pending from the batch's launches. */
+/* Synchronise the device and read the batch's error word into *err (0: the
+ * runs since the last call completed normally; bit 0: a persistent run gave
+ * up a dependency wait, bit 1: a queue was left with unclaimed items -- the
+ * results are then not valid).  A set word is
+ * cleared by this call; until then every later run of the batch is invalid
+ * as well.  LF2_ERR_DEVICE if a HIP error is pending. */
 lf2_status lf2_batch_error(lf2_batch b, uint32_t *err);
+
+/* Queues of the persistent launch (0 in grouped mode) and whether each
+ * serves one XCD (1) or the whole chip (0); either may be NULL. */
+lf2_status lf2_batch_queues(lf2_batch b, int32_t *nqueues, int32_t *per_xcd);
 
 /* Work items, kernel launches per execution and workspace bytes. */
 lf2_status lf2_batch_info(lf2_batch b, int64_t *nitems, int32_t *launches,
@@ -278,15 +328,20 @@ lf2_status lf2_batch_destroy(lf2_batch b);
 /*
  * Serving: a request loop for Poisson solves with optional power spectra on
  * lattices of mixed sizes (continuous batching).  A scheduler thread admits
- * queued requests in arrival order while their footprint (rho + phi +
- * spectrum workspace + bin partials) fits the HBM budget and a slot is
- * free, and launches each admitted request at once on one of `nstreams`
- * streams, so requests that arrive while others run join the device work
- * as capacity frees up.  Plans (twiddles, wavevector and shell tables) stay
- * resident in a cache keyed by lattice; workspaces are pooled.  A
- * completion thread timestamps each request when its work has finished and
- * returns its capacity.  Requests are independent: each gives the same
- * result as lf2_poisson_solve on its own.
+ * queued requests in launch units while a slot is free: the request at the
+ * head of the queue, joined by the queued requests with the same lattice,
+ * lattice spacing, k^2 kind and bin count (up to 16, lattices whose lines
+ * have grouped kernels) -- those run as ONE grouped solve, a launch per pass
+ * over all of them.  A unit takes one slot; every request in it is charged
+ * its footprint (rho + phi + workspace) against the HBM budget, and the
+ * idle pooled workspace counts against the budget too (idle buffers are
+ * freed when a request needs the room).  Each unit is launched at once on
+ * one of `nstreams` streams, so requests that arrive while others run join
+ * the device work as capacity frees up.  Plans (twiddles, wavevector and
+ * shell tables) stay resident in a cache keyed by lattice.  A completion
+ * thread timestamps each request when its work has finished and returns its
+ * capacity.  Requests are independent: each gives the same result as
+ * lf2_poisson_solve on its own (power spectra within FP64 summation order).
  *
  * The caller owns rho, phi and the bin arrays of a request and keeps them
  * valid until lf2_server_poll reports it done.  The server's streams do not
@@ -318,10 +373,14 @@ typedef struct {
     int64_t in_flight, queued;
     size_t bytes_in_flight, peak_bytes_in_flight;
     int64_t plans_cached, plan_hits, plan_misses;
+    int64_t groups, grouped_requests;     /* grouped solves launched, requests in them */
+    size_t pooled_idle_bytes;             /* idle pooled workspace (counts against the budget) */
+    size_t peak_bytes_in_use;             /* largest in-flight + idle pooled bytes seen */
 } lf2_server_stats;
 
 /* Create a GPU server on the current device.  hbm_budget_bytes bounds the
- * summed footprint of admitted requests; max_slots bounds requests in
+ * summed footprint of admitted requests plus the idle pooled workspace;
+ * max_slots bounds launch units (single requests or grouped solves) in
  * flight; nstreams (>= 1) streams of default priority; max_queue bounds
  * requests waiting for admission. */
 lf2_status lf2_server_create(lf2_server *out, size_t hbm_budget_bytes, int32_t max_slots,

@@ -14,7 +14,8 @@ Layouts (N0 fastest, paper section 3.4; components innermost, 3.5):
 from __future__ import annotations
 
 from . import _lib
-from ._lib import (LF2_BACKWARD, LF2_BATCH_PK, LF2_BATCH_POISSON, LF2_C2C, LF2_FORWARD,
+from ._lib import (LF2_BACKWARD, LF2_BATCH_GROUPED, LF2_BATCH_ONE_QUEUE, LF2_BATCH_PK,
+                   LF2_BATCH_POISSON, LF2_C2C, LF2_FORWARD,
                    LF2_PK_OF_PHI, LF2_POISSON_DISCRETE_K2, LF2_R2C, LF2Error, lf2_batch_destroy,
                    lf2_batch_error, lf2_batch_execute, lf2_batch_info, lf2_batch_plan,
                    lf2_fft_execute, lf2_fft_kspace, lf2_fft_plan, lf2_plan_destroy,
@@ -24,7 +25,8 @@ from ._lib import (LF2_ERR_BUDGET, LF2_ERR_BUSY, LF2_ERR_DEVICE, LF2_ERR_INVALID
                    LF2_ERR_NOT_READY, LF2_ERR_UNSUPPORTED, LF2_OK)
 
 __all__ = ["Plan", "Batch", "LF2Error", "LF2_R2C", "LF2_C2C", "LF2_FORWARD", "LF2_BACKWARD",
-           "LF2_POISSON_DISCRETE_K2", "LF2_PK_OF_PHI", "LF2_BATCH_POISSON", "LF2_BATCH_PK",
+           "LF2_POISSON_DISCRETE_K2", "LF2_PK_OF_PHI", "LF2_BATCH_POISSON", "LF2_BATCH_PK", "LF2_BATCH_GROUPED",
+           "LF2_BATCH_ONE_QUEUE",
            "lf2_fft_plan", "lf2_fft_execute", "lf2_fft_kspace", "lf2_poisson_solve",
            "lf2_power_spectrum", "lf2_plan_destroy", "lf2_plan_workspace_bytes",
            "lf2_plan_set_workspace", "lf2_batch_plan", "lf2_batch_execute", "lf2_batch_error",
@@ -79,6 +81,13 @@ class Plan:
 
     def set_tuning(self, axis, variant, chunk=16):
         _lib.lf2_plan_set_tuning(self.handle, axis, variant, chunk)
+
+    def schedule(self, axis):
+        """(radices, runtime) of the passes along axis (0 = x, 1 = y, 2 = z)."""
+        return _lib.lf2_plan_get_schedule(self.handle, axis)
+
+    def set_schedule(self, axis, radices):
+        _lib.lf2_plan_set_schedule(self.handle, axis, radices)
 
     def close(self):
         if self.handle:
@@ -216,15 +225,22 @@ class Plan:
 
 class Batch:
     """Batched Poisson solves (optionally with fused power spectra) on many
-    lattices: grouped launches replayed from one hipGraph (see lf2_batch_plan
+    lattices: one persistent launch replayed from a hipGraph, or with
+    grouped=True one launch per (pass, line length) group (see lf2_batch_plan
     in include/lf2.h)."""
 
-    def __init__(self, sizes_list, nbins=0, dx=1.0, poisson_flags=0):
+    def __init__(self, sizes_list, nbins=0, dx=1.0, poisson_flags=0, grouped=False,
+                 one_queue=False):
         self.sizes = [tuple(int(v) for v in s) for s in sizes_list]
         self.nbins = int(nbins)
         ops = LF2_BATCH_POISSON | (LF2_BATCH_PK if nbins > 0 else 0)
+        if grouped:
+            ops |= LF2_BATCH_GROUPED
+        if one_queue:
+            ops |= LF2_BATCH_ONE_QUEUE
         self.handle = lf2_batch_plan(self.sizes, ops, nbins, dx, poisson_flags)
         self.nitems, self.launches, self.workspace_bytes = lf2_batch_info(self.handle)
+        self.queues, self.per_xcd = _lib.lf2_batch_queues(self.handle)
 
     def close(self):
         if self.handle:

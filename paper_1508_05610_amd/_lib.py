@@ -64,7 +64,9 @@ class lf2_server_stats(ctypes.Structure):
                 ("rejected_budget", ctypes.c_int64), ("in_flight", ctypes.c_int64),
                 ("queued", ctypes.c_int64), ("bytes_in_flight", ctypes.c_size_t),
                 ("peak_bytes_in_flight", ctypes.c_size_t), ("plans_cached", ctypes.c_int64),
-                ("plan_hits", ctypes.c_int64), ("plan_misses", ctypes.c_int64)]
+                ("plan_hits", ctypes.c_int64), ("plan_misses", ctypes.c_int64),
+                ("groups", ctypes.c_int64), ("grouped_requests", ctypes.c_int64),
+                ("pooled_idle_bytes", ctypes.c_size_t), ("peak_bytes_in_use", ctypes.c_size_t)]
 
 
 _lib = None
@@ -78,6 +80,9 @@ _SIGS = {
     "lf2_plan_get_tuning": (_i32, [_vp, _i32, ctypes.POINTER(_i32), ctypes.POINTER(_i32),
                                    ctypes.POINTER(_f64), ctypes.POINTER(_f64)]),
     "lf2_plan_set_tuning": (_i32, [_vp, _i32, _i32, _i32]),
+    "lf2_plan_get_schedule": (_i32, [_vp, _i32, ctypes.POINTER(_i32), ctypes.POINTER(_i32),
+                                     ctypes.POINTER(_i32)]),
+    "lf2_plan_set_schedule": (_i32, [_vp, _i32, ctypes.POINTER(_i32), _i32]),
     "lf2_plan_set_workspace": (_i32, [_vp, _vp, ctypes.c_size_t]),
     "lf2_fft_execute": (_i32, [_vp, _i32, _vp, _vp, _vp]),
     "lf2_poisson_solve": (_i32, [_vp, _vp, _vp, _f64, _u32, _i32, _vp, _vp, _vp, _vp, _vp]),
@@ -94,6 +99,7 @@ _SIGS = {
     "lf2_batch_info": (_i32, [_vp, ctypes.POINTER(_i64), ctypes.POINTER(_i32),
                               ctypes.POINTER(ctypes.c_size_t)]),
     "lf2_batch_destroy": (_i32, [_vp]),
+    "lf2_batch_queues": (_i32, [_vp, ctypes.POINTER(_i32), ctypes.POINTER(_i32)]),
     "lf2_server_create": (_i32, [ctypes.POINTER(_vp), ctypes.c_size_t, _i32, _i32, _i32]),
     "lf2_server_create_fake": (_i32, [ctypes.POINTER(_vp), ctypes.c_size_t, _i32, _i32, _u32,
                                       ctypes.c_uint64]),
@@ -193,6 +199,22 @@ def lf2_plan_set_tuning(plan: int, axis: int, variant: int, chunk: int = 16):
            "lf2_plan_set_tuning")
 
 
+def lf2_plan_get_schedule(plan: int, axis: int):
+    """(radices tuple, runtime flag) of the passes along axis."""
+    r = (_i32 * 15)()
+    n = _i32()
+    rt = _i32()
+    _check(load().lf2_plan_get_schedule(plan, int(axis), r, ctypes.byref(n), ctypes.byref(rt)),
+           "lf2_plan_get_schedule")
+    return tuple(r[i] for i in range(n.value)), bool(rt.value)
+
+
+def lf2_plan_set_schedule(plan: int, axis: int, radices):
+    arr = (_i32 * 15)(*[int(v) for v in radices])
+    _check(load().lf2_plan_set_schedule(plan, int(axis), arr, len(radices)),
+           "lf2_plan_set_schedule")
+
+
 def lf2_plan_workspace_bytes(plan: int) -> int:
     b = ctypes.c_size_t()
     _check(load().lf2_plan_workspace_bytes(plan, ctypes.byref(b)), "lf2_plan_workspace_bytes")
@@ -229,6 +251,8 @@ def lf2_plan_destroy(plan: int):
 
 LF2_BATCH_POISSON = 1
 LF2_BATCH_PK = 2
+LF2_BATCH_GROUPED = 4
+LF2_BATCH_ONE_QUEUE = 8
 
 
 def _lattices(sizes_list):
@@ -245,6 +269,14 @@ def lf2_batch_plan(sizes_list, ops: int, nbins: int = 0, dx: float = 1.0,
     _check(load().lf2_batch_plan(ctypes.byref(out), len(sizes_list), lats, int(ops), int(nbins),
                                  float(dx), int(poisson_flags)), "lf2_batch_plan")
     return out.value
+
+
+def lf2_batch_queues(batch: int):
+    """(queues of the persistent launch, 1 if each serves one XCD)."""
+    n = _i32()
+    x = _i32()
+    _check(load().lf2_batch_queues(batch, ctypes.byref(n), ctypes.byref(x)), "lf2_batch_queues")
+    return int(n.value), int(x.value)
 
 
 def lf2_batch_plan_status(sizes_list, ops: int, nbins: int = 0, dx: float = 1.0,

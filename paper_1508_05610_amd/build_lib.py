@@ -37,6 +37,7 @@ UNITS = [
     ("lf2_ks.hip", [], "ks.o"),
     ("lf2_kmisc.hip", [], "kmisc.o"),
     ("lf2_kbatch.hip", [], "kbatch.o"),
+    ("lf2_kgen.hip", [], "kgen.o"),
     ("lf2_api.cpp", ["-x", "hip"], "api.o"),
     ("lf2_batch.cpp", ["-x", "hip"], "batch.o"),
     ("lf2_server.cpp", ["-x", "hip"], "server.o"),

@@ -22,6 +22,7 @@
 #include <string>
 #include <vector>
 
+#include "lf2_device.hpp"
 #include "lf2_internal.hpp"
 #include "lf2_plan.hpp"
 
@@ -63,21 +64,24 @@ int64_t gcd64(int64_t a, int64_t b)
     return a;
 }
 
-bool radix_ok(int64_t n)
+// Columns of a run-time-schedule strided tile of lines of L points: as many
+// as fit the block's LDS (at most 64), 0 if not even one does.
+int gs_cols(const lf2_plan_s *p, int L, int nbins)
 {
-    // 2^a * 3^b * 5^c with b + c <= 1 (one odd stage per line)
-    if (n < 1) return false;
-    int odd = 0;
-    while (n % 3 == 0) {
-        n /= 3;
-        ++odd;
-    }
-    while (n % 5 == 0) {
-        n /= 5;
-        ++odd;
-    }
-    while (n % 2 == 0) n /= 2;
-    return n == 1 && odd <= 1;
+    int b = 64;
+    while (b > 0 && gs_lds_bytes(L, b, nbins) > p->lds_max) --b;
+    return b;
+}
+
+// Rows of a run-time-schedule x tile: about 4096 complex values per tile (as
+// the compiled x tiles), fewer if the LDS does not hold them, 0 if not even
+// one row fits.
+int gx_rows(const lf2_plan_s *p, int M, int nc)
+{
+    int rb = 4096 / (M * nc);
+    rb = rb < 1 ? 1 : rb > 256 ? 256 : rb;
+    while (rb > 0 && gx_lds_bytes(M, nc, rb) > p->lds_max) --rb;
+    return rb;
 }
 
 size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
@@ -196,7 +200,7 @@ size_t spectrum_bytes(const lf2_plan_s *p)
 
 int x_grid_blocks(const lf2_plan_s *p)
 {
-    int rb = x_rows_per_block(p->len[0], p->nc);
+    const int rb = p->gen[0] ? p->gen_rb : x_rows_per_block(p->len[0], p->nc);
     return (int)((p->n[1] * p->n[2] + rb - 1) / rb);
 }
 
@@ -284,7 +288,15 @@ ModeTables base_tables(const lf2_plan_s *p)
     // below 2^32 whenever N2 > 1 (it is then at most qmax); unused for N2 = 1
     const int64_t uz = p->lcm / p->n[2];
     mt.qz_unit = (uint32_t)(uz * uz);
+    mt.k2z_unit = 0.0;
     return mt;
+}
+
+double k2z_unit(const lf2_plan_s *p, double dx, int discrete)
+{
+    if (discrete) return 0.0;
+    const double u = 6.283185307179586476925286766559 / ((double)p->n[2] * dx);
+    return u * u;
 }
 
 lf2_status get_k2(lf2_plan p, double dx, int discrete, hipStream_t s, const double *out[3],
@@ -463,6 +475,29 @@ lf2_status run_strided(const lf2_plan_s *p, int axis, int sign, const SArgs &a, 
     const double sb = (double)spectrum_bytes(p);
     const bool epi = (a.epi & (EPI_PK | EPI_PK_AFTER | EPI_POISSON)) != 0;
     const bool tr = (a.epi & (EPI_TSTORE | EPI_TLOAD)) != 0;
+    // run-time schedule: lengths without compiled kernels, and plain passes
+    // whose tuned schedule beat the compiled kernels
+    if (p->gen_only[axis] || (p->gen[axis] && !epi)) {
+        if (tr)
+            return fail(LF2_ERR_UNSUPPORTED, "no transposing pass for line length %d", p->len[axis]);
+        const bool pk = (a.epi & (EPI_PK | EPI_PK_AFTER)) != 0;
+        const int b = gs_cols(p, p->len[axis], pk ? a.mt.nbins : 0);
+        if (b < 1)
+            return fail(LF2_ERR_UNSUPPORTED, "line length %d with %d bins does not fit a tile",
+                        p->len[axis], pk ? a.mt.nbins : 0);
+        const int t = prof::begin(kname("k_gs<%d,%d> %s%s%s %lldx%lldx%lld/%d", sign, epi ? 1 : 0,
+                                        axis == 1 ? "y" : "z",
+                                        (a.epi & EPI_POISSON) ? "+poisson" : "", pk ? "+pk" : "",
+                                        (long long)p->n[0], (long long)p->n[1], (long long)p->n[2],
+                                        p->nc),
+                                  (a.epi & EPI_STORE) ? 2 * sb : sb, s);
+        hipError_t e = launch_gs(sign, a, p->sched[axis], p->len[axis], b, grid_cap, s, grid_used);
+        prof::end(t, s);
+        if (e != hipSuccess)
+            return fail(LF2_ERR_DEVICE, "strided pass (axis %d, L=%d) launch: %s", axis,
+                        p->len[axis], hipGetErrorString(e));
+        return LF2_OK;
+    }
     const int variant = (tr || epi) ? 0 : p->svar[axis];
     const int ntm = ((variant & 2) || epi) ? 1 : 0;  // the fused pass always streams
     // "<kernel symbol> <pass>": the symbol part matches the profiler's name
@@ -496,6 +531,16 @@ lf2_status run_x(const lf2_plan_s *p, int which, int sign, const XArgs &a, hipSt
     };
     const std::string shape = kname(" %lldx%lldx%lld/%d", (long long)p->n[0], (long long)p->n[1],
                                     (long long)p->n[2], p->nc);
+    if (p->gen[0]) {
+        static const char *const kModes[] = {"r2c", "c2r", "c2c"};
+        const int mode = which == 0 ? 1 : which == 1 ? 2 : 0;
+        t = prof::begin(kname("k_gx<%s>", kModes[which]) + shape, which == 2 ? 2 * sb : rb + sb, s);
+        e = launch_gx(mode, sign, a, p->sched[0], p->len[0], p->nc, p->gen_rb, s);
+        prof::end(t, s);
+        if (e != hipSuccess)
+            return fail(LF2_ERR_DEVICE, "x pass (L=%d) launch: %s", p->len[0], hipGetErrorString(e));
+        return LF2_OK;
+    }
     if (which == 0) {
         const bool v = p->nc == 1 && paired(a.in, a.in_off, a.in_row, a.in_plane);
         t = prof::begin((v ? kname("k_x_r2c_v<%d>", p->len[0]) : kname("k_x_r2c<%d,%d>", p->len[0], p->nc)) + shape,
@@ -617,17 +662,24 @@ const char *lf2_version(void) { return "lf2 0.1.0 gfx950"; }
 
 namespace {
 
-// Time the tile variants and XCD chunk sizes of the y and z passes on a
-// scratch spectrum of the plan's shape (one warm-up, then the mean of three
-// launches each) and keep the fastest, the default (narrow, 16) first.  Without memory for the scratch
-// spectrum the defaults stay.
+// Time the tile variants and XCD chunk sizes of the y and z passes, and the
+// candidate radix schedules of the run-time-schedule kernels (every axis
+// without a compiled kernel, and the y and z passes as an alternative to
+// the compiled ones), on a scratch spectrum of the plan's shape (one
+// warm-up, then the mean of three launches each), and keep the fastest, the
+// default (compiled narrow tiles, chunk 16, or the first schedule) first.
+// Without memory for the scratch spectrum the defaults stay.
 lf2_status autotune(lf2_plan p)
 {
     const size_t bytes = spectrum_bytes(p);
-    void *w = nullptr;
+    void *w = nullptr, *w2 = nullptr;
     if (hipMalloc(&w, bytes) != hipSuccess) {
         (void)hipGetLastError();
         return LF2_OK;
+    }
+    if (p->gen_only[0] && hipMalloc(&w2, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        w2 = nullptr;
     }
     hipStream_t s = nullptr;
     hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -636,34 +688,86 @@ lf2_status autotune(lf2_plan p)
         if (e != hipSuccess && st == LF2_OK) st = fail(LF2_ERR_DEVICE, "autotune %s: %s", what, hipGetErrorString(e));
         return st == LF2_OK;
     };
+    // mean microseconds of three launches after a warm-up (-1 on failure)
+    auto time_it = [&](auto &&launch) -> double {
+        hip_ok(launch(), "launch");
+        hip_ok(hipEventRecord(e0, s), "record");
+        for (int r = 0; r < 3; ++r) hip_ok(launch(), "launch");
+        hip_ok(hipEventRecord(e1, s), "record");
+        float ms = 0.f;
+        if (!hip_ok(hipEventSynchronize(e1), "sync") || !hip_ok(hipEventElapsedTime(&ms, e0, e1), "elapsed"))
+            return -1.0;
+        return 1e3 * ms / 3.0;
+    };
     static const int kChunks[] = {16, 4, 64};  // the default first
     if (hip_ok(hipStreamCreateWithFlags(&s, hipStreamNonBlocking), "stream") &&
         hip_ok(hipEventCreate(&e0), "event") && hip_ok(hipEventCreate(&e1), "event") &&
-        hip_ok(hipMemsetAsync(w, 0, bytes, s), "memset")) {
+        hip_ok(hipMemsetAsync(w, 0, bytes, s), "memset") &&
+        (!w2 || hip_ok(hipMemsetAsync(w2, 0, bytes, s), "memset"))) {
+        // x axis without a compiled kernel: its schedules, on dense rows
+        if (p->gen_only[0] && w2) {
+            XArgs a{};
+            a.nrows = p->n[1] * p->n[2];
+            a.n1 = (int)p->n[1];
+            a.tw = p->tw[0];
+            a.tw_post = p->tw_post;
+            const int64_t c1 = p->nxk * p->nc;
+            const int64_t xr = p->n[0] * p->nc;  // floats (r2c) or complex (c2c) per row
+            a.in = w;
+            a.out = w2;
+            a.in_row = xr;
+            a.in_plane = xr * p->n[1];
+            a.out_row = c1;
+            a.out_plane = c1 * p->n[1];
+            const int mode = p->kind == LF2_R2C ? 1 : 0;
+            double best = -1.0;
+            for (const GSched &sc : sched_candidates(p->len[0])) {
+                if (st != LF2_OK) break;
+                const double us = time_it([&] {
+                    return launch_gx(mode, -1, a, sc, p->len[0], p->nc, p->gen_rb, s);
+                });
+                if (p->tune_us[0][0] < 0) p->tune_us[0][0] = us;
+                if (us >= 0 && (best < 0 || us < 0.97 * best)) {
+                    best = us;
+                    p->sched[0] = sc;
+                }
+            }
+            p->tune_us[0][1] = best;
+        }
         for (int axis = 1; axis <= 2 && st == LF2_OK; ++axis) {
-            const bool wide = s_wide_supported(p->len[axis]);
+            const bool wide = !p->gen_only[axis] && s_wide_supported(p->len[axis]);
             const SArgs a = s_args(p, axis, w, w, EPI_STORE);
             double best = -1.0;
-            for (int v = 0; v < 4 && st == LF2_OK; ++v) {
-                if ((v & 1) && !wide) continue;
-                for (int c : kChunks) {
-                    hip_ok(launch_strided(p->len[axis], -1, a, kStridedGridCap, s, nullptr, v, c), "launch");
-                    hip_ok(hipEventRecord(e0, s), "record");
-                    for (int r = 0; r < 3; ++r)
-                        hip_ok(launch_strided(p->len[axis], -1, a, kStridedGridCap, s, nullptr, v, c), "launch");
-                    hip_ok(hipEventRecord(e1, s), "record");
-                    float ms = 0.f;
-                    if (!hip_ok(hipEventSynchronize(e1), "sync") || !hip_ok(hipEventElapsedTime(&ms, e0, e1), "elapsed"))
-                        break;
-                    const double us = 1e3 * ms / 3.0;
-                    if (v == 0 && c == 16) p->tune_us[axis][0] = us;
-                    // another setting must beat the current choice by 3 %, so
-                    // that timing noise does not flip the choice from run to run
-                    if (best < 0 || us < 0.97 * best) {
-                        best = us;
-                        p->svar[axis] = v;
-                        p->schunk[axis] = c;
+            if (!p->gen_only[axis]) {
+                for (int v = 0; v < 4 && st == LF2_OK; ++v) {
+                    if ((v & 1) && !wide) continue;
+                    for (int c : kChunks) {
+                        const double us = time_it([&] {
+                            return launch_strided(p->len[axis], -1, a, kStridedGridCap, s, nullptr, v, c);
+                        });
+                        if (us < 0) break;
+                        if (v == 0 && c == 16) p->tune_us[axis][0] = us;
+                        // another setting must beat the current choice by 3 %, so
+                        // that timing noise does not flip the choice from run to run
+                        if (best < 0 || us < 0.97 * best) {
+                            best = us;
+                            p->svar[axis] = v;
+                            p->schunk[axis] = c;
+                        }
                     }
+                }
+            }
+            const int b = gs_cols(p, p->len[axis], 0);
+            for (const GSched &sc : sched_candidates(p->len[axis])) {
+                if (st != LF2_OK || b < 1) break;
+                const double us = time_it([&] {
+                    return launch_gs(-1, a, sc, p->len[axis], b, kStridedGridCap, s, nullptr);
+                });
+                if (p->tune_us[axis][0] < 0) p->tune_us[axis][0] = us;
+                if (us >= 0 && (best < 0 || us < 0.97 * best)) {
+                    best = us;
+                    p->gen[axis] = true;
+                    p->sched[axis] = sc;
                 }
             }
             p->tune_us[axis][1] = best;
@@ -674,6 +778,7 @@ lf2_status autotune(lf2_plan p)
     if (e1) (void)hipEventDestroy(e1);
     if (s) (void)hipStreamDestroy(s);
     (void)hipFree(w);
+    if (w2) (void)hipFree(w2);
     return st;
 }
 
@@ -698,19 +803,23 @@ lf2_status lf2_fft_plan(lf2_plan *out, const lf2_lattice *lat, int32_t ncomp, lf
     for (int i = 0; i < 3; ++i) {
         if (lat->size[i] < 1) return fail(LF2_ERR_INVALID_ARG, "size[%d] = %lld < 1", i, (long long)lat->size[i]);
         if (lat->size[i] > (1 << 20)) return fail(LF2_ERR_UNSUPPORTED, "size[%d] too large", i);
-        if (!radix_ok(lat->size[i]))
-            return fail(LF2_ERR_UNSUPPORTED,
-                        "size[%d] = %lld must be 2^a, 3*2^a or 5*2^a", i, (long long)lat->size[i]);
+        if (!gen_factorable(lat->size[i]))
+            return fail(LF2_ERR_UNSUPPORTED, "size[%d] = %lld must be 2^a 3^b 5^c", i,
+                        (long long)lat->size[i]);
     }
     if (kind == LF2_R2C && lat->size[0] % 2)
         return fail(LF2_ERR_UNSUPPORTED, "r2c needs an even size[0] (got %lld)", (long long)lat->size[0]);
     int lens[3] = {(int)(kind == LF2_R2C ? lat->size[0] / 2 : lat->size[0]), (int)lat->size[1],
                    (int)lat->size[2]};
-    if (!x_supported(lens[0], ncomp))
-        return fail(LF2_ERR_UNSUPPORTED, "no x-pass kernel for line length %d with %d components", lens[0], ncomp);
-    for (int i = 1; i < 3; ++i)
-        if (!s_supported(lens[i]))
-            return fail(LF2_ERR_UNSUPPORTED, "no strided kernel for line length %d", lens[i]);
+    bool gen_only[3];
+    for (int i = 0; i < 3; ++i) {
+        gen_only[i] = i == 0 ? !x_supported(lens[0], ncomp) : !s_supported(lens[i]);
+        if (gen_only[i] && lens[i] > kGenMaxLen)
+            return fail(LF2_ERR_UNSUPPORTED, "line length %d along dimension %d is longer than %d",
+                        lens[i], i, kGenMaxLen);
+    }
+    if (gen_only[2] && (flags & LF2_KLAYOUT_PAPER) && kind == LF2_C2C)
+        return fail(LF2_ERR_UNSUPPORTED, "the c2c paper k-space order needs a compiled z length");
 
     lf2_plan p = new (std::nothrow) lf2_plan_s();
     if (!p) return fail(LF2_ERR_OUT_OF_MEMORY, "plan allocation");
@@ -719,6 +828,29 @@ lf2_status lf2_fft_plan(lf2_plan *out, const lf2_lattice *lat, int32_t ncomp, lf
         delete p;
         return fail(LF2_ERR_DEVICE, "hipGetDevice: %s", hipGetErrorString(e));
     }
+    int lds = 0;
+    if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, p->device) ==
+            hipSuccess &&
+        lds > 0)
+        p->lds_max = (size_t)lds;
+    // compiled kernels where they exist; run-time radix schedules otherwise
+    for (int i = 0; i < 3; ++i) {
+        p->gen_only[i] = gen_only[i];
+        p->gen[i] = gen_only[i];
+        const std::vector<GSched> cand = sched_candidates(lens[i]);
+        if (!cand.empty()) p->sched[i] = cand[0];
+    }
+    if (p->gen_only[0] && (p->gen_rb = gx_rows(p, lens[0], ncomp)) < 1) {
+        delete p;
+        return fail(LF2_ERR_UNSUPPORTED, "x lines of %d points with %d components do not fit a tile",
+                    lens[0], ncomp);
+    }
+    for (int i = 1; i < 3; ++i)
+        if (p->gen_only[i] && gs_cols(p, lens[i], 0) < 1) {
+            delete p;
+            return fail(LF2_ERR_UNSUPPORTED, "strided lines of %d points do not fit a tile", lens[i]);
+        }
+
     p->kind = kind;
     p->nc = ncomp;
     p->halo = lat->halo;
@@ -782,10 +914,54 @@ lf2_status lf2_plan_get_tuning(lf2_plan p, int32_t axis, int32_t *variant, int32
 {
     if (!p) return fail(LF2_ERR_INVALID_ARG, "plan is NULL");
     if (axis != 1 && axis != 2) return fail(LF2_ERR_INVALID_ARG, "axis %d is not 1 or 2", axis);
-    if (variant) *variant = p->svar[axis];
+    if (variant) *variant = p->gen[axis] ? -1 : p->svar[axis];
     if (chunk) *chunk = p->schunk[axis];
     if (us_default) *us_default = p->tune_us[axis][0];
     if (us_tuned) *us_tuned = p->tune_us[axis][1];
+    return LF2_OK;
+}
+
+lf2_status lf2_plan_get_schedule(lf2_plan p, int32_t axis, int32_t radices[15], int32_t *nst,
+                                 int32_t *runtime)
+{
+    if (!p) return fail(LF2_ERR_INVALID_ARG, "plan is NULL");
+    if (axis < 0 || axis > 2) return fail(LF2_ERR_INVALID_ARG, "axis %d is not 0, 1 or 2", axis);
+    int n = 0;
+    int r[kGenMaxStages] = {};
+    if (p->gen[axis]) {
+        n = p->sched[axis].n;
+        for (int i = 0; i < n; ++i) r[i] = p->sched[axis].r[i];
+    } else {
+        // the compiled kernels' schedule (lf2_device.hpp)
+        n = lf2::nstages(p->len[axis]);
+        for (int i = 0; i < n && i < kGenMaxStages; ++i) r[i] = lf2::radix_at(p->len[axis], i);
+    }
+    if (nst) *nst = n;
+    if (runtime) *runtime = p->gen[axis] ? 1 : 0;
+    if (radices)
+        for (int i = 0; i < kGenMaxStages; ++i) radices[i] = i < n ? r[i] : 0;
+    return LF2_OK;
+}
+
+lf2_status lf2_plan_set_schedule(lf2_plan p, int32_t axis, const int32_t *radices, int32_t nstages)
+{
+    if (!p) return fail(LF2_ERR_INVALID_ARG, "plan is NULL");
+    if (axis < 0 || axis > 2) return fail(LF2_ERR_INVALID_ARG, "axis %d is not 0, 1 or 2", axis);
+    if (nstages < 0 || nstages > kGenMaxStages || (nstages > 0 && !radices))
+        return fail(LF2_ERR_INVALID_ARG, "bad schedule (%d stages)", nstages);
+    GSched sc{};
+    sc.n = nstages;
+    for (int i = 0; i < nstages; ++i) sc.r[i] = radices[i];
+    if (!sched_valid(sc, p->len[axis]))
+        return fail(LF2_ERR_INVALID_ARG,
+                    "radices must each be 2, 3, 4, 5, 8 or 16 with product %d", p->len[axis]);
+    if (axis == 0 && !p->gen_only[0])
+        return fail(LF2_ERR_UNSUPPORTED, "the x pass of length %d runs compiled kernels only",
+                    p->len[0]);
+    if (axis > 0 && gs_cols(p, p->len[axis], 0) < 1)
+        return fail(LF2_ERR_UNSUPPORTED, "line length %d does not fit a tile", p->len[axis]);
+    p->sched[axis] = sc;
+    p->gen[axis] = true;
     return LF2_OK;
 }
 
@@ -795,10 +971,13 @@ lf2_status lf2_plan_set_tuning(lf2_plan p, int32_t axis, int32_t variant, int32_
     if (axis != 1 && axis != 2) return fail(LF2_ERR_INVALID_ARG, "axis %d is not 1 or 2", axis);
     if (variant < 0 || variant > 3) return fail(LF2_ERR_INVALID_ARG, "variant %d outside [0, 3]", variant);
     if (chunk < 1 || chunk > 1024) return fail(LF2_ERR_INVALID_ARG, "chunk %d outside [1, 1024]", chunk);
+    if (p->gen_only[axis])
+        return fail(LF2_ERR_UNSUPPORTED, "no compiled kernels for line length %d", p->len[axis]);
     if ((variant & 1) && !s_wide_supported(p->len[axis]))
         return fail(LF2_ERR_UNSUPPORTED, "no wide tiles for line length %d", p->len[axis]);
     p->svar[axis] = variant;
     p->schunk[axis] = chunk;
+    p->gen[axis] = false;  // the compiled kernels again
     return LF2_OK;
 }
 
@@ -938,7 +1117,7 @@ size_t poisson_ws_bytes(const lf2_plan_s *p, int32_t nbins, bool parseval)
 lf2_status poisson_impl(lf2_plan p, const float *rho, float *phi, double dx, uint32_t flags,
                         int32_t nbins, double *d_pk, double *d_kmean, double *d_count,
                         double *d_parseval, hipStream_t stream, char *ws_given,
-                        size_t ws_given_bytes, bool noalloc)
+                        size_t ws_given_bytes, bool noalloc, const PoissonTables *tabs)
 {
     if (!p) return fail(LF2_ERR_INVALID_ARG, "plan is NULL");
     if (p->kind != LF2_R2C || p->nc != 1)
@@ -971,9 +1150,15 @@ lf2_status poisson_impl(lf2_plan p, const float *rho, float *phi, double dx, uin
     }
     void *W = ws + L.w;
     const double *k2[3];
-    if ((st = get_k2(p, dx, (flags & LF2_POISSON_DISCRETE_K2) ? 1 : 0, s, k2, noalloc))) return st;
     ShellEntry sh{};
-    if (nb > 0 && (st = get_shell(p, nb, s, &sh, noalloc))) return st;
+    if (tabs) {
+        for (int i = 0; i < 3; ++i) k2[i] = tabs->k2[i];
+        sh = tabs->sh;
+        if (nb > 0 && sh.nbins != nb) return fail(LF2_ERR_INVALID_ARG, "shell table of another bin count");
+    } else {
+        if ((st = get_k2(p, dx, (flags & LF2_POISSON_DISCRETE_K2) ? 1 : 0, s, k2, noalloc))) return st;
+        if (nb > 0 && (st = get_shell(p, nb, s, &sh, noalloc))) return st;
+    }
 
     XArgs xa = x_args(p, rho, W, true, false, true);
     if (parseval) xa.sumsq = (double *)(ws + L.sq);
@@ -983,6 +1168,7 @@ lf2_status poisson_impl(lf2_plan p, const float *rho, float *phi, double dx, uin
     if (nb > 0) epi |= (flags & LF2_PK_OF_PHI) ? EPI_PK_AFTER : EPI_PK;
     SArgs za = s_args(p, 2, W, W, epi);
     for (int i = 0; i < 3; ++i) za.mt.k2[i] = k2[i];
+    za.mt.k2z_unit = k2z_unit(p, dx, (flags & LF2_POISSON_DISCRETE_K2) ? 1 : 0);
     int grid = 0;
     if (nb > 0) {
         za.mt.thresh = sh.thresh;

@@ -4,6 +4,9 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "lf2_batch_items.hpp"
+#include "lf2_gen.hpp"
+
 namespace lf2 {
 
 constexpr int kMaxBins = 4096;  // LDS histogram limit of the fused binning epilogue
@@ -30,6 +33,8 @@ struct ModeTables {
     double qmax;
     double scale_n;        // Poisson: factor 1/N applied with -1/k^2
     uint32_t qz_unit;      // (lcm / N2)^2: q[2][i] = qz_unit * min(i, N2 - i)^2
+    double k2z_unit;       // continuous k^2: (2 pi / (N2 dx))^2, so k2[2][i] =
+                           // k2z_unit * min(i, N2 - i)^2; 0: read k2[2]
 };
 
 struct XArgs {
@@ -56,6 +61,8 @@ struct SArgs {
     int64_t ncols;       // total columns (O * C)
     int epi;             // EPI_* flags
     int xcd_chunk;       // tiles per XCD chunk (set by the launcher)
+    int hcopies;         // binning: LDS histograms per block, 1 (all waves add into
+                         // one) or one per wave (fixed-order sums: reproducible)
     const void *tw;      // twiddles, length L
     ModeTables mt;
     double *partial;     // [gridDim.x][nbins + 1]
@@ -80,6 +87,21 @@ hipError_t launch_x_c2c(int len, int nc, int sign, const XArgs &a, hipStream_t s
 hipError_t launch_strided(int len, int sign, const SArgs &a, int grid_cap, hipStream_t s,
                           int *grid_used, int variant = 0, int chunk = 16);
 bool s_wide_supported(int len);
+// LDS histogram copies of a fused last-axis tile of length len binning into
+// nbins bins, when the block's LDS is `budget` bytes: one per wave if they
+// fit with the tile, else one.  0 if len has no compiled fused tile.
+int epi_hist_copies(int len, int nbins, size_t budget);
+
+// Run-time-schedule kernels (lf2_kgen.hip): LDS bytes of an x tile of RB
+// rows and of a strided tile of B columns (nbins > 0: with the binning
+// tables), and their launchers.  mode 0: c2c with `sign`, 1: r2c forward,
+// 2: c2r backward.
+size_t gx_lds_bytes(int M, int NC, int RB);
+size_t gs_lds_bytes(int L, int B, int nbins);
+hipError_t launch_gx(int mode, int sign, const XArgs &a, const GSched &sc, int m, int nc, int rb,
+                     hipStream_t s);
+hipError_t launch_gs(int sign, const SArgs &a, const GSched &sc, int len, int b, int grid_cap,
+                     hipStream_t s, int *grid_used);
 
 // Field operations (lf2_kfield.hip).
 hipError_t launch_update_halo(void *field, const int64_t n[3], int64_t h, int64_t site_words,
@@ -113,16 +135,7 @@ int x_rows_per_block(int len, int nc);
 int s_cols_per_block(int len);
 
 // ---------------------------------------------------------------- batches
-// Passes of one field in a batched Poisson solve.
-enum : int {
-    BP_XF = 0,   // x r2c: rho -> W
-    BP_YF = 1,   // y forward on W
-    BP_Z = 2,    // z forward * -1/(N k^2) (+ binning) * z backward on W
-    BP_YI = 3,   // y backward on W
-    BP_XI = 4,   // x c2r: W -> phi
-    BP_FIN = 5,  // power-spectrum finalize (one item)
-    BP_COUNT = 6
-};
+// Passes BP_* of a batched solve and the work-item order: lf2_batch_items.hpp.
 
 struct BatchField {
     XArgs xf, xi;
@@ -144,9 +157,25 @@ struct BatchItem {
 constexpr int kBatchMaxBins = 511;
 bool batch_len_supported(int len);
 int batch_x_rows(int m);
+// Persistent batch kernel: x tiles of batch_px_rows(m) rows; one launch of
+// `grid` blocks runs every item of the nq queues of `items` (ordered and
+// laid out as batch_items makes them; qstart / qcount and ctl have nq + 1
+// entries, the last queue empty).  local = 1: a block serves queue
+// xq[XCC id] (16 entries); 0: every block serves queue 0.
+int batch_px_rows(int m);
+size_t batch_persistent_lds();  // LDS bytes of a persistent block
+hipError_t batch_persistent_launch(const BatchField *fields, const QItem *items,
+                                   const uint32_t *qstart, const uint32_t *qcount, int nq,
+                                   const int32_t *xq, QCtl *ctl, uint32_t *done, int ndone,
+                                   uint32_t spin_limit, int local, int grid, hipStream_t s);
+// XCC (XCD) id of each of n blocks, into out[n].
+hipError_t launch_xcc_probe(int32_t *out, int n, hipStream_t s);
 // One grouped launch: items of pass `pass` whose line length is `len`.
+// k2cont: 1 for the continuous k^2 (computed from |n_z| in the z pass), 0
+// for the discrete one (its table).
 hipError_t batch_group_launch(int pass, int len, const BatchField *fields,
-                              const BatchItem *items, int nitems, int nbins, hipStream_t s);
+                              const BatchItem *items, int nitems, int nbins, int k2cont,
+                              hipStream_t s);
 hipError_t batch_finalize_launch(const BatchField *fields, int nfields, hipStream_t s);
 
 }  // namespace lf2

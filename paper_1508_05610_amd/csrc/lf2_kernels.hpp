@@ -684,6 +684,34 @@ __device__ __forceinline__ void load_edges(const ModeTables &mt, double *hist, B
     }
 }
 
+// The same for `copies` histograms of nbins + 1 entries, one after another
+// (one per wave of the block, or one for all).
+__device__ __forceinline__ void hist_init(const ModeTables &mt, int copies, double *hist,
+                                          BinEdge *edges, int tid, int nt)
+{
+    load_edges(mt, hist, edges, tid, nt);
+    for (int i = mt.nbins + 1 + tid; i < copies * (mt.nbins + 1); i += nt) hist[i] = 0.0;
+}
+
+// out[i] = sum of the copies' entry i, copy 0 first (a fixed order: the
+// block's binned sums do not depend on how its waves were scheduled); the
+// copies are zeroed for the next tile.  Callers wait at a barrier before
+// the histograms are used again.
+__device__ __forceinline__ void hist_flush(int nbins, int copies, double *hist, double *out,
+                                           int tid, int nt)
+{
+    const int w = nbins + 1;
+    for (int i = tid; i < w; i += nt) {
+        double s = hist[i];
+        hist[i] = 0.0;
+        for (int c = 1; c < copies; ++c) {
+            s += hist[c * w + i];
+            hist[c * w + i] = 0.0;
+        }
+        out[i] = s;
+    }
+}
+
 // 1/d for d > 0 in FP64: the hardware reciprocal refined by one Newton step,
 // which squares the estimate's relative error; the scale it feeds multiplies
 // FP32 modes in FP64 and is rounded to FP32 with the product.
@@ -708,25 +736,20 @@ __device__ __forceinline__ int opaque_tid(int tid)
 // ============================================================ strided tiles
 // EPI = false: plain pass (no epilogue code, fewest registers);
 // EPI = true : last-axis pass with the binning / Poisson epilogue.
-// hist / edges: LDS arrays of nbins + 1 entries (EPI with binning only);
-// the tile adds its w|F|^2 sums into hist.
-template <int L, int S, bool EPI, int NT, bool NTM = false>
+// hist / edges: LDS arrays (EPI with binning only): a.hcopies histograms of
+// nbins + 1 entries (wave w adds into copy w, or all into copy 0) and the
+// edge table; the tile adds its w|F|^2 sums into them.
+// K2 (EPI): 1 the continuous k^2 of the last axis from |n_z|, 2 its table,
+// 0 either, chosen per call (fewer kernels, more registers).
+template <int L, int S, bool EPI, int NT, bool NTM = false, int K2 = 0>
 struct STile {
     static constexpr int B = s_b(L);
     static constexpr int RPT = NT / B;  // row groups in the epilogue
-    // EPI tiles also keep the last axis' k^2 table in LDS (read once per
-    // mode in the epilogue)
     static constexpr size_t O_BUF = 0, O_TW = al16(sizeof(c32) * L * B),
-                            O_K2Z = al16(O_TW + sizeof(c32) * L),
-                            BYTES = al16(O_K2Z + (EPI ? 8 * L : 0));
+                            BYTES = al16(O_TW + sizeof(c32) * L);
     static __device__ void tables(const SArgs &a, char *sm, int tid)
     {
         load_table((c32 *)(sm + O_TW), a.tw, L, tid, NT);
-        if constexpr (EPI) {
-            double *k2z = (double *)(sm + O_K2Z);
-            if (a.epi & EPI_POISSON)
-                for (int i = tid; i < L; i += NT) k2z[i] = a.mt.k2[2][i];
-        }
     }
     static __device__ void tile(const SArgs &a, int64_t t, char *sm, int tid, double *hist,
                                 const BinEdge *edges)
@@ -786,32 +809,22 @@ struct STile {
         const int kx = valid ? (int)(f % a.mt.nxk) : 0;
         const int ky = valid ? (int)(f / a.mt.nxk) : 0;
         const bool corner = kx == 0 && ky == 0;
+        // this wave's histogram
+        double *wh = hist + (a.hcopies > 1 ? (tid >> 6) * (a.mt.nbins + 1) : 0);
         if (a.epi & EPI_PK) {
             col_stage_out<L, RL, QL, B, NT, false>(buf, nullptr, 0, false, tid, v);
-            bin_walk(a, buf, col, rg, kx, ky, valid, hist, edges);
+            bin_walk(a, buf, col, rg, kx, ky, valid, wh, edges);
         }
         if (a.epi & EPI_POISSON) {
             const double k2xy = valid ? a.mt.k2[0][kx] + a.mt.k2[1][ky] : 1.0;
-            const double *k2z = (const double *)(sm + O_K2Z);
-#pragma unroll
-            for (int i = 0; i < NB; ++i) {
-                const int j = j0 + i * JS;
-#pragma unroll
-                for (int r = 0; r < RL; ++r) {
-                    const int kz = j + r * QL;
-                    if (QL % JS == 0 || j < QL) {
-                        const double sc = (corner && kz == 0)
-                                              ? 0.0
-                                              : -a.mt.scale_n * rcp_f64(k2xy + k2z[kz]);
-                        v[i][r] = c32{(float)((double)v[i][r].x * sc),
-                                      (float)((double)v[i][r].y * sc)};
-                    }
-                }
-            }
+            if (K2 == 1 || (K2 == 0 && a.mt.k2z_unit > 0.0))
+                scale_modes<true>(a, v, j0, k2xy, corner);   // continuous k^2 from |n_z|
+            else
+                scale_modes<false>(a, v, j0, k2xy, corner);  // the last axis' k^2 table
         }
         if (a.epi & EPI_PK_AFTER) {
             col_stage_out<L, RL, QL, B, NT, false>(buf, nullptr, 0, false, tid, v);
-            bin_walk(a, buf, col, rg, kx, ky, valid, hist, edges);
+            bin_walk(a, buf, col, rg, kx, ky, valid, wh, edges);
         }
         if constexpr (S < 0) {
             if (a.epi & EPI_POISSON) {
@@ -834,10 +847,37 @@ struct STile {
             col_stage_out<L, RL, QL, B, NT, true, NTM>(buf, gout, a.stride, valid, tid, v);
     }
 
+    // The Poisson scale -1/(N k^2) (FP64, rounded once with the product) of
+    // the modes kz = j + r QL a thread holds after the forward transform.
+    template <bool CONT, int RL, int NB>
+    static __device__ __forceinline__ void scale_modes(const SArgs &a, c32 (&v)[NB][RL], int j0,
+                                                       double k2xy, bool corner)
+    {
+        constexpr int QL = L / RL;
+        constexpr int JS = NT / B;
+#pragma unroll
+        for (int i = 0; i < NB; ++i) {
+            const int j = j0 + i * JS;
+#pragma unroll
+            for (int r = 0; r < RL; ++r) {
+                const int kz = j + r * QL;
+                if (QL % JS == 0 || j < QL) {
+                    const int m = 2 * kz < L ? kz : L - kz;
+                    const double k2z = CONT ? a.mt.k2z_unit * (double)(m * m) : a.mt.k2[2][kz];
+                    const double sc =
+                        (corner && kz == 0) ? 0.0 : -a.mt.scale_n * rcp_f64(k2xy + k2z);
+                    v[i][r] = c32{(float)((double)v[i][r].x * sc), (float)((double)v[i][r].y * sc)};
+                }
+            }
+        }
+    }
+
     // P(k) partial sums of the modes in LDS (natural order): thread (col, rg)
     // walks its run of kz, computes each mode's exact bin and adds w |F|^2
-    // into the block's LDS histogram when the bin changes.  Ends at a
-    // barrier, so LDS may be rewritten afterwards.
+    // into `hist` -- its wave's own LDS histogram, or the block's one --
+    // when the bin changes.  A wave's additions come in program order, so
+    // with one histogram per wave the sums do not depend on scheduling.
+    // Ends at a barrier, so LDS may be rewritten afterwards.
     static __device__ void bin_walk(const SArgs &a, const c32 *buf, int col, int rg, int kx,
                                     int ky, bool valid, double *hist, const BinEdge *edges)
     {
@@ -1040,22 +1080,22 @@ __global__ __launch_bounds__(kXThreads) void k_x_c2c_v(XArgs a)
 // Occupancy target: four waves per SIMD (two blocks per CU) except where the
 // fused pass's LDS tables leave room for one block (lines of 1024 points and
 // more), where two waves per SIMD are all it can reach.
-template <int L, int S, bool EPI, bool NTM = false>
+template <int L, int S, bool EPI, bool NTM = false, int K2 = 0>
 __global__ __launch_bounds__(kSThreads)
     __attribute__((amdgpu_waves_per_eu(EPI && L >= 1024 ? 2 : 4))) void k_strided(SArgs a)
 {
-    using T = STile<L, S, EPI, kSThreads, NTM>;
+    using T = STile<L, S, EPI, kSThreads, NTM, K2>;
     constexpr int NT = kSThreads;
     constexpr int B = T::B;
     __shared__ __align__(16) char sm[T::BYTES];
-    extern __shared__ double dyn[];  // hist[nbins + 1], edges[nbins + 1]
+    extern __shared__ double dyn[];  // hist[hcopies][nbins + 1], edges[nbins + 1]
     const int tid = threadIdx.x;
     T::tables(a, sm, tid);
     const bool pk = EPI && (a.epi & (EPI_PK | EPI_PK_AFTER)) != 0;
     const int nb = a.mt.nbins;
     double *hist = dyn;
-    BinEdge *edges = (BinEdge *)(dyn + (nb + 1));
-    if (pk) load_edges(a.mt, hist, edges, tid, NT);
+    BinEdge *edges = (BinEdge *)(dyn + a.hcopies * (nb + 1));
+    if (pk) hist_init(a.mt, a.hcopies, hist, edges, tid, NT);
     __syncthreads();
     const int64_t ntiles = (a.ncols + B - 1) / B;
     // XCD-aware walk over virtual block ids vb = blockIdx.x + i * G (G is a
@@ -1074,7 +1114,7 @@ __global__ __launch_bounds__(kSThreads)
     }
     if (pk) {
         __syncthreads();
-        for (int i = tid; i <= nb; i += NT) a.partial[(int64_t)blockIdx.x * (nb + 1) + i] = hist[i];
+        hist_flush(nb, a.hcopies, hist, a.partial + (int64_t)blockIdx.x * (nb + 1), tid, NT);
     }
 }
 

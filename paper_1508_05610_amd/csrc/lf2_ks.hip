@@ -18,6 +18,22 @@ bool s_supported(int len)
 
 int s_cols_per_block(int len) { return s_b(len); }
 
+int epi_hist_copies(int len, int nbins, size_t budget)
+{
+    constexpr int kWaves = kSThreads / 64;
+    switch (len) {
+#define LF2_CASE(L)                                                                          \
+    case L: {                                                                                \
+        const size_t tile = STile<L, -1, true, kSThreads, true>::BYTES;                      \
+        return tile + (size_t)(nbins + 1) * 8 * (kWaves + 1) <= budget ? kWaves : 1;         \
+    }
+        LF2_S_LENGTHS(LF2_CASE)
+#undef LF2_CASE
+    default:
+        return 0;
+    }
+}
+
 // Lengths with a wide (split-exchange) tile: the long lines, whose narrow
 // tiles read the shortest row segments.
 #define LF2_WIDE_LENGTHS(X) X(256) X(320) X(384) X(512) X(640) X(768) X(1024) X(2048)
@@ -109,7 +125,11 @@ hipError_t launch_strided(int len, int sign, const SArgs &a_in, int grid_cap, hi
     if (grid_cap < 8) grid_cap = 8;
     const bool pk = (a.epi & (EPI_PK | EPI_PK_AFTER)) != 0;
     const bool epi = (a.epi & (EPI_PK | EPI_PK_AFTER | EPI_POISSON)) != 0;
-    const size_t shm = pk ? (size_t)(a.mt.nbins + 1) * 16 : 0;
+    // one histogram per wave where the LDS allows (two blocks per CU, one
+    // for lines of 1024 points and more)
+    a.hcopies = pk ? epi_hist_copies(len, a.mt.nbins, len >= 1024 ? 160 * 1024 : 80 * 1024) : 1;
+    if (a.hcopies < 1) a.hcopies = 1;
+    const size_t shm = pk ? (size_t)(a.mt.nbins + 1) * 8 * (a.hcopies + 1) : 0;
     if (a.epi & (EPI_TSTORE | EPI_TLOAD)) {
         if (epi) return hipErrorInvalidValue;
         return launch_transposed(len, sign, a, grid_cap, s, grid_used);
@@ -126,8 +146,12 @@ hipError_t launch_strided(int len, int sign, const SArgs &a_in, int grid_cap, hi
         int64_t span = (ntiles + 8 * kChunk - 1) / (8 * kChunk) * (8 * kChunk);              \
         int g = (int)(span < grid_cap ? span : grid_cap);                                    \
         if (grid_used) *grid_used = g;                                                       \
-        if (epi && sign < 0)                                                                 \
-            hipLaunchKernelGGL((k_strided<L, -1, true, true>), dim3(g), dim3(kSThreads), shm, s, a);\
+        if (epi && sign < 0 && a.mt.k2z_unit > 0.0)                                          \
+            hipLaunchKernelGGL((k_strided<L, -1, true, true, 1>), dim3(g), dim3(kSThreads), shm, \
+                               s, a);                                                        \
+        else if (epi && sign < 0)                                                            \
+            hipLaunchKernelGGL((k_strided<L, -1, true, true, 2>), dim3(g), dim3(kSThreads), shm, \
+                               s, a);                                                        \
         else if (epi)                                                                        \
             return hipErrorInvalidValue;                                                     \
         else if (ntm)                                                                        \

@@ -38,6 +38,14 @@ struct lf2_plan_s {
     int svar[3] = {0, 0, 0};              // strided tile variant per axis (1, 2)
     int schunk[3] = {16, 16, 16};         // tiles per XCD chunk per axis
     double tune_us[3][2] = {{-1, -1}, {-1, -1}, {-1, -1}};  // [axis][default, tuned]
+    // run-time-schedule kernels: gen_only = no compiled kernel for the axis'
+    // length; gen = the plain passes of the axis use them (gen_only, or the
+    // tuner found a schedule faster than the compiled kernels)
+    bool gen_only[3] = {false, false, false};
+    bool gen[3] = {false, false, false};
+    lf2::GSched sched[3] = {};
+    int gen_rb = 1;          // x tile rows of the run-time x kernels
+    size_t lds_max = 65536;  // LDS bytes a block may use on the plan's device
     void *tw[3] = {nullptr, nullptr, nullptr};
     void *tw_post = nullptr;
     int64_t *q[3] = {nullptr, nullptr, nullptr};
@@ -77,6 +85,9 @@ void end(int idx, hipStream_t s);
 lf2_status plan_alloc(lf2_plan p, void **dst, size_t bytes);
 size_t spectrum_bytes(const lf2_plan_s *p);
 ModeTables base_tables(const lf2_plan_s *p);
+// (2 pi / (N2 dx))^2 for the continuous k^2 (the fused pass then computes
+// the last axis' k^2 from |n_z|), 0 for the discrete one.
+double k2z_unit(const lf2_plan_s *p, double dx, int discrete);
 // Tables of a plan, built on first use (lookup_only: never build; a
 // missing table is LF2_ERR_NOT_READY).
 lf2_status get_k2(lf2_plan p, double dx, int discrete, hipStream_t s, const double *out[3],
@@ -91,12 +102,38 @@ SArgs s_args(const lf2_plan_s *p, int axis, const void *in, void *out, int epi);
 lf2_status check_bins(const lf2_plan_s *p, int32_t nbins);
 
 size_t poisson_ws_bytes(const lf2_plan_s *p, int32_t nbins, bool parseval);
+// The plan tables a Poisson solve reads (k^2 of its dx and kind, shell
+// table of its bin count).
+struct PoissonTables {
+    const double *k2[3];
+    ShellEntry sh;
+};
 // noalloc: use only tables that already exist (LF2_ERR_NOT_READY otherwise)
-// and make no allocation; ws_given must then be given.
+// and make no allocation; ws_given must then be given.  tabs (nullable):
+// tables the caller already looked up, so the plan's table lists are not
+// read (callers that share plans across threads look them up under a lock).
 lf2_status poisson_impl(lf2_plan p, const float *rho, float *phi, double dx, uint32_t flags,
                         int32_t nbins, double *d_pk, double *d_kmean, double *d_count,
                         double *d_parseval, hipStream_t stream, char *ws_given,
-                        size_t ws_given_bytes, bool noalloc = false);
+                        size_t ws_given_bytes, bool noalloc = false,
+                        const PoissonTables *tabs = nullptr);
+
+// Grouped Poisson solves of one lattice (lf2_batch.cpp): R requests with
+// the same plan, dx, k^2 kind and bin count as one launch per pass.
+struct GroupReq {
+    const float *rho;
+    float *phi;
+    double *pk, *kmean, *count;  // nullable
+    void *ws;                    // group_ws_bytes of workspace
+};
+bool group_supported(const lf2_plan_s *p);
+size_t group_ws_bytes(const lf2_plan_s *p, int32_t nbins);
+size_t group_stage_bytes(const lf2_plan_s *p, int R);
+// stage_host (pinned) and stage_dev: group_stage_bytes each; both must stay
+// untouched until the stream has passed the group's launches.
+lf2_status group_enqueue(lf2_plan p, int R, const GroupReq *req, double dx, uint32_t flags,
+                         int32_t nbins, const PoissonTables &tabs, void *stage_host,
+                         void *stage_dev, size_t stage_bytes, hipStream_t s);
 
 }  // namespace host
 }  // namespace lf2

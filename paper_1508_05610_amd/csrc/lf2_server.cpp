@@ -2,10 +2,14 @@
 // power spectra on lattices of mixed sizes.
 //
 // submit() appends to a bounded FIFO.  The scheduler thread admits requests
-// from the head while the in-flight footprint stays within the HBM budget
-// and a slot is free, and launches each admitted request immediately on the
-// next of K streams (its own pooled workspace, a resident plan), recording
-// an event after its kernels.  The completion thread polls the in-flight
+// from the head while the in-flight footprint plus the idle pooled
+// workspace stays within the HBM budget and a slot is free (idle workspace
+// is freed to make room when needed).  Requests admitted together that
+// share a lattice, lattice spacing, k^2 kind and bin count run as one
+// grouped solve -- one launch per pass over all of them plus one finalize
+// -- and the others one by one; each unit goes on the next of K streams
+// with its own pooled workspaces and a resident plan, and an event is
+// recorded after its kernels.  The completion thread polls the in-flight
 // events, timestamps finished requests, returns their workspace and budget
 // and wakes the scheduler, so new arrivals join while earlier work is still
 // running on the device.
@@ -41,20 +45,36 @@ double now_s()
 
 using LatKey = std::tuple<int64_t, int64_t, int64_t>;
 
+// Resources of a grouped solve, shared by its requests: the completion
+// event and the staging of its descriptors; the last request to finish
+// returns them.
+struct Group {
+    hipEvent_t ev = nullptr;
+    char *stage_host = nullptr, *stage_dev = nullptr;
+    size_t stage_bytes = 0;
+    int refs = 0;
+};
+
+constexpr int kMaxGroup = 16;  // requests in one grouped solve
+
 struct Req {
     uint64_t ticket = 0;
     lf2_request r{};
-    size_t bytes = 0;     // admission footprint
-    size_t ws_bytes = 0;  // workspace part of it
+    size_t bytes = 0;     // admission footprint (nominal workspace)
+    size_t charge = 0;    // what it holds of the budget once its workspace is taken
+    size_t ws_bytes = 0;  // nominal workspace part of the footprint
+    size_t ws_real = 0;   // size of the workspace buffer it got
     double t_arr = 0, t_adm = 0, t_done = 0, due = 0;
     lf2_status st = LF2_OK;
     bool done = false, has_plan = false;
     hipEvent_t ev = nullptr;
+    Group *grp = nullptr;
     char *ws = nullptr;
     LatKey key{};
 };
 
-// Workspace bytes of a Poisson solve (the same layout the solver uses).
+// Workspace bytes of a request: enough for a solve alone (the layout the
+// solver uses) and for a grouped solve (bin rows per z tile).
 size_t ws_bytes_of(const lf2_lattice &lat, int32_t nbins)
 {
     lf2_plan_s tmp;
@@ -67,7 +87,9 @@ size_t ws_bytes_of(const lf2_lattice &lat, int32_t nbins)
     tmp.len[0] = (int)(lat.size[0] / 2);
     tmp.len[1] = (int)lat.size[1];
     tmp.len[2] = (int)lat.size[2];
-    return poisson_ws_bytes(&tmp, nbins, false);
+    const size_t solo = poisson_ws_bytes(&tmp, nbins, false);
+    const size_t grouped = group_supported(&tmp) ? group_ws_bytes(&tmp, nbins) : 0;
+    return solo > grouped ? solo : grouped;
 }
 
 size_t footprint_of(const lf2_request &r)
@@ -101,6 +123,14 @@ lf2_status validate(const lf2_request *r)
     return LF2_OK;
 }
 
+// Requests that may run as one grouped solve.
+using GroupKey = std::tuple<int64_t, int64_t, int64_t, double, uint32_t, int32_t>;
+GroupKey group_key(const Req *q)
+{
+    return GroupKey{q->r.lat.size[0], q->r.lat.size[1], q->r.lat.size[2], q->r.dx, q->r.flags,
+                    q->r.nbins};
+}
+
 struct PlanEntry {
     lf2_plan plan = nullptr;
     int refs = 0;
@@ -126,7 +156,8 @@ struct lf2_server_s {
     std::unordered_map<uint64_t, Req *> reqs;
     uint64_t next_ticket = 1;
     size_t bytes_inflight = 0, peak = 0;
-    int launching = 0;  // admitted, not yet in flight
+    int launching = 0;  // requests admitted, not yet in flight
+    int units_busy = 0; // launch units (a request, or a group) admitted and not finished
     int64_t n_sub = 0, n_done = 0, n_fail = 0, n_busy = 0, n_budget = 0;
     bool draining = false, stop = false;
 
@@ -135,9 +166,16 @@ struct lf2_server_s {
     std::map<LatKey, PlanEntry> plans;
     uint64_t use_clock = 0;
     int64_t plan_hits = 0, plan_misses = 0;
+    // workspace pool: idle buffers by their real size; the idle bytes count
+    // against the budget (pool lock; admission reads ws_idle holding both locks)
     std::multimap<size_t, char *> ws_free;
-    std::vector<char *> ws_all;
+    std::map<char *, size_t> ws_size;
+    size_t ws_idle = 0;
+    size_t peak_use = 0;  // largest in-flight + idle bytes seen
     std::vector<hipEvent_t> ev_free, ev_all;
+    std::multimap<size_t, std::pair<char *, char *>> stage_free;  // pinned host, device
+    std::vector<std::pair<char *, char *>> stage_all;
+    int64_t n_groups = 0, n_grouped = 0;
 
     std::thread sched, compl_;
 };
@@ -186,26 +224,123 @@ void put_plan(lf2_server s, const LatKey &key)
     if (it != s->plans.end() && it->second.refs > 0) it->second.refs -= 1;
 }
 
-char *ws_get(lf2_server s, size_t bytes)
+char *ws_alloc(lf2_server s, size_t bytes)
+{
+    if (s->fake) return (char *)malloc(1);  // a token: the fake executor runs no kernels
+    void *p = nullptr;
+    if (hipMalloc(&p, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    return (char *)p;
+}
+
+void ws_release(lf2_server s, char *p)
+{
+    if (s->fake)
+        free(p);
+    else
+        (void)hipFree(p);
+}
+
+// Free idle buffers, those that would not serve a `keep`-byte request
+// first, until `need` more bytes fit the budget next to `inflight` (pool
+// lock held by the caller; `mu` too).
+void ws_trim_locked(lf2_server s, size_t inflight, size_t need, size_t keep)
+{
+    for (int pass = 0; pass < 2; ++pass) {
+        for (auto it = s->ws_free.begin(); it != s->ws_free.end();) {
+            if (inflight + s->ws_idle + need <= s->budget) return;
+            const bool fits = it->first >= keep && it->first <= 2 * keep;
+            if (pass == 0 && fits) {
+                ++it;
+                continue;
+            }
+            ws_release(s, it->second);
+            s->ws_idle -= it->first;
+            s->ws_size.erase(it->second);
+            it = s->ws_free.erase(it);
+        }
+    }
+}
+
+// A workspace of at least `bytes`: an idle buffer of at most twice that
+// size, else a new one (after freeing idle buffers that do not fit, if the
+// allocation fails).  *real: its size.
+char *ws_get(lf2_server s, size_t bytes, size_t *real)
 {
     std::lock_guard<std::mutex> lk(s->pmu);
     auto it = s->ws_free.lower_bound(bytes);
     if (it != s->ws_free.end() && it->first <= 2 * bytes) {
         char *p = it->second;
+        *real = it->first;
+        s->ws_idle -= it->first;
         s->ws_free.erase(it);
         return p;
     }
-    void *p = nullptr;
-    if (hipMalloc(&p, bytes) != hipSuccess) return nullptr;
-    s->ws_all.push_back((char *)p);
-    return (char *)p;
+    char *p = ws_alloc(s, bytes);
+    if (!p) {
+        for (auto &kv : s->ws_free) {
+            ws_release(s, kv.second);
+            s->ws_size.erase(kv.second);
+        }
+        s->ws_free.clear();
+        s->ws_idle = 0;
+        p = ws_alloc(s, bytes);
+        if (!p) return nullptr;
+    }
+    s->ws_size[p] = bytes;
+    *real = bytes;
+    return p;
 }
 
-void ws_put(lf2_server s, char *p, size_t bytes)
+void ws_put(lf2_server s, char *p)
 {
     if (!p) return;
     std::lock_guard<std::mutex> lk(s->pmu);
-    s->ws_free.emplace(bytes, p);
+    auto it = s->ws_size.find(p);
+    const size_t real = it == s->ws_size.end() ? 0 : it->second;
+    s->ws_free.emplace(real, p);
+    s->ws_idle += real;
+}
+
+// Staging for a grouped solve's descriptors: pinned host and device memory
+// of at least `bytes`, pooled.
+bool stage_get(lf2_server s, size_t bytes, Group *g)
+{
+    std::lock_guard<std::mutex> lk(s->pmu);
+    auto it = s->stage_free.lower_bound(bytes);
+    if (it != s->stage_free.end()) {
+        g->stage_host = it->second.first;
+        g->stage_dev = it->second.second;
+        g->stage_bytes = it->first;
+        s->stage_free.erase(it);
+        return true;
+    }
+    const size_t b = bytes < 4096 ? 4096 : bytes;
+    void *h = nullptr, *d = nullptr;
+    if (hipHostMalloc(&h, b, 0) != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    if (hipMalloc(&d, b) != hipSuccess) {
+        (void)hipGetLastError();
+        (void)hipHostFree(h);
+        return false;
+    }
+    s->stage_all.emplace_back((char *)h, (char *)d);
+    g->stage_host = (char *)h;
+    g->stage_dev = (char *)d;
+    g->stage_bytes = b;
+    return true;
+}
+
+void stage_put(lf2_server s, Group *g)
+{
+    if (!g->stage_host) return;
+    std::lock_guard<std::mutex> lk(s->pmu);
+    s->stage_free.emplace(g->stage_bytes, std::make_pair(g->stage_host, g->stage_dev));
+    g->stage_host = g->stage_dev = nullptr;
 }
 
 hipEvent_t ev_get(lf2_server s)
@@ -229,98 +364,233 @@ void ev_put(lf2_server s, hipEvent_t e)
     s->ev_free.push_back(e);
 }
 
-// Launch one admitted request (no server lock held; the scheduler thread or
-// a submitting thread).  On failure nothing of the request is left running
-// on the device.
-void launch(lf2_server s, Req *q)
+// The plan's tables for a request, made on first use on stream `strm` (and
+// waited for once, since later requests may run on other streams); the plan
+// lists are only touched under the pool lock, which is not held while
+// kernels are enqueued.
+lf2_status request_tables(lf2_server s, lf2_plan plan, const lf2_request &r, hipStream_t strm,
+                          PoissonTables *t)
 {
-    lf2_plan plan = nullptr;
-    lf2_status st = get_plan(s, q->key, q->r.lat, &plan);
-    if (st) {
-        q->st = st;
-        return;
-    }
-    q->has_plan = true;
-    if (s->fake) {
-        q->st = (q->ticket == s->fail_ticket) ? LF2_ERR_DEVICE : LF2_OK;
-        return;
-    }
-    q->ws = ws_get(s, q->ws_bytes);
-    q->ev = ev_get(s);
-    if (!q->ws || !q->ev) {
-        q->st = LF2_ERR_OUT_OF_MEMORY;
-        return;
-    }
-    hipStream_t strm = s->streams[s->rr.fetch_add(1) % (unsigned)s->nstreams];
-    {
-        // Tables a plan builds on first use are written on this stream;
-        // later requests may run on other streams, so wait for them once.
-        std::lock_guard<std::mutex> lk(s->pmu);
-        const size_t nk = plan->k2.size(), ns = plan->shells.size();
-        const double *k2[3];
-        ShellEntry sh{};
-        st = get_k2(plan, q->r.dx, (q->r.flags & LF2_POISSON_DISCRETE_K2) ? 1 : 0, strm, k2);
-        if (st == LF2_OK && q->r.nbins > 0) st = get_shell(plan, q->r.nbins, strm, &sh);
-        if (st == LF2_OK && (plan->k2.size() != nk || plan->shells.size() != ns) &&
-            hipStreamSynchronize(strm) != hipSuccess)
-            st = LF2_ERR_DEVICE;
-        if (st == LF2_OK)
-            st = poisson_impl(plan, q->r.rho, q->r.phi, q->r.dx, q->r.flags, q->r.nbins,
-                              q->r.d_pk, q->r.d_kmean, q->r.d_count, nullptr, strm, q->ws,
-                              q->ws_bytes);
-    }
-    if (st == LF2_OK && hipEventRecord(q->ev, strm) != hipSuccess) st = LF2_ERR_DEVICE;
-    if (st != LF2_OK) (void)hipStreamSynchronize(strm);
-    q->st = st;
+    std::lock_guard<std::mutex> lk(s->pmu);
+    const size_t nk = plan->k2.size(), ns = plan->shells.size();
+    lf2_status st = get_k2(plan, r.dx, (r.flags & LF2_POISSON_DISCRETE_K2) ? 1 : 0, strm, t->k2);
+    t->sh = ShellEntry{};
+    if (st == LF2_OK && r.nbins > 0) st = get_shell(plan, r.nbins, strm, &t->sh);
+    if (st == LF2_OK && (plan->k2.size() != nk || plan->shells.size() != ns) &&
+        hipStreamSynchronize(strm) != hipSuccess)
+        st = fail(LF2_ERR_DEVICE, "plan tables");
+    return st;
 }
 
-// Return a finished request's resources (completion thread).
-void release(lf2_server s, Req *q)
+// Take the request's workspace and settle its budget charge (server lock
+// not held).
+bool take_ws(lf2_server s, Req *q)
 {
-    if (!s->fake) {
-        ws_put(s, q->ws, q->ws_bytes);
+    size_t real = 0;
+    q->ws = ws_get(s, q->ws_bytes, &real);
+    if (!q->ws) return false;
+    q->ws_real = real;
+    std::lock_guard<std::mutex> lk(s->mu);
+    // an idle buffer larger than asked moves from the pool to the request:
+    // in-flight plus idle bytes do not grow by more than the admission check
+    q->charge = q->bytes - q->ws_bytes + real;
+    s->bytes_inflight += q->charge - q->bytes;
+    return true;
+}
+
+// Launch admitted requests that form one unit: a single request, or a
+// group sharing lattice, dx, k^2 kind and bin count (no server lock held;
+// the scheduler thread or a submitting thread).  On failure nothing of the
+// unit is left running on the device and every request of it carries the
+// error.
+void launch_unit(lf2_server s, std::vector<Req *> &unit)
+{
+    Req *q0 = unit[0];
+    lf2_plan plan = nullptr;
+    lf2_status st = get_plan(s, q0->key, q0->r.lat, &plan);
+    if (st) {
+        for (Req *q : unit) q->st = st;
+        return;
+    }
+    q0->has_plan = true;
+    for (size_t i = 1; i < unit.size(); ++i) {
+        lf2_plan p2 = nullptr;
+        st = get_plan(s, unit[i]->key, unit[i]->r.lat, &p2);  // a reference per request
+        if (st) break;
+        unit[i]->has_plan = true;
+    }
+    if (s->fake) {
+        for (Req *q : unit) {
+            if (st == LF2_OK && !take_ws(s, q)) st = LF2_ERR_OUT_OF_MEMORY;
+            q->st = st ? st : (q->ticket == s->fail_ticket ? LF2_ERR_DEVICE : LF2_OK);
+        }
+        if (unit.size() > 1) {
+            Group *g = new Group();
+            g->refs = (int)unit.size();
+            for (Req *q : unit) q->grp = g;
+            std::lock_guard<std::mutex> lk(s->mu);
+            s->n_groups += 1;
+            s->n_grouped += (int64_t)unit.size();
+        }
+        return;
+    }
+    for (Req *q : unit)
+        if (st == LF2_OK && !take_ws(s, q)) st = fail(LF2_ERR_OUT_OF_MEMORY, "workspace");
+    hipStream_t strm = s->streams[s->rr.fetch_add(1) % (unsigned)s->nstreams];
+    PoissonTables tabs{};
+    if (st == LF2_OK) st = request_tables(s, plan, q0->r, strm, &tabs);
+    const int R = (int)unit.size();
+    Group *g = nullptr;
+    if (st == LF2_OK && R > 1) {
+        g = new (std::nothrow) Group();
+        if (!g || !stage_get(s, group_stage_bytes(plan, R), g)) {
+            st = fail(LF2_ERR_OUT_OF_MEMORY, "group staging");
+        } else {
+            std::vector<GroupReq> gr(R);
+            for (int i = 0; i < R; ++i)
+                gr[i] = GroupReq{unit[i]->r.rho, unit[i]->r.phi, unit[i]->r.d_pk,
+                                 unit[i]->r.d_kmean, unit[i]->r.d_count, unit[i]->ws};
+            st = group_enqueue(plan, R, gr.data(), q0->r.dx, q0->r.flags, q0->r.nbins, tabs,
+                               g->stage_host, g->stage_dev, g->stage_bytes, strm);
+        }
+    } else if (st == LF2_OK) {
+        st = poisson_impl(plan, q0->r.rho, q0->r.phi, q0->r.dx, q0->r.flags, q0->r.nbins,
+                          q0->r.d_pk, q0->r.d_kmean, q0->r.d_count, nullptr, strm, q0->ws,
+                          q0->ws_real, false, &tabs);
+    }
+    hipEvent_t ev = st == LF2_OK ? ev_get(s) : nullptr;
+    if (st == LF2_OK && (!ev || hipEventRecord(ev, strm) != hipSuccess)) st = LF2_ERR_DEVICE;
+    if (st != LF2_OK) {
+        (void)hipStreamSynchronize(strm);
+        if (ev) ev_put(s, ev);
+        ev = nullptr;
+        if (g) {
+            stage_put(s, g);
+            delete g;
+            g = nullptr;
+        }
+    }
+    if (g) {
+        g->ev = ev;
+        g->refs = R;
+        std::lock_guard<std::mutex> lk(s->mu);
+        s->n_groups += 1;
+        s->n_grouped += R;
+    }
+    for (Req *q : unit) {
+        q->st = st;
+        q->ev = ev;
+        q->grp = g;
+    }
+}
+
+// Return a finished request's resources (completion thread).  True when
+// this was the last request of its launch unit.
+bool release(lf2_server s, Req *q)
+{
+    bool unit_done = true;
+    if (q->ws) ws_put(s, q->ws);
+    if (q->grp) {
+        Group *g = q->grp;
+        if (--g->refs == 0) {  // the completion thread is the only one touching refs here
+            if (g->ev) ev_put(s, g->ev);
+            stage_put(s, g);
+            delete g;
+        } else {
+            unit_done = false;
+        }
+    } else if (!s->fake && q->ev) {
         ev_put(s, q->ev);
     }
     if (q->has_plan) put_plan(s, q->key);
     q->ws = nullptr;
     q->ev = nullptr;
+    q->grp = nullptr;
+    return unit_done;
 }
 
-// Admit from the head of the queue while a slot and budget are free (FIFO:
-// a request that does not fit holds back the ones behind it).  Server lock
-// held.
-void admit_locked(lf2_server s, std::vector<Req *> &adm)
+// Whether requests of this key can run as one grouped solve.
+bool groupable(const Req *q)
+{
+    lf2_plan_s tmp;
+    tmp.kind = LF2_R2C;
+    tmp.nc = 1;
+    tmp.len[0] = (int)(q->r.lat.size[0] / 2);
+    tmp.len[1] = (int)q->r.lat.size[1];
+    tmp.len[2] = (int)q->r.lat.size[2];
+    return group_supported(&tmp) && q->r.nbins <= kBatchMaxBins;
+}
+
+// Budget check of one request (idle pooled workspace is freed to make room);
+// charges it when it fits.  Server lock held.
+bool fits_budget_locked(lf2_server s, Req *q)
+{
+    if (s->bytes_inflight + q->bytes > s->budget) return false;
+    std::lock_guard<std::mutex> pk(s->pmu);
+    if (s->bytes_inflight + s->ws_idle + q->bytes > s->budget)
+        ws_trim_locked(s, s->bytes_inflight, q->bytes, q->ws_bytes);
+    if (s->bytes_inflight + s->ws_idle + q->bytes > s->budget) return false;
+    s->peak_use = std::max(s->peak_use, s->bytes_inflight + s->ws_idle + q->bytes);
+    s->bytes_inflight += q->bytes;
+    q->charge = q->bytes;
+    s->peak = std::max(s->peak, s->bytes_inflight);
+    return true;
+}
+
+// Admit launch units from the head of the queue while a slot is free: the
+// head request, joined by later queued requests of the same lattice, dx,
+// k^2 kind and bin count (at most kMaxGroup in all) while the budget holds
+// them -- those run as one grouped solve.  A unit takes one slot.  FIFO for
+// the heads: a head that does not fit the budget holds back the ones behind
+// it.  Server lock held.
+void admit_locked(lf2_server s, std::vector<std::vector<Req *>> &adm)
 {
     while (!s->queue.empty()) {
+        if (s->units_busy >= s->max_slots) break;
         Req *q = s->queue.front();
-        if ((int)s->inflight.size() + s->launching >= s->max_slots) break;
-        if (s->bytes_inflight + q->bytes > s->budget) break;
+        if (!fits_budget_locked(s, q)) break;
         s->queue.pop_front();
-        s->bytes_inflight += q->bytes;
-        s->peak = std::max(s->peak, s->bytes_inflight);
-        s->launching += 1;
-        q->t_adm = now_s();
-        adm.push_back(q);
+        std::vector<Req *> unit{q};
+        if (groupable(q)) {
+            const GroupKey k = group_key(q);
+            for (auto it = s->queue.begin(); it != s->queue.end() && (int)unit.size() < kMaxGroup;) {
+                if (group_key(*it) == k && fits_budget_locked(s, *it)) {
+                    unit.push_back(*it);
+                    it = s->queue.erase(it);
+                } else {
+                    ++it;
+                }
+            }
+        }
+        const double t = now_s();
+        for (Req *u : unit) u->t_adm = t;
+        s->launching += (int)unit.size();
+        s->units_busy += 1;
+        adm.push_back(std::move(unit));
     }
 }
 
-// Launch admitted requests and hand them to the completion thread; called
-// and returns with the server lock held.
-void launch_admitted(lf2_server s, std::unique_lock<std::mutex> &lk, std::vector<Req *> &adm)
+// Launch admitted units and hand them to the completion thread; called and
+// returns with the server lock held.
+void launch_admitted(lf2_server s, std::unique_lock<std::mutex> &lk,
+                     std::vector<std::vector<Req *>> &adm)
 {
     if (adm.empty()) return;
     lk.unlock();
     int prev = -1;
     if (!s->fake && hipGetDevice(&prev) == hipSuccess && prev != s->device)
         (void)hipSetDevice(s->device);  // a submitting thread may have another device current
-    for (Req *q : adm) {
-        launch(s, q);
-        if (s->fake) q->due = q->t_adm + 1e-6 * s->delay_us;
+    for (std::vector<Req *> &u : adm) {
+        launch_unit(s, u);
+        if (s->fake)
+            for (Req *q : u) q->due = q->t_adm + 1e-6 * s->delay_us;
     }
     if (prev >= 0 && prev != s->device) (void)hipSetDevice(prev);
     lk.lock();
-    s->launching -= (int)adm.size();
-    for (Req *q : adm) s->inflight.push_back(q);
+    for (std::vector<Req *> &u : adm) {
+        s->launching -= (int)u.size();
+        for (Req *q : u) s->inflight.push_back(q);
+    }
     s->cv_compl.notify_one();
 }
 
@@ -332,11 +602,11 @@ void scheduler_main(lf2_server s)
         s->cv_sched.wait(lk, [&] {
             if (s->stop) return true;
             if (s->queue.empty()) return false;
-            return (int)s->inflight.size() + s->launching < s->max_slots &&
+            return s->units_busy < s->max_slots &&
                    s->bytes_inflight + s->queue.front()->bytes <= s->budget;
         });
         if (s->stop) break;
-        std::vector<Req *> adm;
+        std::vector<std::vector<Req *>> adm;
         admit_locked(s, adm);
         launch_admitted(s, lk, adm);
     }
@@ -373,8 +643,10 @@ void completion_main(lf2_server s)
             }
         }
         const double tdone = now_s();
-        for (Req *q : fin) release(s, q);
+        int units_done = 0;
+        for (Req *q : fin) units_done += release(s, q) ? 1 : 0;
         lk.lock();
+        s->units_busy -= units_done;
         if (fin.empty()) {
             // requests in flight: poll again at once (yield the core to
             // other runnable threads); the fake executor's delays are long
@@ -388,7 +660,7 @@ void completion_main(lf2_server s)
         }
         for (Req *q : fin) {
             s->inflight.erase(std::find(s->inflight.begin(), s->inflight.end(), q));
-            s->bytes_inflight -= q->bytes;
+            s->bytes_inflight -= q->charge;
             q->t_done = tdone;
             q->done = true;
             if (q->st == LF2_OK)
@@ -504,9 +776,16 @@ lf2_status lf2_server_prepare(lf2_server s, int32_t n, const lf2_lattice *lats, 
         r.lat = L;
         r.nbins = nbins;
         const size_t wb = ws_bytes_of(L, nbins);
-        char *w = ws_get(s, wb);
+        {
+            // only while the budget holds it next to what is in flight
+            std::lock_guard<std::mutex> lk(s->mu);
+            std::lock_guard<std::mutex> pk(s->pmu);
+            if (s->bytes_inflight + s->ws_idle + wb > s->budget) continue;
+        }
+        size_t real = 0;
+        char *w = ws_get(s, wb, &real);
         if (!w) return fail(LF2_ERR_OUT_OF_MEMORY, "workspace");
-        ws_put(s, w, wb);
+        ws_put(s, w);
     }
     LF2_HIP(hipDeviceSynchronize());
     return LF2_OK;
@@ -555,7 +834,7 @@ lf2_status lf2_server_submit(lf2_server s, const lf2_request *r, uint64_t *ticke
     if (s->queue.size() == 1) {
         // nothing waits ahead of it: admit and launch on this thread, which
         // saves the hand-off to the scheduler thread
-        std::vector<Req *> adm;
+        std::vector<std::vector<Req *>> adm;
         admit_locked(s, adm);
         launch_admitted(s, lk, adm);
     }
@@ -596,11 +875,15 @@ lf2_status lf2_server_get_stats(lf2_server s, lf2_server_stats *st)
     st->queued = (int64_t)s->queue.size();
     st->bytes_in_flight = s->bytes_inflight;
     st->peak_bytes_in_flight = s->peak;
+    st->groups = s->n_groups;
+    st->grouped_requests = s->n_grouped;
     {
         std::lock_guard<std::mutex> pk(s->pmu);
         st->plans_cached = (int64_t)s->plans.size();
         st->plan_hits = s->plan_hits;
         st->plan_misses = s->plan_misses;
+        st->pooled_idle_bytes = s->ws_idle;
+        st->peak_bytes_in_use = s->peak_use;
     }
     return LF2_OK;
 }
@@ -621,12 +904,16 @@ lf2_status lf2_server_destroy(lf2_server s)
     if (s->sched.joinable()) s->sched.join();
     if (s->compl_.joinable()) s->compl_.join();
     for (auto &kv : s->reqs) delete kv.second;
+    for (auto &kv : s->ws_free) ws_release(s, kv.second);  // every buffer is idle now
     if (!s->fake) {
         for (hipStream_t x : s->streams) (void)hipStreamSynchronize(x);
         for (auto &kv : s->plans)
             if (kv.second.plan) lf2_plan_destroy(kv.second.plan);
-        for (char *p : s->ws_all) (void)hipFree(p);
         for (hipEvent_t e : s->ev_all) (void)hipEventDestroy(e);
+        for (auto &hd : s->stage_all) {
+            (void)hipHostFree(hd.first);
+            (void)hipFree(hd.second);
+        }
         for (hipStream_t x : s->streams) (void)hipStreamDestroy(x);
     }
     delete s;

@@ -43,16 +43,31 @@ def test_version_and_status_strings(lib):
     ((0, 32, 32), 0, 1, 0, 3, -1),           # empty extent
     ((33, 32, 32), 0, 1, 1, 3, -2),          # prime factor 11
     ((14, 32, 32), 0, 1, 0, 3, -2),          # prime factor 7
-    ((15, 32, 32), 0, 1, 1, 3, -2),          # both 3 and 5 in one extent
     ((31, 32, 32), 0, 1, 0, 3, -2),          # odd N0 for r2c
-    ((32, 32, 32), 0, 4, 0, 3, -2),          # four components: no kernel in this build
     ((32, 32, 32), 0, 1, 7, 3, -1),          # bad kind
-    ((4096, 32, 32), 0, 1, 1, 3, -2),        # line longer than the compiled kernels
+    ((16384, 32, 32), 0, 1, 1, 3, -2),       # line longer than the run-time kernels take
+    ((32, 3 * 8192, 32), 0, 1, 1, 3, -2),    # likewise along y
+    ((7 * 16, 32, 32), 0, 1, 1, 3, -2),      # prime factor 7 with a power of two
 ])
 def test_plan_validation(lib, sizes, halo, ncomp, kind, dim, expect):
     st = lib.lf2_fft_plan_status(sizes, halo, ncomp, kind, dim=dim)
     assert st == expect, (st, lib.last_error())
     assert lib.last_error()
+
+
+@pytest.mark.parametrize("sizes,ncomp,kind", [
+    ((15, 32, 32), 1, 1),          # both 3 and 5 in one extent
+    ((15 * 16, 9 * 128, 45), 1, 1),
+    ((18, 25, 27), 1, 0),          # r2c with N0/2 = 9
+    ((144, 360, 450), 1, 0),
+    ((720, 900, 8), 3, 1),
+    ((32, 32, 32), 4, 0),          # four components: run-time kernels along x
+])
+def test_plan_accepts_any_235_extent(lib, sizes, ncomp, kind):
+    """Every 2^a 3^b 5^c extent passes validation: without a GPU the call then
+    fails only at the device query (LF2_ERR_DEVICE), never as unsupported."""
+    st = lib.lf2_fft_plan_status(sizes, 0, ncomp, kind)
+    assert st in (lib.LF2_OK, lib.LF2_ERR_DEVICE), (st, lib.last_error())
 
 
 def test_null_plan_calls(lib):

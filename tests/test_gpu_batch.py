@@ -1,6 +1,6 @@
-"""GPU tests of the batched persistent launch: every field against the FP64
-oracle, batch against solo solves, and repeated graph launches with eager
-work in between."""
+"""GPU tests of the batched solves -- one persistent launch by default, and
+the grouped launches -- every field against the FP64 oracle, batch against
+solo solves, and repeated graph launches with eager work in between."""
 import numpy as np
 import pytest
 
@@ -37,19 +37,14 @@ def fields_for(sizes, seed):
     return out
 
 
-@pytest.mark.skip(reason="single persistent launch with in-kernel dependency counters: did not "
-                         "finish on gfx950 in testing, cause not found; that code path is removed "
-                         "and batches run as grouped launches in a hipGraph")
-def test_batch_single_persistent_launch(lf2):
-    pass
-
-
-def test_batch_tiny(lf2):
-    """Two small fields; a dependency error shows up as error bit 0 within a second."""
+@pytest.mark.parametrize("grouped", [False, True])
+def test_batch_tiny(lf2, grouped):
+    """Two small fields; a dependency wait that gives up shows up as error bit 0."""
     sizes = [(32, 32, 32), (64, 32, 16)]
     fs = fields_for(sizes, seed=30)
-    b = lf2.Batch(sizes, nbins=8)
-    print(f"case batch tiny: items {b.nitems} launches {b.launches}", flush=True)
+    b = lf2.Batch(sizes, nbins=8, grouped=grouped)
+    print(f"case batch tiny grouped={grouped}: items {b.nitems} launches {b.launches}", flush=True)
+    assert grouped or b.launches == 1
     rhos = [torch.from_numpy(f).to(dev()) for f in fs]
     phis = [torch.zeros_like(r) for r in rhos]
     pks = [torch.zeros(8, dtype=torch.float64, device=dev()) for _ in fs]
@@ -65,11 +60,16 @@ def test_batch_tiny(lf2):
         assert_close(pk.cpu().numpy(), opk, s)
 
 
-def test_batch_matches_oracle_and_solo(lf2):
-    print("case batch small mixed sizes", flush=True)
+@pytest.mark.parametrize("mode", ["xcd", "one_queue", "grouped"])
+def test_batch_matches_oracle_and_solo(lf2, mode):
+    print(f"case batch small mixed sizes mode={mode}", flush=True)
     nb = 16
     fs = fields_for(SMALL, seed=31)
-    b = lf2.Batch(SMALL, nbins=nb)
+    b = lf2.Batch(SMALL, nbins=nb, grouped=mode == "grouped", one_queue=mode == "one_queue")
+    print(f"  launches {b.launches} queues {b.queues} per-XCD {b.per_xcd}", flush=True)
+    assert mode == "grouped" or b.launches == 1
+    if mode == "one_queue":
+        assert b.queues == 1 and b.per_xcd == 0
     rhos = [torch.from_numpy(f).to(dev()) for f in fs]
     phis = [torch.zeros_like(r) for r in rhos]
     pks = [torch.zeros(nb, dtype=torch.float64, device=dev()) for _ in fs]
@@ -95,10 +95,12 @@ def test_batch_matches_oracle_and_solo(lf2):
         assert rel_l2(spk.cpu().numpy(), pks[i].cpu().numpy()) <= 1e-6
 
 
-def test_batch_graph_replays_with_eager_work(lf2):
+@pytest.mark.parametrize("grouped", [False, True])
+def test_batch_graph_replays_with_eager_work(lf2, grouped):
+    print(f"case batch replays grouped={grouped}", flush=True)
     sizes = [(64, 64, 64), (96, 32, 48), (32, 128, 64)]
     fs = fields_for(sizes, seed=32)
-    b = lf2.Batch(sizes)
+    b = lf2.Batch(sizes, nbins=8, grouped=grouped)
     rhos = [torch.from_numpy(f).to(dev()) for f in fs]
     phis = [torch.zeros_like(r) for r in rhos]
     b.run(rhos, phis)
@@ -142,12 +144,21 @@ def test_batch_config_48_uneven_grf(lf2):
         f32, f64, _ = grf_field(s, 2.0, seed=1000 + i)
         fl.append((f32, f64))
     b = lf2.Batch(sizes, nbins=32)
+    print(f"  one persistent launch: {b.launches} launch(es), {b.nitems} work items, "
+          f"{b.queues} queues, per-XCD {b.per_xcd}", flush=True)
+    assert b.launches == 1
     rhos = [torch.from_numpy(f32).to(dev()) for f32, _ in fl]
     phis = [torch.zeros_like(r) for r in rhos]
     pks = [torch.zeros(32, dtype=torch.float64, device=dev()) for _ in fl]
     b.run(rhos, phis, pks)
     torch.cuda.synchronize()
     assert b.error() == 0
+    # a second replay gives the same bits (the queue resets itself)
+    phis2 = [torch.zeros_like(r) for r in rhos]
+    b.run(rhos, phis2, pks)
+    torch.cuda.synchronize()
+    assert b.error() == 0
+    assert all(torch.equal(a, c) for a, c in zip(phis, phis2))
     worst = 0.0
     for i, (s, (f32, f64)) in enumerate(zip(sizes, fl)):
         opk, _, _ = oracle.power_spectrum(oracle.r2c(f64), s, 32)
@@ -157,17 +168,21 @@ def test_batch_config_48_uneven_grf(lf2):
     print(f"  worst error / tolerance {worst:.3e}", flush=True)
 
 
-@pytest.mark.parametrize("discrete,dx", [(0, 0.5), (1, 1.0), (1, 0.25)])
-def test_batch_without_pk_flags_and_dx(lf2, discrete, dx):
-    """Poisson-only batches (no binning epilogue, no finalize launch) with the
+@pytest.mark.parametrize("discrete,dx,grouped", [(0, 0.5, False), (1, 1.0, False), (1, 0.25, True)])
+def test_batch_without_pk_flags_and_dx(lf2, discrete, dx, grouped):
+    """Poisson-only batches (no binning epilogue, no finalize) with the
     discrete-Laplacian k^2 and a lattice spacing: every field against the
     oracle and against its solo solve with the same settings."""
-    print(f"case batch no pk discrete={discrete} dx={dx}", flush=True)
+    print(f"case batch no pk discrete={discrete} dx={dx} grouped={grouped}", flush=True)
     flags = lf2.LF2_POISSON_DISCRETE_K2 if discrete else 0
     fs = fields_for(SMALL, seed=33)
-    b = lf2.Batch(SMALL, nbins=0, dx=dx, poisson_flags=flags)
-    bp = lf2.Batch(SMALL, nbins=8, dx=dx, poisson_flags=flags)
-    assert b.launches + 1 == bp.launches  # the finalize only with binning
+    b = lf2.Batch(SMALL, nbins=0, dx=dx, poisson_flags=flags, grouped=grouped)
+    bp = lf2.Batch(SMALL, nbins=8, dx=dx, poisson_flags=flags, grouped=grouped)
+    if grouped:
+        assert b.launches + 1 == bp.launches  # the finalize launch only with binning
+    else:
+        assert b.launches == bp.launches == 1
+        assert b.nitems + len(SMALL) == bp.nitems  # one finalize item per field
     bp.close()
     rhos = [torch.from_numpy(f).to(dev()) for f in fs]
     phis = [torch.zeros_like(r) for r in rhos]

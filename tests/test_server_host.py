@@ -36,8 +36,10 @@ def overlap_max(results):
 
 
 def test_fifo_and_slot_limit():
+    # distinct bin counts: no two requests can share a grouped solve, so each
+    # is a launch unit of its own and takes a slot
     s = lf2.Server(1 << 40, max_slots=2, fake=True, delay_us=15000)
-    tickets = [s.submit_raw((64, 64, 64), RHO, PHI)[1] for _ in range(6)]
+    tickets = [s.submit_raw((64, 64, 64), RHO, PHI, nbins=i + 1)[1] for i in range(6)]
     res = [s.poll(t) for t in tickets]
     s.close()
     assert all(r[0] == lf2.LF2_OK for r in res)
@@ -234,3 +236,57 @@ def test_latency_percentiles_nearest_rank():
     assert lf2.latency_percentiles(w, (50, 99)) == (4.0, 9.0)
     with pytest.raises(ValueError):
         lf2.latency_percentiles([], (50,))
+
+
+def test_pooled_workspace_counts_against_budget():
+    """A mix of sizes under a small budget: in-flight plus idle pooled
+    workspace never exceeds the budget (idle buffers that do not fit are
+    freed to make room), and buffers are reused."""
+    import random
+    sizes = [(32, 32, 32), (64, 64, 64), (64, 32, 48), (96, 64, 64), (128, 64, 32)]
+    fp = {sz: lf2.Server(1, fake=True).footprint(sz, nbins=16) for sz in sizes}
+    budget = int(2.2 * max(fp.values()))
+    s = lf2.Server(budget, max_slots=8, max_queue=64, fake=True, delay_us=3000)
+    rng = random.Random(7)
+    tickets = []
+    for i in range(60):
+        sz = rng.choice(sizes)
+        st, t = s.submit_raw(sz, RHO, PHI, nbins=16)
+        while st == lf2.LF2_ERR_BUSY:
+            time.sleep(0.002)
+            st, t = s.submit_raw(sz, RHO, PHI, nbins=16)
+        assert st == lf2.LF2_OK
+        tickets.append(t)
+        if i % 7 == 0:
+            time.sleep(0.004)
+        cur = s.stats()
+        assert cur["bytes_in_flight"] + cur["pooled_idle_bytes"] <= budget
+    res = [s.poll(t) for t in tickets]
+    st = s.stats()
+    s.close()
+    assert all(r[0] == lf2.LF2_OK for r in res)
+    assert st["peak_bytes_in_use"] <= budget
+    assert st["bytes_in_flight"] == 0
+    assert 0 < st["pooled_idle_bytes"] <= budget
+
+
+def test_requests_queued_together_are_grouped():
+    """Requests that wait for a slot are admitted in launch units: the head
+    of the queue with every queued request of the same lattice, dx, k^2 kind
+    and bin count, as one grouped solve in one slot; the others wait their
+    turn in order."""
+    s = lf2.Server(1 << 40, max_slots=1, max_queue=64, fake=True, delay_us=30000)
+    first = s.submit_raw((32, 32, 32), RHO, PHI)[1]          # takes the only slot
+    a = [s.submit_raw((64, 64, 64), RHO, PHI, nbins=8)[1] for _ in range(2)]
+    b = s.submit_raw((64, 64, 64), RHO, PHI, nbins=16)[1]     # another bin count
+    a += [s.submit_raw((64, 64, 64), RHO, PHI, nbins=8)[1] for _ in range(2)]
+    res = {t: s.poll(t) for t in [first] + a + [b]}
+    st = s.stats()
+    s.close()
+    assert all(r[0] == lf2.LF2_OK for r in res.values())
+    assert st["groups"] == 1 and st["grouped_requests"] == 4
+    # the four nbins=8 requests ran together, after the first and before b
+    ta = {res[t][2] for t in a}
+    assert len(ta) == 1
+    assert res[first][3] <= min(ta) + 1e-6
+    assert res[b][2] >= res[a[0]][3] - 1e-6
