@@ -276,6 +276,7 @@ ModeTables base_tables(const lf2_plan_s *p)
     ModeTables mt{};
     mt.nxk = (int)p->nxk;
     mt.n0 = (int)p->n[0];
+    mt.n1 = (int)p->n[1];
     mt.half = p->kind == LF2_R2C ? 1 : 0;
     for (int i = 0; i < 3; ++i) {
         mt.k2[i] = nullptr;
@@ -288,15 +289,25 @@ ModeTables base_tables(const lf2_plan_s *p)
     // below 2^32 whenever N2 > 1 (it is then at most qmax); unused for N2 = 1
     const int64_t uz = p->lcm / p->n[2];
     mt.qz_unit = (uint32_t)(uz * uz);
-    mt.k2z_unit = 0.0;
+    // (lcm / N_i)^2 <= qmax < 2^32 for N_i > 1; m = 0 only along N_i = 1
+    const int64_t ux = p->lcm / p->n[0], uy = p->lcm / p->n[1];
+    mt.qx_unit = (uint32_t)(ux * ux);
+    mt.qy_unit = (uint32_t)(uy * uy);
+    mt.k2z_unit = mt.k2x_unit = mt.k2y_unit = 0.0;
     return mt;
 }
 
-double k2z_unit(const lf2_plan_s *p, double dx, int discrete)
+void set_k2_units(ModeTables &mt, const lf2_plan_s *p, double dx, int discrete)
 {
-    if (discrete) return 0.0;
-    const double u = 6.283185307179586476925286766559 / ((double)p->n[2] * dx);
-    return u * u;
+    double u[3] = {0.0, 0.0, 0.0};
+    if (!discrete)
+        for (int i = 0; i < 3; ++i) {
+            const double a = 6.283185307179586476925286766559 / ((double)p->n[i] * dx);
+            u[i] = a * a;
+        }
+    mt.k2x_unit = u[0];
+    mt.k2y_unit = u[1];
+    mt.k2z_unit = u[2];
 }
 
 lf2_status get_k2(lf2_plan p, double dx, int discrete, hipStream_t s, const double *out[3],
@@ -325,6 +336,21 @@ lf2_status get_k2(lf2_plan p, double dx, int discrete, hipStream_t s, const doub
     return LF2_OK;
 }
 
+// Whether one step of m = |n_z| (q_xy + m^2 q_u to q_xy + (m + 1)^2 q_u)
+// crosses at most one of the thresholds t_1 .. t_{nbins-1}.  A step from
+// q < t_b has m^2 q_u <= q < t_b, so it moves q by (2 m + 1) q_u <
+// 2 sqrt(t_b q_u) + q_u; if every gap t_{b+1} - t_b is at least that (plus
+// one for the rounding of the square root), no step spans two thresholds.
+static bool walk_one_step(const std::vector<int64_t> &t, uint32_t qu)
+{
+    const int nb = (int)t.size() - 1;
+    for (int b = 0; b + 1 <= nb - 1; ++b) {
+        const double need = 2.0 * std::sqrt((double)t[b] * (double)qu) + (double)qu + 1.0;
+        if ((double)(t[b + 1] - t[b]) < need) return false;
+    }
+    return true;
+}
+
 lf2_status get_shell(lf2_plan p, int nbins, hipStream_t s, ShellEntry *out, bool lookup_only)
 {
     for (auto &e : p->shells)
@@ -336,7 +362,7 @@ lf2_status get_shell(lf2_plan p, int nbins, hipStream_t s, ShellEntry *out, bool
         return fail(LF2_ERR_NOT_READY,
                     "no %d-bin shell table on this plan yet: an allocating call with this bin "
                     "count builds it", nbins);
-    ShellEntry e{nbins, nullptr, nullptr, nullptr};
+    ShellEntry e{nbins, nullptr, nullptr, nullptr, 0};
     void *ptr;
     lf2_status st = plan_alloc(p, &ptr, (size_t)(nbins + 1) * 8);
     if (st) return st;
@@ -358,6 +384,7 @@ lf2_status get_shell(lf2_plan p, int nbins, hipStream_t s, ShellEntry *out, bool
     ModeTables mt = base_tables(p);
     mt.thresh = e.thresh;
     mt.nbins = nbins;
+    mt.walk1 = 0;
     hipError_t e3 = launch_shell_partials(mt, (int)p->n[1], (int)p->n[2], 0.0, pc, pkk, grid, s);
     if (e3 == hipSuccess) e3 = launch_reduce_cols(pc, grid, nbins, e.count, s);
     if (e3 == hipSuccess) e3 = launch_reduce_cols(pkk, grid, nbins, e.sumk, s);
@@ -365,6 +392,9 @@ lf2_status get_shell(lf2_plan p, int nbins, hipStream_t s, ShellEntry *out, bool
     (void)hipFree(pc);
     (void)hipFree(pkk);
     if (e3 != hipSuccess) return fail(LF2_ERR_DEVICE, "shell table: %s", hipGetErrorString(e3));
+    std::vector<int64_t> th((size_t)nbins + 1);
+    LF2_HIP(hipMemcpy(th.data(), e.thresh, th.size() * 8, hipMemcpyDeviceToHost));
+    e.walk1 = walk_one_step(th, mt.qz_unit) ? 1 : 0;
     p->shells.push_back(e);
     *out = e;
     return LF2_OK;
@@ -1168,11 +1198,10 @@ lf2_status poisson_impl(lf2_plan p, const float *rho, float *phi, double dx, uin
     if (nb > 0) epi |= (flags & LF2_PK_OF_PHI) ? EPI_PK_AFTER : EPI_PK;
     SArgs za = s_args(p, 2, W, W, epi);
     for (int i = 0; i < 3; ++i) za.mt.k2[i] = k2[i];
-    za.mt.k2z_unit = k2z_unit(p, dx, (flags & LF2_POISSON_DISCRETE_K2) ? 1 : 0);
+    set_k2_units(za.mt, p, dx, (flags & LF2_POISSON_DISCRETE_K2) ? 1 : 0);
     int grid = 0;
     if (nb > 0) {
-        za.mt.thresh = sh.thresh;
-        za.mt.nbins = nb;
+        use_shell(za.mt, sh);
         za.partial = (double *)(ws + L.part);
     }
     if ((st = run_strided(p, 2, -1, za, nb > 0 ? kPkGrid : kStridedGridCap, s, &grid))) return st;
@@ -1276,8 +1305,7 @@ lf2_status lf2_power_spectrum(lf2_plan p, const void *field, int32_t field_is_ks
     int grid = 0;
     if (field_is_kspace) {
         ModeTables mt = base_tables(p);
-        mt.thresh = sh.thresh;
-        mt.nbins = nbins;
+        use_shell(mt, sh);
         grid = kPkGrid;
         const int t = prof::begin("k_pk_kspace", (double)spectrum_bytes(p), s);
         int64_t kst[3];
@@ -1295,8 +1323,7 @@ lf2_status lf2_power_spectrum(lf2_plan p, const void *field, int32_t field_is_ks
         }
         if ((st = run_strided(p, 1, -1, s_args(p, 1, W, W, EPI_STORE), kStridedGridCap, s, nullptr))) return st;
         SArgs za = s_args(p, 2, W, W, EPI_PK);
-        za.mt.thresh = sh.thresh;
-        za.mt.nbins = nbins;
+        use_shell(za.mt, sh);
         za.partial = part;
         if ((st = run_strided(p, 2, -1, za, kPkGrid, s, &grid))) return st;
     }

@@ -313,7 +313,7 @@ lf2_status lf2_batch_plan(lf2_batch *out, int32_t nfields, const lf2_lattice *la
         if ((st = get_k2(p, dx, (poisson_flags & LF2_POISSON_DISCRETE_K2) ? 1 : 0, nullptr, k2)))
             break;
         for (int i = 0; i < 3; ++i) F.z.mt.k2[i] = k2[i];
-        F.z.mt.k2z_unit = k2z_unit(p, dx, (poisson_flags & LF2_POISSON_DISCRETE_K2) ? 1 : 0);
+        set_k2_units(F.z.mt, p, dx, (poisson_flags & LF2_POISSON_DISCRETE_K2) ? 1 : 0);
         // bin histograms per wave where the z tile's LDS leaves room for them
         F.z.hcopies = pk ? epi_hist_copies(p->len[2], nbins,
                                            b->persistent ? batch_persistent_lds() : 80 * 1024)
@@ -327,8 +327,7 @@ lf2_status lf2_batch_plan(lf2_batch *out, int32_t nfields, const lf2_lattice *la
         if (pk) {
             ShellEntry sh{};
             if ((st = get_shell(p, nbins, nullptr, &sh))) break;
-            F.z.mt.thresh = sh.thresh;
-            F.z.mt.nbins = nbins;
+            use_shell(F.z.mt, sh);
             F.partial = b->d_partial + pofs[f];
             F.count = sh.count;
             F.sumk = sh.sumk;
@@ -642,7 +641,7 @@ lf2_status group_enqueue(lf2_plan p, int R, const GroupReq *req, double dx, uint
         F.yi = s_args(p, 1, W, W, EPI_STORE);
         F.z = s_args(p, 2, W, W, EPI_STORE | EPI_POISSON | (pk ? (of_phi ? EPI_PK_AFTER : EPI_PK) : 0));
         for (int i = 0; i < 3; ++i) F.z.mt.k2[i] = tabs.k2[i];
-        F.z.mt.k2z_unit = k2z_unit(p, dx, (flags & LF2_POISSON_DISCRETE_K2) ? 1 : 0);
+        set_k2_units(F.z.mt, p, dx, (flags & LF2_POISSON_DISCRETE_K2) ? 1 : 0);
         F.z.hcopies = pk ? epi_hist_copies(p->len[2], nbins, 80 * 1024) : 1;
         if (F.z.hcopies < 1) F.z.hcopies = 1;
         F.m = p->len[0];
@@ -653,8 +652,7 @@ lf2_status group_enqueue(lf2_plan p, int R, const GroupReq *req, double dx, uint
         F.ntiles[BP_Z] = (int)g.tz;
         F.nbins = nbins;
         if (pk) {
-            F.z.mt.thresh = tabs.sh.thresh;
-            F.z.mt.nbins = nbins;
+            use_shell(F.z.mt, tabs.sh);
             F.partial = (double *)((char *)W + align256(spectrum_bytes(p)));
             F.count = tabs.sh.count;
             F.sumk = tabs.sh.sumk;

@@ -243,6 +243,35 @@ __device__ __forceinline__ void gstore(c32 *p, c32 v)
     }
 }
 
+// Twiddle index r k C (C = L / (NS R), r < R, k < NS, all below 2^24) with
+// a 24-bit multiply (full rate) rather than a 32-bit one.
+template <int C>
+__device__ __forceinline__ int tw_index(int r, int k)
+{
+    return (int)__umul24((unsigned)k, (unsigned)(r * C));
+}
+
+// Points p, p + qs, ..., p + (R - 1) qs of a column (zeros when !gv), and
+// the stores back: one 64-bit pointer add per access, no multiplies.
+template <int R, bool NTM>
+__device__ __forceinline__ void gload_pts(c32 (&v)[R], const c32 *p, int64_t qs, bool gv)
+{
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        v[r] = gv ? gload<NTM>(p) : c32{0.f, 0.f};
+        p += qs;
+    }
+}
+template <int R, bool NTM>
+__device__ __forceinline__ void gstore_pts(const c32 (&v)[R], c32 *p, int64_t qs)
+{
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        gstore<NTM>(p, v[r]);
+        p += qs;
+    }
+}
+
 template <int L, int R, int NS, int S, int NL, int NT, bool SRC_G, bool DST_G, bool NTM = false>
 __device__ __forceinline__ void col_stage(c32 *buf, const c32 *gin, c32 *gout, int64_t gs,
                                           bool gv, const c32 *tw, int tid)
@@ -259,12 +288,11 @@ __device__ __forceinline__ void col_stage(c32 *buf, const c32 *gin, c32 *gout, i
     for (int i = 0; i < NB; ++i) {
         const int j = j0 + i * JS;
         if (Q % JS == 0 || j < Q) {
+            if (SRC_G) {
+                gload_pts<R, NTM>(v[i], gin + (int64_t)j * gs, (int64_t)Q * gs, gv);
+            } else {
 #pragma unroll
-            for (int r = 0; r < R; ++r) {
-                if (SRC_G)
-                    v[i][r] = gv ? gload<NTM>(gin + (int64_t)j * gs + (int64_t)(r * Q) * gs) : c32{0.f, 0.f};
-                else
-                    v[i][r] = buf[l + (j + r * Q) * NL];
+                for (int r = 0; r < R; ++r) v[i][r] = buf[l + (j + r * Q) * NL];
             }
         }
     }
@@ -277,17 +305,14 @@ __device__ __forceinline__ void col_stage(c32 *buf, const c32 *gin, c32 *gout, i
             if (NS > 1) {
 #pragma unroll
                 for (int r = 1; r < R; ++r) {
-                    c32 w = tw[r * k * (L / (NS * R))];
+                    c32 w = tw[tw_index<L / (NS * R)>(r, k)];
                     if (S > 0) w = conjg(w);
                     v[i][r] = mul(v[i][r], w);
                 }
             }
             Dft<R, S>::run(v[i]);
             if (DST_G) {
-                if (gv) {
-#pragma unroll
-                    for (int r = 0; r < R; ++r) gstore<NTM>(gout + (int64_t)j * gs + (int64_t)(r * Q) * gs, v[i][r]);
-                }
+                if (gv) gstore_pts<R, NTM>(v[i], gout + (int64_t)j * gs, (int64_t)Q * gs);
             } else {
                 c32 *dst = buf + l + ((j / NS) * NS * R + k) * NL;
 #pragma unroll
@@ -387,7 +412,7 @@ __device__ __forceinline__ void row_stage(c32 *buf, const c32 *gin, c32 *gout,
             if (NS > 1) {
 #pragma unroll
                 for (int r = 1; r < R; ++r) {
-                    c32 w = tw[r * k * (L / (NS * R))];
+                    c32 w = tw[tw_index<L / (NS * R)>(r, k)];
                     if (S > 0) w = conjg(w);
                     v[i][r] = mul(v[i][r], w);
                 }
@@ -493,16 +518,16 @@ __device__ __forceinline__ void col_stage_in(const c32 *buf, const c32 *gin, int
 #pragma unroll
     for (int i = 0; i < NB; ++i) {
         const int j = j0 + i * JS;
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
-            if (Q % JS == 0 || j < Q) {
-                if (SRC_G)
-                    v[i][r] = gv ? gload<NTM>(gin + (int64_t)j * gs + (int64_t)(r * Q) * gs) : c32{0.f, 0.f};
-                else
-                    v[i][r] = buf[l + (j + r * Q) * NL];
+        if (Q % JS == 0 || j < Q) {
+            if (SRC_G) {
+                gload_pts<R, NTM>(v[i], gin + (int64_t)j * gs, (int64_t)Q * gs, gv);
             } else {
-                v[i][r] = c32{0.f, 0.f};
+#pragma unroll
+                for (int r = 0; r < R; ++r) v[i][r] = buf[l + (j + r * Q) * NL];
             }
+        } else {
+#pragma unroll
+            for (int r = 0; r < R; ++r) v[i][r] = c32{0.f, 0.f};
         }
     }
     if (!SRC_G) __syncthreads();
@@ -513,7 +538,7 @@ __device__ __forceinline__ void col_stage_in(const c32 *buf, const c32 *gin, int
         if (NS > 1) {
 #pragma unroll
             for (int r = 1; r < R; ++r) {
-                c32 w = tw[r * k * (L / (NS * R))];
+                c32 w = tw[tw_index<L / (NS * R)>(r, k)];
                 if (S > 0) w = conjg(w);
                 v[i][r] = mul(v[i][r], w);
             }
@@ -541,10 +566,7 @@ __device__ __forceinline__ void col_stage_out(c32 *buf, c32 *gout, int64_t gs, b
         if (Q % JS == 0 || j < Q) {
             const int k = j % NS;
             if (DST_G) {
-                if (gv) {
-#pragma unroll
-                    for (int r = 0; r < R; ++r) gstore<NTM>(gout + (int64_t)j * gs + (int64_t)(r * Q) * gs, v[i][r]);
-                }
+                if (gv) gstore_pts<R, NTM>(v[i], gout + (int64_t)j * gs, (int64_t)Q * gs);
             } else {
                 c32 *dst = buf + l + ((j / NS) * NS * R + k) * NL;
 #pragma unroll

@@ -25,6 +25,7 @@ enum : int {
 struct ModeTables {
     int nxk;               // k-space extent of dimension 0 (Nh or N0)
     int n0;                // real-space N0 (weight rule)
+    int n1;                // N1
     int half;              // 1: r2c half spectrum weights, 0: c2c
     const double *k2[3];   // per-axis k^2 contributions (FP64), NULL if unused
     const int64_t *q[3];   // per-axis integer (nt L / N)^2
@@ -33,8 +34,11 @@ struct ModeTables {
     double qmax;
     double scale_n;        // Poisson: factor 1/N applied with -1/k^2
     uint32_t qz_unit;      // (lcm / N2)^2: q[2][i] = qz_unit * min(i, N2 - i)^2
+    uint32_t qx_unit, qy_unit;  // the same for dimensions 0 and 1
+    int walk1;             // 1: one step of |n_z| never crosses two bin thresholds
     double k2z_unit;       // continuous k^2: (2 pi / (N2 dx))^2, so k2[2][i] =
                            // k2z_unit * min(i, N2 - i)^2; 0: read k2[2]
+    double k2x_unit, k2y_unit;  // the same for dimensions 0 and 1 (when k2z_unit > 0)
 };
 
 struct XArgs {

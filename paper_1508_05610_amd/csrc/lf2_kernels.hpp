@@ -648,7 +648,8 @@ struct XC2CV {
 // on rounding.
 
 // Bin edges (thresh[b], thresh[b + 1]) of bin b = 0..nbins as one 8-byte
-// LDS entry (hi = 2^32 - 1 past the last bin); thresholds are < 2^32.
+// LDS entry; thresholds are < 2^32.  hi = 2^32 - 1 for the last bin (which
+// also holds q = qmax) and past it.
 struct BinEdge {
     uint32_t lo, hi;
 };
@@ -680,7 +681,7 @@ __device__ __forceinline__ void load_edges(const ModeTables &mt, double *hist, B
     for (int i = tid; i <= mt.nbins; i += nt) {
         hist[i] = 0.0;
         edges[i] = BinEdge{(uint32_t)mt.thresh[i],
-                           i < mt.nbins ? (uint32_t)mt.thresh[i + 1] : 0xffffffffu};
+                           i < mt.nbins - 1 ? (uint32_t)mt.thresh[i + 1] : 0xffffffffu};
     }
 }
 
@@ -741,6 +742,19 @@ __device__ __forceinline__ int opaque_tid(int tid)
 // edge table; the tile adds its w|F|^2 sums into them.
 // K2 (EPI): 1 the continuous k^2 of the last axis from |n_z|, 2 its table,
 // 0 either, chosen per call (fewer kernels, more registers).
+// m^2 for 0 <= m < 2^12 (mode indices) with a full-rate 24-bit multiply.
+__device__ __forceinline__ uint32_t sq24(int m) { return __umul24((unsigned)m, (unsigned)m); }
+
+// Element offset of column f of a strided pass: outer group o = f / C,
+// then f - o C within it.  Passes have fewer than 2^31 columns (at most
+// (N0 / 2 + 1) N1 nc of a 2048^3 lattice), so 32-bit division suffices.
+__device__ __forceinline__ int64_t col_base(const SArgs &a, int64_t f)
+{
+    const int fi = (int)f, c = (int)a.ncols_inner;
+    const int o = fi / c;
+    return (int64_t)o * a.outer + (fi - o * c);
+}
+
 template <int L, int S, bool EPI, int NT, bool NTM = false, int K2 = 0>
 struct STile {
     static constexpr int B = s_b(L);
@@ -751,8 +765,70 @@ struct STile {
     {
         load_table((c32 *)(sm + O_TW), a.tw, L, tid, NT);
     }
+    // The fused tile's inputs: the first forward stage's inputs, rows
+    // j + r L/R0 of the thread's column (radix R0), all loads issued before
+    // any of them is used (a column past the end loads column 0 and is
+    // zeroed).
+    static constexpr int R0 = nstages(L) == 0 ? 1 : radix_sel(L, 0, false);
+    static constexpr int NB0 = col_nb(L, R0, B, NT);
+    struct In {
+        c32 v[NB0][R0];
+    };
+    static __device__ __forceinline__ void load_in(const SArgs &a, int64_t t, int tid, In &in)
+    {
+        constexpr int Q0 = L / R0;
+        constexpr int JS = NT / B;
+        const int col = tid % B;
+        const int64_t f = t * B + col;
+        const bool valid = f < a.ncols;
+        // a column past the end reads column 0 (in bounds) and keeps zeros
+        const int64_t base = valid ? col_base(a, f) : 0;
+        const c32 *gin = (const c32 *)a.in + base;
+        const int j0 = tid / B;
+#pragma unroll
+        for (int i = 0; i < NB0; ++i) {
+            const int j = j0 + i * JS;
+            if (Q0 % JS == 0 || j < Q0) {
+                gload_pts<R0, NTM>(in.v[i], gin + (int64_t)j * a.stride, (int64_t)Q0 * a.stride,
+                                   true);
+#pragma unroll
+                for (int r = 0; r < R0; ++r)
+                    if (!valid) in.v[i][r] = c32{0.f, 0.f};
+            } else {
+#pragma unroll
+                for (int r = 0; r < R0; ++r) in.v[i][r] = c32{0.f, 0.f};
+            }
+        }
+    }
+
     static __device__ void tile(const SArgs &a, int64_t t, char *sm, int tid, double *hist,
                                 const BinEdge *edges)
+    {
+        if constexpr (EPI) {
+            In in;
+            load_in(a, t, tid, in);
+            tile_in(a, t, sm, tid, hist, edges, in);
+            return;
+        }
+        c32 *buf = (c32 *)(sm + O_BUF);
+        const c32 *tw = (const c32 *)(sm + O_TW);
+        const int col = tid % B;
+        const int rg = tid / B;
+        const bool store = (a.epi & EPI_STORE) != 0;
+        const int64_t f = t * B + col;
+        const bool valid = f < a.ncols;
+        const int64_t base = valid ? col_base(a, f) : 0;
+        const c32 *gin = (const c32 *)a.in + base;
+        c32 *gout = (c32 *)a.out + base;
+        // global -> registers -> stages -> registers -> global
+        col_fft<L, S, B, NT, true, true, 0, 1, NTM>(buf, gin, gout, a.stride, valid && store, tw,
+                                                     tid);
+        __syncthreads();
+    }
+
+    // The fused tile from its loaded inputs (load_in of the same t).
+    static __device__ __forceinline__ void tile_in(const SArgs &a, int64_t t, char *sm, int tid,
+                                                   double *hist, const BinEdge *edges, In &in)
     {
         c32 *buf = (c32 *)(sm + O_BUF);
         const c32 *tw = (const c32 *)(sm + O_TW);
@@ -761,20 +837,9 @@ struct STile {
         const bool store = (a.epi & EPI_STORE) != 0;
         const int64_t f = t * B + col;
         const bool valid = f < a.ncols;
-        int64_t base = 0;
-        if (valid) {
-            const int64_t o = f / a.ncols_inner;
-            base = o * a.outer + (f - o * a.ncols_inner);
-        }
-        const c32 *gin = (const c32 *)a.in + base;
+        const int64_t base = valid ? col_base(a, f) : 0;
         c32 *gout = (c32 *)a.out + base;
-        if constexpr (!EPI) {
-            // global -> registers -> stages -> registers -> global
-            col_fft<L, S, B, NT, true, true, 0, 1, NTM>(buf, gin, gout, a.stride, valid && store,
-                                                         tw, tid);
-        } else {
-            epilogue(a, sm, buf, tw, tid, col, rg, f, valid, store, gin, gout, hist, edges);
-        }
+        epilogue(a, buf, tw, tid, col, rg, f, valid, store, gout, hist, edges, in);
         __syncthreads();
     }
 
@@ -787,10 +852,10 @@ struct STile {
     // neighbouring modes share a bin): for them the modes are also written
     // to LDS in natural order and thread (col, rg) walks kz in
     // [rg EP, rg EP + EP).
-    static __device__ void epilogue(const SArgs &a, char *sm, c32 *buf, const c32 *tw, int tid,
-                                    int col, int rg, int64_t f, bool valid, bool store,
-                                    const c32 *gin, c32 *gout, double *hist,
-                                    const BinEdge *edges)
+    static __device__ __forceinline__ void epilogue(const SArgs &a, c32 *buf, const c32 *tw,
+                                                    int tid, int col, int rg, int64_t f,
+                                                    bool valid, bool store, c32 *gout,
+                                                    double *hist, const BinEdge *edges, In &in)
     {
         constexpr int NST = nstages(L);
         constexpr int RL = NST == 0 ? 1 : radix_at(L, NST - 1);
@@ -798,33 +863,53 @@ struct STile {
         constexpr int JS = NT / B;
         constexpr int NB = col_nb(L, RL, B, NT);
         const int j0 = tid / B;
+        // first forward stage (no twiddles) on the loaded inputs
+#pragma unroll
+        for (int i = 0; i < NB0; ++i) Dft<R0, S>::run(in.v[i]);
         c32 v[NB][RL];
         if constexpr (NST <= 1) {
-            col_stage_in<L, RL, 1, S, B, NT, true, NTM>(buf, gin, a.stride, valid, tw, tid, v);
+            static_assert(NB0 == NB && R0 == RL, "one stage: its inputs are its butterflies");
+#pragma unroll
+            for (int i = 0; i < NB; ++i)
+#pragma unroll
+                for (int r = 0; r < RL; ++r) v[i][r] = in.v[i][r];
         } else {
-            col_fft<L, S, B, NT, true, false, 0, 1, NTM, false, true>(buf, gin, nullptr, a.stride,
-                                                                      valid, tw, tid);
+            col_stage_out<L, R0, 1, B, NT, false>(buf, nullptr, 0, false, tid, in.v);
+            col_fft<L, S, B, NT, false, false, 1, R0, NTM, false, true>(buf, nullptr, nullptr, 0,
+                                                                      false, tw, tid);
             col_stage_in<L, RL, QL, S, B, NT, false>(buf, nullptr, 0, false, tw, tid, v);
         }
-        const int kx = valid ? (int)(f % a.mt.nxk) : 0;
-        const int ky = valid ? (int)(f / a.mt.nxk) : 0;
+        // column f = ky nxk + kx of the (kx, ky) plane (fewer than 2^31 columns)
+        const int kx = valid ? (int)f % a.mt.nxk : 0;
+        const int ky = valid ? (int)f / a.mt.nxk : 0;
         const bool corner = kx == 0 && ky == 0;
+        // the column's |n_x|, |n_y| (the r2c half spectrum holds kx <= N0 / 2)
+        const int mx = 2 * kx <= a.mt.n0 ? kx : a.mt.n0 - kx;
+        const int my = 2 * ky <= a.mt.n1 ? ky : a.mt.n1 - ky;
         // this wave's histogram
         double *wh = hist + (a.hcopies > 1 ? (tid >> 6) * (a.mt.nbins + 1) : 0);
+        // q_x + q_y of the column (exact integers below 2^32)
+        const uint32_t qxy = a.mt.qx_unit * sq24(mx) + a.mt.qy_unit * sq24(my);
         if (a.epi & EPI_PK) {
             col_stage_out<L, RL, QL, B, NT, false>(buf, nullptr, 0, false, tid, v);
-            bin_walk(a, buf, col, rg, kx, ky, valid, wh, edges);
+            bin_walk(a, buf, col, rg, kx, corner, qxy, valid, wh, edges);
         }
         if (a.epi & EPI_POISSON) {
-            const double k2xy = valid ? a.mt.k2[0][kx] + a.mt.k2[1][ky] : 1.0;
-            if (K2 == 1 || (K2 == 0 && a.mt.k2z_unit > 0.0))
-                scale_modes<true>(a, v, j0, k2xy, corner);   // continuous k^2 from |n_z|
-            else
-                scale_modes<false>(a, v, j0, k2xy, corner);  // the last axis' k^2 table
+            if (K2 == 1 || (K2 == 0 && a.mt.k2z_unit > 0.0)) {
+                // continuous k^2 from |n_x|, |n_y|, |n_z|
+                const double k2xy = valid ? fma(a.mt.k2x_unit, (double)sq24(mx),
+                                                a.mt.k2y_unit * (double)sq24(my))
+                                          : 1.0;
+                scale_modes<true>(a, v, j0, k2xy, corner);
+            } else {
+                // the tables
+                const double k2xy = valid ? a.mt.k2[0][kx] + a.mt.k2[1][ky] : 1.0;
+                scale_modes<false>(a, v, j0, k2xy, corner);
+            }
         }
         if (a.epi & EPI_PK_AFTER) {
             col_stage_out<L, RL, QL, B, NT, false>(buf, nullptr, 0, false, tid, v);
-            bin_walk(a, buf, col, rg, kx, ky, valid, wh, edges);
+            bin_walk(a, buf, col, rg, kx, corner, qxy, valid, wh, edges);
         }
         if constexpr (S < 0) {
             if (a.epi & EPI_POISSON) {
@@ -863,7 +948,7 @@ struct STile {
                 const int kz = j + r * QL;
                 if (QL % JS == 0 || j < QL) {
                     const int m = 2 * kz < L ? kz : L - kz;
-                    const double k2z = CONT ? a.mt.k2z_unit * (double)(m * m) : a.mt.k2[2][kz];
+                    const double k2z = CONT ? a.mt.k2z_unit * (double)sq24(m) : a.mt.k2[2][kz];
                     const double sc =
                         (corner && kz == 0) ? 0.0 : -a.mt.scale_n * rcp_f64(k2xy + k2z);
                     v[i][r] = c32{(float)((double)v[i][r].x * sc), (float)((double)v[i][r].y * sc)};
@@ -872,69 +957,74 @@ struct STile {
         }
     }
 
-    // P(k) partial sums of the modes in LDS (natural order): thread (col, rg)
-    // walks its run of kz, computes each mode's exact bin and adds w |F|^2
-    // into `hist` -- its wave's own LDS histogram, or the block's one --
-    // when the bin changes.  A wave's additions come in program order, so
+    // P(k) partial sums of the modes in LDS (natural order).  The modes kz
+    // and L - kz have the same m = |n_z|, hence the same q and bin, so
+    // thread (col, rg) walks m upward over its run [rg EH, rg EH + EH) of
+    // 0 .. L/2 and takes both modes of each m (one at m = 0, and at m = L/2
+    // for even L).  Along the run q = q_xy + m^2 q_u grows by integer
+    // differences, and the bin changes where q reaches the current bin's
+    // upper edge: to the next bin when one step of m never crosses two
+    // thresholds (mt.walk1, checked when the thresholds are made), else to
+    // the exact bin of q.  w |F|^2 sums go to `hist` -- the wave's own LDS
+    // histogram, or the block's one -- at each change, in program order, so
     // with one histogram per wave the sums do not depend on scheduling.
     // Ends at a barrier, so LDS may be rewritten afterwards.
+    static constexpr int MH = L / 2;                       // largest m
+    static constexpr int EH = (MH + 1 + RPT - 1) / RPT;    // m values per row group
     static __device__ void bin_walk(const SArgs &a, const c32 *buf, int col, int rg, int kx,
-                                    int ky, bool valid, double *hist, const BinEdge *edges)
+                                    bool corner, uint32_t qxy, bool valid, double *hist,
+                                    const BinEdge *edges)
     {
-        constexpr int EP = (L + RPT - 1) / RPT;
         const int nb = a.mt.nbins;
         const float cq = (float)((double)nb * nb / a.mt.qmax);
         // the half-spectrum weight is the same for the whole column
         const double wgt = (a.mt.half && !(kx == 0 || 2 * kx == a.mt.n0)) ? 2.0 : 1.0;
-        // q < 2^32 (checked at plan time); the last axis' part from |n_z|
-        const uint32_t qxy = valid ? (uint32_t)(a.mt.q[0][kx] + a.mt.q[1][ky]) : 0u;
         const uint32_t qu = a.mt.qz_unit;
-        auto qof = [&](int k) {
-            const uint32_t m = (uint32_t)(2 * k < L ? k : L - k);
-            return qxy + m * m * qu;
-        };
-        const bool corner = kx == 0 && ky == 0;
-        // every row group's run has EP modes when RPT EP = L; otherwise the
-        // last runs are shorter or empty (n <= 0)
-        constexpr bool EXACT = RPT * EP == L;
-        const int n = EXACT ? EP : (L - rg * EP < EP ? L - rg * EP : EP);
-        int cur = -1;
-        double acc = 0.0;
+        const bool walk1 = a.mt.walk1 != 0;
+        const int m0 = rg * EH;
+        const int n = MH + 1 - m0 < EH ? MH + 1 - m0 : EH;  // may be <= 0
         if (valid && n > 0) {
-            // selects, not branches, for the zero mode and the bin; the next
-            // mode's value and bin-edge LDS reads are issued before this
-            // mode's work
-            int kz = rg * EP;
-            c32 v = buf[kz * B + col];
-            uint32_t q = qof(kz);
-            int be = bin_est(q, cq);
-            BinEdge ed = edges[be];
-#pragma unroll 4
-            for (int e = 0; e < EP; ++e) {
-                if (!EXACT && e >= n) break;
-                const int kzn = kz + 1 < L ? kz + 1 : kz;  // in bounds; unused past the run
-                const c32 vn = buf[kzn * B + col];
-                const uint32_t qn = qof(kzn);
-                const int ben = bin_est(qn, cq);
-                const BinEdge edn = edges[ben];
-                const int bq = bin_fix(q, be, ed, nb);
-                // slot nbins: the zero mode (kept for the Parseval sum)
-                const int b = (corner && kz == 0) ? nb : bq;
-                const double p = (double)v.x * v.x + (double)v.y * v.y;
-                v = vn;
-                q = qn;
-                be = ben;
-                ed = edn;
-                kz = kzn;
-                if (b != cur) {
-                    if (cur >= 0) atomicAdd(&hist[cur], wgt * acc);
-                    cur = b;
-                    acc = 0.0;
-                }
-                acc += p;
+            // q at m0 and its first difference (m0 + 1)^2 - m0^2 = 2 m0 + 1
+            uint32_t q = qxy + sq24(m0) * qu;
+            uint32_t dq = (uint32_t)(2 * m0 + 1) * qu;
+            const uint32_t ddq = 2u * qu;
+            // slot nbins: the zero mode (kept for the Parseval sum); q = 0
+            // there, and the next mode's bin is then found from scratch
+            int b;
+            uint32_t hi;
+            if (corner && m0 == 0) {
+                b = nb;
+                hi = 1u;
+            } else {
+                b = bin_edge(q, nb, cq, edges);
+                hi = edges[b].hi;
             }
+            double acc = 0.0;
+#pragma unroll 4
+            for (int e = 0; e < EH; ++e) {
+                if (EH * RPT != MH + 1 && e >= n) break;
+                const int m = m0 + e;
+                const c32 u = buf[m * B + col];
+                // the partner mode L - m (none for m = 0, the same mode for 2 m = L)
+                const bool two = m != 0 && 2 * m != L;
+                const c32 w = buf[(two ? L - m : m) * B + col];
+                if (q >= hi) {
+                    atomicAdd(&hist[b], wgt * acc);
+                    acc = 0.0;
+                    if (walk1 && b < nb)
+                        ++b;
+                    else
+                        b = bin_edge(q, nb, cq, edges);
+                    hi = edges[b].hi;
+                }
+                double pw = (double)u.x * u.x + (double)u.y * u.y;
+                if (two) pw += (double)w.x * w.x + (double)w.y * w.y;
+                acc += pw;
+                q += dq;
+                dq += ddq;
+            }
+            atomicAdd(&hist[b], wgt * acc);
         }
-        if (cur >= 0) atomicAdd(&hist[cur], wgt * acc);
         __syncthreads();
     }
 };
@@ -961,11 +1051,7 @@ struct STileW {
         const int col = tid % B;
         const int64_t f = t * B + col;
         const bool valid = f < a.ncols;
-        int64_t base = 0;
-        if (valid) {
-            const int64_t o = f / a.ncols_inner;
-            base = o * a.outer + (f - o * a.ncols_inner);
-        }
+        const int64_t base = valid ? col_base(a, f) : 0;
         col_fft<L, S, B, NT, true, true, 0, 1, NTM>(buf, (const c32 *)a.in + base, (c32 *)a.out + base,
                                          a.stride, valid && (a.epi & EPI_STORE) != 0, tw, tid);
         __syncthreads();
@@ -1106,9 +1192,12 @@ __global__ __launch_bounds__(kSThreads)
     // while all XCDs stream from nearby addresses.
     const int64_t K = a.xcd_chunk;
     const int64_t span = (ntiles + 8 * K - 1) / (8 * K) * (8 * K);
-    for (int64_t vb = blockIdx.x; vb < span; vb += gridDim.x) {
+    auto tile_of = [&](int64_t vb) {
         const int64_t lb = vb / 8;
-        const int64_t t = ((lb / K) * 8 + (vb % 8)) * K + lb % K;
+        return ((lb / K) * 8 + (vb % 8)) * K + lb % K;
+    };
+    for (int64_t vb = blockIdx.x; vb < span; vb += gridDim.x) {
+        const int64_t t = tile_of(vb);
         if (t >= ntiles) continue;  // uniform over the block
         T::tile(a, t, sm, opaque_tid<EPI>(tid), hist, edges);
     }

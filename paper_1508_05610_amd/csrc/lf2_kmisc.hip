@@ -109,7 +109,7 @@ __global__ __launch_bounds__(256) void k_shell_partials(ModeTables mt, int n1, i
         hk[i] = 0.0;
     }
     for (int i = threadIdx.x; i <= nb; i += NT)
-        edges[i] = BinEdge{(uint32_t)mt.thresh[i], i < nb ? (uint32_t)mt.thresh[i + 1] : 0xffffffffu};
+        edges[i] = BinEdge{(uint32_t)mt.thresh[i], i < nb - 1 ? (uint32_t)mt.thresh[i + 1] : 0xffffffffu};
     __syncthreads();
     const float cq = (float)((double)nb * nb / mt.qmax);
     const uint32_t qu = mt.qz_unit;

@@ -20,7 +20,16 @@ struct ShellEntry {
     int64_t *thresh;  // nbins + 1
     double *count;    // nbins
     double *sumk;     // nbins (sum w sqrt(q))
+    int walk1;        // ModeTables::walk1 for these thresholds
 };
+
+// The binning fields of the mode tables from a shell table.
+inline void use_shell(lf2::ModeTables &mt, const ShellEntry &sh)
+{
+    mt.thresh = sh.thresh;
+    mt.nbins = sh.nbins;
+    mt.walk1 = sh.walk1;
+}
 
 struct lf2_plan_s {
     int device = 0;
@@ -87,7 +96,9 @@ size_t spectrum_bytes(const lf2_plan_s *p);
 ModeTables base_tables(const lf2_plan_s *p);
 // (2 pi / (N2 dx))^2 for the continuous k^2 (the fused pass then computes
 // the last axis' k^2 from |n_z|), 0 for the discrete one.
-double k2z_unit(const lf2_plan_s *p, double dx, int discrete);
+// Continuous k^2 units (2 pi / (N_i dx))^2 of the three dimensions (zero for
+// the discrete k^2, which the kernels read from the tables).
+void set_k2_units(ModeTables &mt, const lf2_plan_s *p, double dx, int discrete);
 // Tables of a plan, built on first use (lookup_only: never build; a
 // missing table is LF2_ERR_NOT_READY).
 lf2_status get_k2(lf2_plan p, double dx, int discrete, hipStream_t s, const double *out[3],
