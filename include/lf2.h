@@ -330,12 +330,17 @@ lf2_status lf2_batch_destroy(lf2_batch b);
  * lattices of mixed sizes (continuous batching).  A scheduler thread admits
  * queued requests in launch units while a slot is free: the request at the
  * head of the queue, joined by the queued requests with the same lattice,
- * lattice spacing, k^2 kind and bin count (up to 16, lattices whose lines
- * have grouped kernels) -- those run as ONE grouped solve, a launch per pass
- * over all of them.  A unit takes one slot; every request in it is charged
+ * lattice spacing, k^2 kind and bin count (up to 16 requests and 2^26
+ * lattice points, lattices of at most 2^24 points whose lines have grouped
+ * kernels) -- those run as ONE grouped solve, a launch per pass over all of
+ * them; larger lattices run alone.  A unit takes one slot; every request in it is charged
  * its footprint (rho + phi + workspace) against the HBM budget, and the
- * idle pooled workspace counts against the budget too (idle buffers are
- * freed when a request needs the room).  Each unit is launched at once on
+ * idle pooled workspace counts against the budget too.  A request reuses an
+ * idle buffer that fits its workspace when there is one (reserved at
+ * admission); idle buffers are freed only when a request needs the room.
+ * Workspaces come from a stream-ordered memory pool of the server's own
+ * (hipMallocFromPoolAsync / hipFreeAsync), so a free does not wait for the
+ * device.  Each unit is launched at once on
  * one of `nstreams` streams, so requests that arrive while others run join
  * the device work as capacity frees up.  Plans (twiddles, wavevector and
  * shell tables) stay resident in a cache keyed by lattice.  A completion
@@ -376,6 +381,7 @@ typedef struct {
     int64_t groups, grouped_requests;     /* grouped solves launched, requests in them */
     size_t pooled_idle_bytes;             /* idle pooled workspace (counts against the budget) */
     size_t peak_bytes_in_use;             /* largest in-flight + idle pooled bytes seen */
+    int64_t workspace_allocs, workspace_frees;  /* pooled workspace buffers made and freed */
 } lf2_server_stats;
 
 /* Create a GPU server on the current device.  hbm_budget_bytes bounds the

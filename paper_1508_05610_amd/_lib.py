@@ -66,7 +66,8 @@ class lf2_server_stats(ctypes.Structure):
                 ("peak_bytes_in_flight", ctypes.c_size_t), ("plans_cached", ctypes.c_int64),
                 ("plan_hits", ctypes.c_int64), ("plan_misses", ctypes.c_int64),
                 ("groups", ctypes.c_int64), ("grouped_requests", ctypes.c_int64),
-                ("pooled_idle_bytes", ctypes.c_size_t), ("peak_bytes_in_use", ctypes.c_size_t)]
+                ("pooled_idle_bytes", ctypes.c_size_t), ("peak_bytes_in_use", ctypes.c_size_t),
+                ("workspace_allocs", ctypes.c_int64), ("workspace_frees", ctypes.c_int64)]
 
 
 _lib = None

@@ -56,6 +56,12 @@ struct Group {
 };
 
 constexpr int kMaxGroup = 16;  // requests in one grouped solve
+// Grouped solves pay where launches and tails dominate (small lattices); a
+// lattice above kGroupFieldPoints runs alone on the tuned per-lattice path,
+// which is faster there, and a group holds at most kGroupPoints lattice
+// points, so that its requests do not wait long for each other.
+constexpr int64_t kGroupFieldPoints = (int64_t)1 << 24;  // 256^3
+constexpr int64_t kGroupPoints = (int64_t)1 << 26;
 
 struct Req {
     uint64_t ticket = 0;
@@ -171,6 +177,12 @@ struct lf2_server_s {
     std::multimap<size_t, char *> ws_free;
     std::map<char *, size_t> ws_size;
     size_t ws_idle = 0;
+    // workspaces come from a memory pool of the server's own, allocated and
+    // freed in stream order, so that freeing an idle buffer does not wait
+    // for the whole device (hipFree would); plain hipMalloc where the device
+    // has no memory pools
+    hipMemPool_t mpool = nullptr;
+    int64_t n_ws_alloc = 0, n_ws_free = 0;
     size_t peak_use = 0;  // largest in-flight + idle bytes seen
     std::vector<hipEvent_t> ev_free, ev_all;
     std::multimap<size_t, std::pair<char *, char *>> stage_free;  // pinned host, device
@@ -224,21 +236,29 @@ void put_plan(lf2_server s, const LatKey &key)
     if (it != s->plans.end() && it->second.refs > 0) it->second.refs -= 1;
 }
 
-char *ws_alloc(lf2_server s, size_t bytes)
+// A new workspace buffer, allocated in order on the stream that will use it.
+char *ws_alloc(lf2_server s, size_t bytes, hipStream_t strm)
 {
+    s->n_ws_alloc += 1;
     if (s->fake) return (char *)malloc(1);  // a token: the fake executor runs no kernels
     void *p = nullptr;
-    if (hipMalloc(&p, bytes) != hipSuccess) {
+    const hipError_t e = s->mpool ? hipMallocFromPoolAsync(&p, bytes, s->mpool, strm)
+                                  : hipMalloc(&p, bytes);
+    if (e != hipSuccess) {
         (void)hipGetLastError();
         return nullptr;
     }
     return (char *)p;
 }
 
+// Free an idle buffer (its last use has completed).
 void ws_release(lf2_server s, char *p)
 {
+    s->n_ws_free += 1;
     if (s->fake)
         free(p);
+    else if (s->mpool)
+        (void)hipFreeAsync(p, s->streams[0]);
     else
         (void)hipFree(p);
 }
@@ -267,7 +287,7 @@ void ws_trim_locked(lf2_server s, size_t inflight, size_t need, size_t keep)
 // A workspace of at least `bytes`: an idle buffer of at most twice that
 // size, else a new one (after freeing idle buffers that do not fit, if the
 // allocation fails).  *real: its size.
-char *ws_get(lf2_server s, size_t bytes, size_t *real)
+char *ws_get(lf2_server s, size_t bytes, size_t *real, hipStream_t strm)
 {
     std::lock_guard<std::mutex> lk(s->pmu);
     auto it = s->ws_free.lower_bound(bytes);
@@ -278,7 +298,7 @@ char *ws_get(lf2_server s, size_t bytes, size_t *real)
         s->ws_free.erase(it);
         return p;
     }
-    char *p = ws_alloc(s, bytes);
+    char *p = ws_alloc(s, bytes, strm);
     if (!p) {
         for (auto &kv : s->ws_free) {
             ws_release(s, kv.second);
@@ -286,7 +306,7 @@ char *ws_get(lf2_server s, size_t bytes, size_t *real)
         }
         s->ws_free.clear();
         s->ws_idle = 0;
-        p = ws_alloc(s, bytes);
+        p = ws_alloc(s, bytes, strm);
         if (!p) return nullptr;
     }
     s->ws_size[p] = bytes;
@@ -384,10 +404,11 @@ lf2_status request_tables(lf2_server s, lf2_plan plan, const lf2_request &r, hip
 
 // Take the request's workspace and settle its budget charge (server lock
 // not held).
-bool take_ws(lf2_server s, Req *q)
+bool take_ws(lf2_server s, Req *q, hipStream_t strm)
 {
+    if (q->ws) return true;  // an idle buffer reserved at admission
     size_t real = 0;
-    q->ws = ws_get(s, q->ws_bytes, &real);
+    q->ws = ws_get(s, q->ws_bytes, &real, strm);
     if (!q->ws) return false;
     q->ws_real = real;
     std::lock_guard<std::mutex> lk(s->mu);
@@ -421,7 +442,7 @@ void launch_unit(lf2_server s, std::vector<Req *> &unit)
     }
     if (s->fake) {
         for (Req *q : unit) {
-            if (st == LF2_OK && !take_ws(s, q)) st = LF2_ERR_OUT_OF_MEMORY;
+            if (st == LF2_OK && !take_ws(s, q, nullptr)) st = LF2_ERR_OUT_OF_MEMORY;
             q->st = st ? st : (q->ticket == s->fail_ticket ? LF2_ERR_DEVICE : LF2_OK);
         }
         if (unit.size() > 1) {
@@ -434,9 +455,9 @@ void launch_unit(lf2_server s, std::vector<Req *> &unit)
         }
         return;
     }
-    for (Req *q : unit)
-        if (st == LF2_OK && !take_ws(s, q)) st = fail(LF2_ERR_OUT_OF_MEMORY, "workspace");
     hipStream_t strm = s->streams[s->rr.fetch_add(1) % (unsigned)s->nstreams];
+    for (Req *q : unit)
+        if (st == LF2_OK && !take_ws(s, q, strm)) st = fail(LF2_ERR_OUT_OF_MEMORY, "workspace");
     PoissonTables tabs{};
     if (st == LF2_OK) st = request_tables(s, plan, q0->r, strm, &tabs);
     const int R = (int)unit.size();
@@ -509,9 +530,15 @@ bool release(lf2_server s, Req *q)
     return unit_done;
 }
 
+int64_t points_of(const Req *q)
+{
+    return q->r.lat.size[0] * q->r.lat.size[1] * q->r.lat.size[2];
+}
+
 // Whether requests of this key can run as one grouped solve.
 bool groupable(const Req *q)
 {
+    if (points_of(q) > kGroupFieldPoints) return false;
     lf2_plan_s tmp;
     tmp.kind = LF2_R2C;
     tmp.nc = 1;
@@ -521,25 +548,52 @@ bool groupable(const Req *q)
     return group_supported(&tmp) && q->r.nbins <= kBatchMaxBins;
 }
 
-// Budget check of one request (idle pooled workspace is freed to make room);
-// charges it when it fits.  Server lock held.
+// Budget check of one request; charges it when it fits.  An idle buffer
+// that fits its workspace (at most twice the size) is reserved for it at
+// once: it moves from the pool to the request, so the bytes in use grow by
+// the request's rho and phi only (other idle buffers are freed if that makes
+// room).  Otherwise the request needs a new workspace, and idle buffers are
+// freed to make room for it.  Whenever the in-flight bytes leave room for
+// the request's footprint, one of the two succeeds.  Server lock held.
 bool fits_budget_locked(lf2_server s, Req *q)
 {
-    if (s->bytes_inflight + q->bytes > s->budget) return false;
     std::lock_guard<std::mutex> pk(s->pmu);
+    const size_t own = q->bytes - q->ws_bytes;  // rho + phi
+    auto it = s->ws_free.lower_bound(q->ws_bytes);
+    if (it != s->ws_free.end() && it->first <= 2 * q->ws_bytes) {
+        const size_t sz = it->first;
+        char *buf = it->second;
+        s->ws_free.erase(it);
+        s->ws_idle -= sz;
+        if (s->bytes_inflight + s->ws_idle + own + sz > s->budget)
+            ws_trim_locked(s, s->bytes_inflight, own + sz, q->ws_bytes);
+        if (s->bytes_inflight + s->ws_idle + own + sz <= s->budget) {
+            q->ws = buf;
+            q->ws_real = sz;
+            q->charge = own + sz;
+            s->bytes_inflight += q->charge;
+            s->peak_use = std::max(s->peak_use, s->bytes_inflight + s->ws_idle);
+            s->peak = std::max(s->peak, s->bytes_inflight);
+            return true;
+        }
+        s->ws_free.emplace(sz, buf);  // not this way: back to the pool
+        s->ws_idle += sz;
+    }
+    if (s->bytes_inflight + q->bytes > s->budget) return false;
     if (s->bytes_inflight + s->ws_idle + q->bytes > s->budget)
         ws_trim_locked(s, s->bytes_inflight, q->bytes, q->ws_bytes);
     if (s->bytes_inflight + s->ws_idle + q->bytes > s->budget) return false;
-    s->peak_use = std::max(s->peak_use, s->bytes_inflight + s->ws_idle + q->bytes);
     s->bytes_inflight += q->bytes;
     q->charge = q->bytes;
+    s->peak_use = std::max(s->peak_use, s->bytes_inflight + s->ws_idle);
     s->peak = std::max(s->peak, s->bytes_inflight);
     return true;
 }
 
 // Admit launch units from the head of the queue while a slot is free: the
 // head request, joined by later queued requests of the same lattice, dx,
-// k^2 kind and bin count (at most kMaxGroup in all) while the budget holds
+// k^2 kind and bin count (at most kMaxGroup in all and kGroupPoints lattice
+// points, lattices up to kGroupFieldPoints) while the budget holds
 // them -- those run as one grouped solve.  A unit takes one slot.  FIFO for
 // the heads: a head that does not fit the budget holds back the ones behind
 // it.  Server lock held.
@@ -553,9 +607,13 @@ void admit_locked(lf2_server s, std::vector<std::vector<Req *>> &adm)
         std::vector<Req *> unit{q};
         if (groupable(q)) {
             const GroupKey k = group_key(q);
-            for (auto it = s->queue.begin(); it != s->queue.end() && (int)unit.size() < kMaxGroup;) {
+            const int64_t pts = points_of(q);
+            int64_t total = pts;
+            for (auto it = s->queue.begin(); it != s->queue.end() && (int)unit.size() < kMaxGroup &&
+                                              total + pts <= kGroupPoints;) {
                 if (group_key(*it) == k && fits_budget_locked(s, *it)) {
                     unit.push_back(*it);
+                    total += pts;
                     it = s->queue.erase(it);
                 } else {
                     ++it;
@@ -707,10 +765,24 @@ lf2_status lf2_server_create(lf2_server *out, size_t hbm_budget_bytes, int32_t m
         delete s;
         return fail(LF2_ERR_DEVICE, "hipGetDevice");
     }
+    int pools = 0;
+    if (hipDeviceGetAttribute(&pools, hipDeviceAttributeMemoryPoolsSupported, s->device) ==
+            hipSuccess &&
+        pools) {
+        hipMemPoolProps props{};
+        props.allocType = hipMemAllocationTypePinned;
+        props.location.type = hipMemLocationTypeDevice;
+        props.location.id = s->device;
+        if (hipMemPoolCreate(&s->mpool, &props) != hipSuccess) {
+            (void)hipGetLastError();
+            s->mpool = nullptr;
+        }
+    }
     for (int i = 0; i < nstreams; ++i) {
         hipStream_t st = nullptr;
         if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) {
             for (hipStream_t x : s->streams) (void)hipStreamDestroy(x);
+            if (s->mpool) (void)hipMemPoolDestroy(s->mpool);
             delete s;
             return fail(LF2_ERR_DEVICE, "stream creation");
         }
@@ -719,6 +791,7 @@ lf2_status lf2_server_create(lf2_server *out, size_t hbm_budget_bytes, int32_t m
     lf2_status st = server_start(s);
     if (st) {
         for (hipStream_t x : s->streams) (void)hipStreamDestroy(x);
+        if (s->mpool) (void)hipMemPoolDestroy(s->mpool);
         delete s;
         return st;
     }
@@ -783,7 +856,7 @@ lf2_status lf2_server_prepare(lf2_server s, int32_t n, const lf2_lattice *lats, 
             if (s->bytes_inflight + s->ws_idle + wb > s->budget) continue;
         }
         size_t real = 0;
-        char *w = ws_get(s, wb, &real);
+        char *w = ws_get(s, wb, &real, s->fake ? nullptr : s->streams[0]);
         if (!w) return fail(LF2_ERR_OUT_OF_MEMORY, "workspace");
         ws_put(s, w);
     }
@@ -884,6 +957,8 @@ lf2_status lf2_server_get_stats(lf2_server s, lf2_server_stats *st)
         st->plan_misses = s->plan_misses;
         st->pooled_idle_bytes = s->ws_idle;
         st->peak_bytes_in_use = s->peak_use;
+        st->workspace_allocs = s->n_ws_alloc;
+        st->workspace_frees = s->n_ws_free;
     }
     return LF2_OK;
 }
@@ -915,6 +990,7 @@ lf2_status lf2_server_destroy(lf2_server s)
             (void)hipFree(hd.second);
         }
         for (hipStream_t x : s->streams) (void)hipStreamDestroy(x);
+        if (s->mpool) (void)hipMemPoolDestroy(s->mpool);
     }
     delete s;
     return LF2_OK;

@@ -290,3 +290,21 @@ def test_requests_queued_together_are_grouped():
     assert len(ta) == 1
     assert res[first][3] <= min(ta) + 1e-6
     assert res[b][2] >= res[a[0]][3] - 1e-6
+
+
+def test_group_caps_by_lattice_points():
+    """Grouping stops at 2^26 lattice points per grouped solve (four 256^3
+    requests), and lattices above 2^24 points (384^3) always run alone."""
+    s = lf2.Server(1 << 40, max_slots=1, max_queue=64, fake=True, delay_us=20000)
+    first = s.submit_raw((32, 32, 32), RHO, PHI)[1]          # takes the only slot
+    big = [s.submit_raw((256, 256, 256), RHO, PHI, nbins=8)[1] for _ in range(6)]
+    huge = [s.submit_raw((384, 384, 384), RHO, PHI, nbins=8)[1] for _ in range(3)]
+    res = {t: s.poll(t) for t in [first] + big + huge}
+    st = s.stats()
+    s.close()
+    assert all(r[0] == lf2.LF2_OK for r in res.values())
+    assert st["groups"] == 2 and st["grouped_requests"] == 6
+    admits = sorted({res[t][2] for t in big})
+    assert len(admits) == 2
+    assert sum(res[t][2] == admits[0] for t in big) == 4
+    assert len({res[t][2] for t in huge}) == 3
