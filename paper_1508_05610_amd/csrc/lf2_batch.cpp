@@ -375,9 +375,9 @@ lf2_status lf2_batch_plan(lf2_batch *out, int32_t nfields, const lf2_lattice *la
                 b->local = 1;
             }
         }
-        // tiles per item: about eight items per block, so that each item's
+        // tiles per item: about fifteen items per block, so that each item's
         // wait and publication (and the call into its tile code) are spread
-        // over several tiles
+        // over several tiles while the last items of a pass stay short
         int64_t ntiles_all = 0;
         for (int f = 0; f < nfields; ++f)
             for (int p = 0; p < BP_COUNT; ++p) ntiles_all += tiles[f][p];
@@ -385,7 +385,7 @@ lf2_status lf2_batch_plan(lf2_batch *out, int32_t nfields, const lf2_lattice *la
         if (hipDeviceGetAttribute(&ncu0, hipDeviceAttributeMultiprocessorCount, b->device) != hipSuccess ||
             ncu0 < 1)
             ncu0 = 256;
-        int per_item = (int)(ntiles_all / (2 * ncu0 * 8));
+        int per_item = (int)(ntiles_all / (2 * ncu0 * 15));
         if (const char *ev = getenv("LF2_BATCH_TILES_PER_ITEM")) per_item = atoi(ev);
         per_item = per_item < 1 ? 1 : per_item > 64 ? 64 : per_item;
         b->per_item = per_item;

@@ -38,7 +38,7 @@ inline int batch_dep_pass(int p)
 }
 
 // Work items of a batch.  An item is up to `per_item` consecutive tiles of
-// one pass of one field (the finalize is one item).  Queue q holds the
+// one pass of one field, sized by batch_chunks (the finalize is one item).  Queue q holds the
 // items of the fields with
 // queue_of[f] == q, pass by pass (x forward of every such field, then y, z,
 // the finalizes, y backward, x backward), fields in order within a pass:
@@ -47,7 +47,25 @@ inline int batch_dep_pass(int p)
 // queue q is items [qstart[q], qstart[q] + qcount[q]).
 // tiles[f][p] = tiles of pass p of field f (0: no item).  The counter of
 // (f, p) is f * BP_COUNT + p and counts items.
-inline int batch_nitems(int tiles, int per_item) { return (tiles + per_item - 1) / per_item; }
+// Item sizes of one pass of one field: per_item tiles while at least twice
+// that many are left, then half of what is left (at least one), so that the
+// pass's last items end close together and the next pass waits less.
+inline std::vector<int> batch_chunks(int tiles, int per_item)
+{
+    std::vector<int> out;
+    for (int left = tiles; left > 0;) {
+        int n = left / 2;
+        if (n > per_item) n = per_item;
+        if (n < 1) n = 1;
+        out.push_back(n);
+        left -= n;
+    }
+    return out;
+}
+inline int batch_nitems(int tiles, int per_item)
+{
+    return (int)batch_chunks(tiles, per_item < 1 ? 1 : per_item).size();
+}
 
 inline std::vector<QItem> batch_items(const std::vector<std::array<int, BP_COUNT>> &tiles,
                                       int per_item, const std::vector<int> &queue_of, int nq,
@@ -66,10 +84,11 @@ inline std::vector<QItem> batch_items(const std::vector<std::array<int, BP_COUNT
                 if (queue_of[f] != q) continue;
                 const int dp = batch_dep_pass(p);
                 const int need = dp < 0 ? 0 : batch_nitems(tiles[f][dp], per_item);
-                for (int t = 0; t < tiles[f][p]; t += per_item) {
-                    const int n = tiles[f][p] - t < per_item ? tiles[f][p] - t : per_item;
+                int t = 0;
+                for (int n : batch_chunks(tiles[f][p], per_item)) {
                     items.push_back(QItem{f, p, t, n, f * BP_COUNT + p,
                                           dp < 0 ? -1 : f * BP_COUNT + dp, need, 0});
+                    t += n;
                 }
             }
         qcount[q] = (uint32_t)items.size() - qstart[q];

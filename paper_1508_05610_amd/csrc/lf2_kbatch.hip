@@ -168,11 +168,6 @@ struct DevAtomics {
         return uni(__hip_atomic_fetch_add(p, lane0() ? v : 0u, __ATOMIC_RELAXED,
                                           __HIP_MEMORY_SCOPE_AGENT));
     }
-    static __device__ uint32_t fetch_add_release(uint32_t *p, uint32_t v)
-    {
-        return uni(__hip_atomic_fetch_add(p, lane0() ? v : 0u, __ATOMIC_RELEASE,
-                                          __HIP_MEMORY_SCOPE_AGENT));
-    }
     static __device__ uint32_t fetch_add_acq_rel(uint32_t *p, uint32_t v)
     {
         return uni(__hip_atomic_fetch_add(p, lane0() ? v : 0u, __ATOMIC_ACQ_REL,
@@ -187,15 +182,17 @@ struct DevAtomics {
     {
         return uni(__hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
     }
-    static __device__ uint32_t load_acquire(const uint32_t *p)
-    {
-        return uni(__hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT));
-    }
     // every lane stores the same value
     static __device__ void store_relaxed(uint32_t *p, uint32_t v)
     {
         __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
+    // Completion counts are relaxed atomics (performed in the L2); the
+    // ordering of the tile data around them is the policy's wave and leader
+    // operations.  (Release / acquire at agent scope here would write back
+    // and invalidate the whole L2 at every publication and every poll.)
+    static __device__ uint32_t publish_add(uint32_t *p, uint32_t v) { return fetch_add_relaxed(p, v); }
+    static __device__ uint32_t poll_load(const uint32_t *p) { return load_relaxed(p); }
     static __device__ void pause() { __builtin_amdgcn_s_sleep(2); }
     // every wave: its stores have reached the L2 (the L1 writes through)
     static __device__ void wave_release() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
@@ -204,7 +201,8 @@ struct DevAtomics {
 };
 
 // Producer and consumer of every tile on one XCD (one queue per XCD): the
-// L2 they share is the point of coherence, so only the L1 needs care.
+// L2 they share is the point of coherence, so only the L1 needs care (the
+// wave operations).
 struct DevLocal : DevAtomics {
     static __device__ void leader_release() {}
     static __device__ void leader_acquire() {}
@@ -212,7 +210,7 @@ struct DevLocal : DevAtomics {
 
 // One queue for the whole chip: a tile written through one XCD's L2 is read
 // through another's, so the leader writes the L2 back before publishing and
-// invalidates it after its wait (once per item, not once per wave).
+// invalidates it after its wait (once per item, not once per wave or poll).
 struct DevAgent : DevAtomics {
     static __device__ void leader_release() { __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent"); }
     static __device__ void leader_acquire() { __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent"); }

@@ -61,13 +61,19 @@ struct QCtl {
 };
 
 // Atomics and memory-ordering policy A:
-//   fetch_add_relaxed / fetch_add_release / fetch_add_acq_rel / fetch_or_relaxed,
-//   load_relaxed / load_acquire / store_relaxed on uint32_t,
-//   wave_release()   every thread, after the item's stores,
-//   leader_release() the leader, after the block barrier, before the count,
-//   leader_acquire() the leader, after its wait,
-//   wave_acquire()   every thread, after the block barrier that ends the wait,
-//   pause()          between polls.
+//   fetch_add_relaxed / fetch_add_acq_rel / fetch_or_relaxed, load_relaxed /
+//   store_relaxed on uint32_t,
+//   publish_add(p, v) the completion count of an item,
+//   poll_load(p)      the count a wait polls,
+//   wave_release()    every thread, after the item's stores,
+//   leader_release()  the leader, after the block barrier, before publish_add,
+//   leader_acquire()  the leader, after its wait,
+//   wave_acquire()    every thread, after the block barrier that ends the wait,
+//   pause()           between polls.
+// A policy makes an item's stores visible to the readers of a published
+// count either in publish_add / poll_load themselves (release / acquire) or
+// through the wave and leader operations around them (then the two may be
+// relaxed).
 // B: one block: leader(), share(v) / shared() (one word the block shares),
 // barrier().  work(item) runs the item on every thread; it may use the
 // block's barrier, the same number of times on every thread.
@@ -92,7 +98,7 @@ LF2_QFN void run_queue(B &blk, QCtl *ctl, int q, int nq, uint32_t *done, int ndo
         if (it.dep >= 0) {
             if (blk.leader()) {
                 uint32_t polls = 0;
-                while (A::load_acquire(&done[it.dep]) < (uint32_t)it.need) {
+                while (A::poll_load(&done[it.dep]) < (uint32_t)it.need) {
                     // once any wait has given up, no block waits any more
                     if (++polls > spin_limit || A::load_relaxed(&ctl[0].error)) {
                         A::fetch_or_relaxed(&ctl[0].error, 1u);
@@ -110,7 +116,7 @@ LF2_QFN void run_queue(B &blk, QCtl *ctl, int q, int nq, uint32_t *done, int ndo
         blk.barrier();
         if (blk.leader()) {
             A::leader_release();
-            A::fetch_add_release(&done[it.slot], 1u);
+            A::publish_add(&done[it.slot], 1u);
         }
     }
     if (blk.leader()) {

@@ -45,11 +45,12 @@ using namespace lf2;
 
 struct HostAtomics {
     static uint32_t fetch_add_relaxed(uint32_t *p, uint32_t v) { return __atomic_fetch_add(p, v, __ATOMIC_RELAXED); }
-    static uint32_t fetch_add_release(uint32_t *p, uint32_t v) { return __atomic_fetch_add(p, v, __ATOMIC_RELEASE); }
+    // the host model orders an item's stores through the counts themselves
+    static uint32_t publish_add(uint32_t *p, uint32_t v) { return __atomic_fetch_add(p, v, __ATOMIC_RELEASE); }
     static uint32_t fetch_add_acq_rel(uint32_t *p, uint32_t v) { return __atomic_fetch_add(p, v, __ATOMIC_ACQ_REL); }
     static uint32_t fetch_or_relaxed(uint32_t *p, uint32_t v) { return __atomic_fetch_or(p, v, __ATOMIC_RELAXED); }
     static uint32_t load_relaxed(const uint32_t *p) { return __atomic_load_n(p, __ATOMIC_RELAXED); }
-    static uint32_t load_acquire(const uint32_t *p) { return __atomic_load_n(p, __ATOMIC_ACQUIRE); }
+    static uint32_t poll_load(const uint32_t *p) { return __atomic_load_n(p, __ATOMIC_ACQUIRE); }
     static void store_relaxed(uint32_t *p, uint32_t v) { __atomic_store_n(p, v, __ATOMIC_RELAXED); }
     // The block barrier (std::barrier) already orders the threads of a
     // block; the kernel's per-thread agent-scope fences have no host analogue.
@@ -176,7 +177,7 @@ int main(int argc, char **argv)
                             const QItem &it = items[t];
                             if (it.dep >= 0 && blk.leader()) {
                                 uint32_t polls = 0;
-                                while (HostAtomics::load_acquire(&done[it.dep]) < (uint32_t)it.need) {
+                                while (HostAtomics::poll_load(&done[it.dep]) < (uint32_t)it.need) {
                                     if (++polls > spin_limit || HostAtomics::load_relaxed(&ctl.error)) {
                                         HostAtomics::fetch_or_relaxed(&ctl.error, 1u);
                                         break;
@@ -187,7 +188,7 @@ int main(int argc, char **argv)
                             blk.barrier();
                             work(it, l, bar);
                             blk.barrier();
-                            if (blk.leader()) HostAtomics::fetch_add_release(&done[it.slot], 1u);
+                            if (blk.leader()) HostAtomics::publish_add(&done[it.slot], 1u);
                         }
                     } else {
                         // block b serves queue b mod NQ; "starved": no block serves the last queue
