@@ -141,6 +141,12 @@ lf2_status lf2_fft_kspace(lf2_plan p, int64_t ksize[3], int64_t kstride[3]);
  * schedule (lf2_plan_get_schedule).  set overrides the setting and returns
  * the axis to its compiled kernels (LF2_ERR_UNSUPPORTED for wide tiles on a
  * length without them, or for a length without compiled kernels).
+ * axis 0 (the x pass): variant = how the two radix-8 stages of a c2c row of
+ * 64 points (one component) exchange their values -- 0 through LDS (every
+ * plan), 1 across the row's eight lanes with ds_bpermute, 2 across them with
+ * DPP moves (LF2_ERR_UNSUPPORTED for other plans); chunk is ignored (0 on
+ * get).  LF2_PLAN_AUTOTUNE times the three on such plans.  Every setting
+ * computes the same transform up to FP32 rounding.
  */
 lf2_status lf2_plan_get_tuning(lf2_plan p, int32_t axis, int32_t *variant, int32_t *chunk,
                                double *us_default, double *us_tuned);

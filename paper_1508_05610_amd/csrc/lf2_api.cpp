@@ -581,6 +581,10 @@ lf2_status run_x(const lf2_plan_s *p, int which, int sign, const XArgs &a, hipSt
         t = prof::begin((v ? kname("k_x_c2r_v<%d>", p->len[0]) : kname("k_x_c2r<%d,%d>", p->len[0], p->nc)) + shape,
                         rb + sb, s);
         e = launch_x_c2r(p->len[0], p->nc, a, s);
+    } else if (p->xx) {
+        t = prof::begin(kname("k_x_c2c_s64<%s,%d>", p->xx == 2 ? "dpp" : "bpermute", sign) + shape,
+                        2 * sb, s);
+        e = launch_x_c2c_shfl(sign, p->xx == 2, a, s);
     } else {
         t = prof::begin(kname("k_x_c2c_v<%d,%d,%d>", p->len[0], p->nc, sign) + shape, 2 * sb, s);
         e = launch_x_c2c(p->len[0], p->nc, sign, a, s);
@@ -692,7 +696,15 @@ const char *lf2_version(void) { return "lf2 0.1.0 gfx950"; }
 
 namespace {
 
-// Time the tile variants and XCD chunk sizes of the y and z passes, and the
+// Whether the x pass can exchange across lanes: c2c rows of 64 points, one
+// component, compiled kernels.
+bool x_lane_exchange_ok(const lf2_plan_s *p)
+{
+    return p->kind == LF2_C2C && p->len[0] == 64 && p->nc == 1 && !p->gen[0] && !p->gen_only[0];
+}
+
+// Time the x pass's stage exchange (64-point c2c rows: LDS or across
+// lanes), the tile variants and XCD chunk sizes of the y and z passes, and the
 // candidate radix schedules of the run-time-schedule kernels (every axis
 // without a compiled kernel, and the y and z passes as an alternative to
 // the compiled ones), on a scratch spectrum of the plan's shape (one
@@ -707,7 +719,7 @@ lf2_status autotune(lf2_plan p)
         (void)hipGetLastError();
         return LF2_OK;
     }
-    if (p->gen_only[0] && hipMalloc(&w2, bytes) != hipSuccess) {
+    if ((p->gen_only[0] || x_lane_exchange_ok(p)) && hipMalloc(&w2, bytes) != hipSuccess) {
         (void)hipGetLastError();
         w2 = nullptr;
     }
@@ -760,6 +772,29 @@ lf2_status autotune(lf2_plan p)
                 if (us >= 0 && (best < 0 || us < 0.97 * best)) {
                     best = us;
                     p->sched[0] = sc;
+                }
+            }
+            p->tune_us[0][1] = best;
+        }
+        // 64-point c2c rows: the stage exchange through LDS or across lanes
+        if (x_lane_exchange_ok(p) && w2) {
+            XArgs a{};
+            a.nrows = p->n[1] * p->n[2];
+            a.n1 = (int)p->n[1];
+            a.tw = p->tw[0];
+            a.in = w;
+            a.out = w2;
+            a.in_row = a.out_row = p->n[0];
+            a.in_plane = a.out_plane = p->n[0] * p->n[1];
+            double best = -1.0;
+            for (int v = 0; v < 3 && st == LF2_OK; ++v) {
+                const double us = time_it([&] {
+                    return v == 0 ? launch_x_c2c(64, 1, -1, a, s) : launch_x_c2c_shfl(-1, v == 2, a, s);
+                });
+                if (v == 0) p->tune_us[0][0] = us;
+                if (us >= 0 && (best < 0 || us < 0.97 * best)) {
+                    best = us;
+                    p->xx = v;
                 }
             }
             p->tune_us[0][1] = best;
@@ -943,7 +978,14 @@ lf2_status lf2_plan_get_tuning(lf2_plan p, int32_t axis, int32_t *variant, int32
                                double *us_default, double *us_tuned)
 {
     if (!p) return fail(LF2_ERR_INVALID_ARG, "plan is NULL");
-    if (axis != 1 && axis != 2) return fail(LF2_ERR_INVALID_ARG, "axis %d is not 1 or 2", axis);
+    if (axis < 0 || axis > 2) return fail(LF2_ERR_INVALID_ARG, "axis %d is not 0, 1 or 2", axis);
+    if (axis == 0) {
+        if (variant) *variant = p->gen[0] ? -1 : p->xx;
+        if (chunk) *chunk = 0;
+        if (us_default) *us_default = p->tune_us[0][0];
+        if (us_tuned) *us_tuned = p->tune_us[0][1];
+        return LF2_OK;
+    }
     if (variant) *variant = p->gen[axis] ? -1 : p->svar[axis];
     if (chunk) *chunk = p->schunk[axis];
     if (us_default) *us_default = p->tune_us[axis][0];
@@ -998,7 +1040,21 @@ lf2_status lf2_plan_set_schedule(lf2_plan p, int32_t axis, const int32_t *radice
 lf2_status lf2_plan_set_tuning(lf2_plan p, int32_t axis, int32_t variant, int32_t chunk)
 {
     if (!p) return fail(LF2_ERR_INVALID_ARG, "plan is NULL");
-    if (axis != 1 && axis != 2) return fail(LF2_ERR_INVALID_ARG, "axis %d is not 1 or 2", axis);
+    if (axis == 0) {
+        if (variant < 0 || variant > 2) return fail(LF2_ERR_INVALID_ARG, "variant %d outside [0, 2]", variant);
+        if (p->gen_only[0])
+            return fail(LF2_ERR_UNSUPPORTED, "no compiled kernels for line length %d", p->len[0]);
+        const bool was_gen = p->gen[0];
+        p->gen[0] = false;  // the compiled kernels again
+        if (variant && !x_lane_exchange_ok(p)) {
+            p->gen[0] = was_gen;
+            return fail(LF2_ERR_UNSUPPORTED,
+                        "lane exchange needs c2c rows of 64 points and one component");
+        }
+        p->xx = variant;
+        return LF2_OK;
+    }
+    if (axis != 1 && axis != 2) return fail(LF2_ERR_INVALID_ARG, "axis %d is not 0, 1 or 2", axis);
     if (variant < 0 || variant > 3) return fail(LF2_ERR_INVALID_ARG, "variant %d outside [0, 3]", variant);
     if (chunk < 1 || chunk > 1024) return fail(LF2_ERR_INVALID_ARG, "chunk %d outside [1, 1024]", chunk);
     if (p->gen_only[axis])

@@ -82,6 +82,10 @@ bool s_supported(int len);
 hipError_t launch_x_r2c(int m, int nc, const XArgs &a, hipStream_t s);
 hipError_t launch_x_c2r(int m, int nc, const XArgs &a, hipStream_t s);
 hipError_t launch_x_c2c(int len, int nc, int sign, const XArgs &a, hipStream_t s);
+// c2c x pass of 64-point one-component rows with the stage exchange across
+// lanes (eight lanes per row) instead of LDS: DPP moves (dpp) or
+// ds_bpermute.
+hipError_t launch_x_c2c_shfl(int sign, bool dpp, const XArgs &a, hipStream_t s);
 // variant bit 0: STileW (wide tiles, plain passes of s_wide_supported
 // lengths) instead of STile (narrow, any pass); bit 1: nontemporal global
 // loads and stores (plain passes).  EPI_TSTORE / EPI_TLOAD in a.epi select

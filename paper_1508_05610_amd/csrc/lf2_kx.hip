@@ -125,6 +125,111 @@ static void c2c_nc(int sign, const XArgs &a, hipStream_t s)
                            dim3(kXThreads), 0, s, a);
 }
 
+// Lane j ^ M's value of v, for lanes in groups of eight (M = 1, 2, 4).
+// DPP: data-parallel moves of the VALU (quad permutes for M = 1 and 2; for
+// M = 4 a shift by four lanes either way within each row of sixteen lanes,
+// the right one selected per lane); otherwise ds_bpermute (the LDS
+// crossbar, no LDS memory).
+template <int M, bool DPP>
+__device__ __forceinline__ float lane_xor(float v, int j)
+{
+    if constexpr (!DPP) {
+        return __shfl_xor(v, M);
+    } else {
+        const int x = __float_as_int(v);
+        if constexpr (M == 1) return __int_as_float(__builtin_amdgcn_update_dpp(0, x, 0xB1, 0xF, 0xF, false));
+        if constexpr (M == 2) return __int_as_float(__builtin_amdgcn_update_dpp(0, x, 0x4E, 0xF, 0xF, false));
+        const int up = __builtin_amdgcn_update_dpp(0, x, 0x104, 0xF, 0xF, false);    // lane + 4
+        const int down = __builtin_amdgcn_update_dpp(0, x, 0x114, 0xF, 0xF, false);  // lane - 4
+        return __int_as_float((j & 4) ? down : up);
+    }
+}
+
+// One pair of one round of the 8 x 8 exchange (registers r0 and r1 = r0 | M
+// of lanes j and j ^ M): the lane with bit M clear keeps r0 and receives its
+// partner's r0 into r1; the other keeps r1 and receives r0.
+template <int M, bool DPP>
+__device__ __forceinline__ void xpair(c32 &a0, c32 &a1, int j)
+{
+    const bool hi = (j & M) != 0;
+    const c32 b0 = a0, b1 = a1;  // values, so that the selects are of values
+    const c32 send = c32{hi ? b0.x : b1.x, hi ? b0.y : b1.y};
+    const c32 got = c32{lane_xor<M, DPP>(send.x, j), lane_xor<M, DPP>(send.y, j)};
+    a0 = c32{hi ? got.x : b0.x, hi ? got.y : b0.y};
+    a1 = c32{hi ? b1.x : got.x, hi ? b1.y : got.y};
+}
+
+// The three rounds (lane bits 4, 2, 1), each swapping a register bit with
+// the same lane bit: element (lane j, register k) ends in lane k, register j.
+template <bool DPP>
+__device__ __forceinline__ void xchg8(c32 (&v)[8], int j)
+{
+    xpair<4, DPP>(v[0], v[4], j);
+    xpair<4, DPP>(v[1], v[5], j);
+    xpair<4, DPP>(v[2], v[6], j);
+    xpair<4, DPP>(v[3], v[7], j);
+    xpair<2, DPP>(v[0], v[2], j);
+    xpair<2, DPP>(v[1], v[3], j);
+    xpair<2, DPP>(v[4], v[6], j);
+    xpair<2, DPP>(v[5], v[7], j);
+    xpair<1, DPP>(v[0], v[1], j);
+    xpair<1, DPP>(v[2], v[3], j);
+    xpair<1, DPP>(v[4], v[5], j);
+    xpair<1, DPP>(v[6], v[7], j);
+}
+
+// c2c rows of 64 points (one component) with the exchange between the two
+// radix-8 stages done across lanes instead of through LDS: eight lanes per
+// row, lane j holding points j + 8 r.  Stage one is an 8-point DFT per
+// lane; after the twiddles W_64^(j k), lane j holds element (j, k) of an
+// 8 x 8 block spread over the row's lanes, and three rounds of lane
+// exchanges (lane bits 4, 2, 1) leave element (j, k) in lane k, register
+// j, where stage two runs; lane k then holds the outputs k + 8 k2.  No LDS
+// exchange and no block barrier.  DPP: the exchanges as VALU moves, else
+// as ds_bpermute.
+template <int S, bool DPP>
+__global__ __launch_bounds__(256) void k_x_c2c_s64(XArgs a)
+{
+    constexpr int L = 64, R = 8, ROWS = 256 / R;
+    __shared__ c32 tw[L];
+    load_table(tw, a.tw, L, threadIdx.x, 256);
+    __syncthreads();
+    const int j = threadIdx.x & (R - 1);
+    const int64_t row = (int64_t)blockIdx.x * ROWS + (threadIdx.x >> 3);
+    if (row >= a.nrows) return;  // whole 8-lane groups leave together
+    const int64_t z = row / a.n1, y = row - z * a.n1;
+    const c32 *src = (const c32 *)a.in + a.in_off + z * a.in_plane + y * a.in_row + j;
+    c32 *dst = (c32 *)a.out + a.out_off + z * a.out_plane + y * a.out_row + j;
+    c32 v[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) v[r] = gload<true>(src + R * r);
+    Dft<R, S>::run(v);
+#pragma unroll
+    for (int k = 1; k < R; ++k) {
+        c32 w = tw[(j * k) & (L - 1)];
+        if (S > 0) w = conjg(w);
+        v[k] = mul(v[k], w);
+    }
+    xchg8<DPP>(v, j);
+    Dft<R, S>::run(v);
+#pragma unroll
+    for (int k2 = 0; k2 < R; ++k2) gstore<true>(dst + R * k2, v[k2]);
+}
+
+hipError_t launch_x_c2c_shfl(int sign, bool dpp, const XArgs &a, hipStream_t s)
+{
+    const unsigned g = x_grid(a.nrows, 256 / 8);
+    if (sign < 0 && dpp)
+        hipLaunchKernelGGL((k_x_c2c_s64<-1, true>), dim3(g), dim3(256), 0, s, a);
+    else if (sign < 0)
+        hipLaunchKernelGGL((k_x_c2c_s64<-1, false>), dim3(g), dim3(256), 0, s, a);
+    else if (dpp)
+        hipLaunchKernelGGL((k_x_c2c_s64<1, true>), dim3(g), dim3(256), 0, s, a);
+    else
+        hipLaunchKernelGGL((k_x_c2c_s64<1, false>), dim3(g), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
 hipError_t launch_x_c2c(int len, int nc, int sign, const XArgs &a, hipStream_t s)
 {
 #define LF2_CASE(L)                                                                          \
