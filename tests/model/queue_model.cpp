@@ -139,7 +139,10 @@ int main(int argc, char **argv)
     std::vector<std::vector<std::atomic<int>>> runs(ndone);
     for (int i = 0; i < ndone; ++i) runs[i] = std::vector<std::atomic<int>>(stamp[i].size());
     std::atomic<int> bad{0};
-    const uint32_t spin_limit = 200000;
+    // waits of the ticket protocol always end (a poll yields the core, so an
+    // oversubscribed host can stretch one a long way); the deadlocking
+    // orders end only through the limit
+    const uint32_t spin_limit = mode == "ticket" ? 50000000u : 200000u;
 
     auto work = [&](const QItem &it, int lane, std::barrier<> &bar) {
         // every lane checks a share of the dependency's tiles, then the
