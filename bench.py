@@ -53,10 +53,10 @@ def tuning_spec(tuning: dict) -> str:
         for nm, t in tuning.items())
 
 
-def measured_traffic(kernel: str, tuning: str):
-    """HBM bytes per launch of `kernel` from the committed PMC summary, if it
-    was taken on the current kernel sources with the same pass tuning (which
-    decides the mix of launches a kernel symbol covers); else None."""
+def measured_traffic(record: str, tuning: str):
+    """HBM bytes per launch of the kernel record `record` (kernel, pass and
+    shape) from the committed PMC summary, if it was taken on the current
+    kernel sources with the same pass tuning; else None."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
@@ -64,7 +64,7 @@ def measured_traffic(kernel: str, tuning: str):
         t = json.load(f)
     if t.get("source_hash") != kernel_source_hash() or t.get("tuning") != tuning:
         return None
-    k = t.get("kernels", {}).get(kernel)
+    k = t.get("records", {}).get(record)
     return None if k is None else k.get("hbm_bytes_per_launch")
 
 
@@ -275,6 +275,37 @@ def bench_small_configs(args, torch, np, lf2, stream):
         p.close()
         out[name] = res
     return out
+
+
+def bench_lane_exchange(args, torch, lf2, _lib):
+    """The x pass of a 64x1024x1024 c2c transform (one component, 1 GiB of
+    traffic per pass) with the exchange between its two radix-8 stages
+    through LDS (tuning 0), ds_bpermute (1) or DPP moves (2): average
+    microseconds per launch from the library's event records."""
+    shape = (64, 1024, 1024)
+    g = torch.Generator(device="cuda").manual_seed(11)
+    z = torch.randn(shape[2], shape[1], shape[0], dtype=torch.complex64, device="cuda",
+                    generator=g)
+    out = torch.empty_like(z)
+    res = {}
+    for v, name in ((0, "lds"), (1, "ds_bpermute"), (2, "dpp")):
+        plan = lf2.Plan(shape, lf2.LF2_C2C)
+        plan.set_tuning(0, v)
+        for _ in range(args.warmup):
+            plan.forward(z, out=out)
+        torch.cuda.synchronize()
+        _lib.lf2_profile_enable(True)
+        _lib.lf2_profile_reset()
+        for _ in range(args.steps):
+            plan.forward(z, out=out)
+        torch.cuda.synchronize()
+        t = _lib.profile_table()
+        _lib.lf2_profile_enable(False)
+        for k, (n_, ms_, by_) in t.items():
+            if k.startswith("k_x"):
+                res[name] = {"kernel": k, "avg_us": round(1e3 * ms_ / n_, 2),
+                             "gbps": round(by_ / n_ / (ms_ / n_ * 1e-3) / 1e9, 1)}
+    return {"lane_exchange": res, "lattice": list(shape), "steps": args.steps}
 
 
 def bench_serving(args, torch, np, lf2):
@@ -583,6 +614,9 @@ def main():
     ap.add_argument("--only", default=None,
                     help="time one op alone (r2c_fwd, c2r_bwd, c2c_fwd_3comp, c2c_bwd_3comp, "
                          "poisson_pk, copy) for profiler runs")
+    ap.add_argument("--lane-exchange", action="store_true",
+                    help="only time the x pass of a 64x1024x1024 c2c lattice with its stage "
+                         "exchange through LDS, ds_bpermute and DPP (one JSON line)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -600,6 +634,9 @@ def main():
 
     lf2.load()
     dev = torch.device("cuda:0")
+    if args.lane_exchange:
+        print(json.dumps(bench_lane_exchange(args, torch, lf2, _lib)), flush=True)
+        return
     S = args.size
     n = (S, S, S)
     N = S ** 3
@@ -724,16 +761,9 @@ def main():
         per_op_p90[name] = float(np.percentile(t, 90))
 
     step_bytes = sum(v[2] for v in table.values()) / args.steps
-    # group the per-pass records by kernel symbol (the part before the space)
-    by_symbol = {}
-    for k, (n_, ms_, by_) in table.items():
-        sym = k.split(" ")[0]
-        a0 = by_symbol.setdefault(sym, [0, 0.0, 0.0])
-        a0[0] += n_
-        a0[1] += ms_
-        a0[2] += by_
-    dom = max(by_symbol.items(), key=lambda kv: kv[1][1])
-    dname, (dn, dms, dbytes) = dom
+    # the dominant kernel: the record (kernel, pass and shape; one launch
+    # configuration) with the most time in the step
+    dname, (dn, dms, dbytes) = max(table.items(), key=lambda kv: kv[1][1])
     achieved = (dbytes / dn) / (dms / dn * 1e-3) / 1e9
     traffic = measured_traffic(dname, tuning_spec(tuning))
     kernels = {k: {"launches": v[0], "avg_us": 1e3 * v[1] / v[0],

@@ -27,15 +27,18 @@ def test_traffic_only_for_matching_sources_and_tuning(tmp_path, monkeypatch):
     os.symlink(os.path.join(ROOT, "paper_1508_05610_amd", "csrc"),
                tmp_path / "paper_1508_05610_amd" / "csrc")
     rec = {"source_hash": bench.kernel_source_hash(), "tuning": "r2c:y=0/16,z=2/16",
-           "kernels": {"k_strided<512,-1,0,1>": {"hbm_bytes_per_launch": 123.0}}}
+           "records": {"k_strided<512,-1,0,1> z 512x512x512/1": {"hbm_bytes_per_launch": 123.0}}}
     (prof / "traffic.json").write_text(json.dumps(rec))
     monkeypatch.setattr(bench, "ROOT", str(tmp_path))
-    assert bench.measured_traffic("k_strided<512,-1,0,1>", "r2c:y=0/16,z=2/16") == 123.0
-    assert bench.measured_traffic("k_strided<512,-1,0,1>", "r2c:y=1/16,z=2/16") is None
-    assert bench.measured_traffic("k_x_r2c_v<256>", "r2c:y=0/16,z=2/16") is None
+    z = "k_strided<512,-1,0,1> z 512x512x512/1"
+    assert bench.measured_traffic(z, "r2c:y=0/16,z=2/16") == 123.0
+    assert bench.measured_traffic(z, "r2c:y=1/16,z=2/16") is None
+    # the same kernel symbol on another pass or shape is another record
+    assert bench.measured_traffic("k_strided<512,-1,0,1> y 512x512x512/3", "r2c:y=0/16,z=2/16") is None
+    assert bench.measured_traffic("k_x_r2c_v<256> 512x512x512/1", "r2c:y=0/16,z=2/16") is None
     rec["source_hash"] = "0" * 16
     (prof / "traffic.json").write_text(json.dumps(rec))
-    assert bench.measured_traffic("k_strided<512,-1,0,1>", "r2c:y=0/16,z=2/16") is None
+    assert bench.measured_traffic(z, "r2c:y=0/16,z=2/16") is None
 
 
 def test_more_than_one_gpu_is_refused():
