@@ -613,7 +613,7 @@ def main():
                          "'r2c:y=0/16,z=0/16;c2c3:y=1/16,z=1/64' (variant/chunk)")
     ap.add_argument("--only", default=None,
                     help="time one op alone (r2c_fwd, c2r_bwd, c2c_fwd_3comp, c2c_bwd_3comp, "
-                         "poisson_pk, copy) for profiler runs")
+                         "poisson_pk, copy, field_ops) for profiler runs")
     ap.add_argument("--lane-exchange", action="store_true",
                     help="only time the x pass of a 64x1024x1024 c2c lattice with its stage "
                          "exchange through LDS, ds_bpermute and DPP (one JSON line)")
@@ -636,6 +636,9 @@ def main():
     dev = torch.device("cuda:0")
     if args.lane_exchange:
         print(json.dumps(bench_lane_exchange(args, torch, lf2, _lib)), flush=True)
+        return
+    if args.only == "field_ops":
+        print(json.dumps({"only": args.only, **bench_field_ops(args, torch, lf2)}), flush=True)
         return
     S = args.size
     n = (S, S, S)

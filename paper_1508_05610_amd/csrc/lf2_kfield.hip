@@ -96,16 +96,20 @@ hipError_t launch_update_halo(void *field, const int64_t n[3], int64_t h, int64_
 // out(x)[3 c + i] = (f(x + e_i) - f(x))[c] / dx.  The input's halo (width
 // h >= 1) supplies the neighbours across the upper faces; the output has
 // the same halo layout and only its interior is written.  A row of the
-// field is a run of N0 ncomp words (site-major, components inner).  A block
-// covers 256 consecutive words of GY consecutive rows and marches through
-// ZC planes: per plane it reads GY + 1 rows of the following plane (the
-// extra row is the y neighbour of the group's last row), which later serve
-// as the current plane, so HBM sees each input row (GY + 1) / GY times.
-// Those reads run one plane ahead of the arithmetic.  The x neighbour is
-// the word ncomp further on: the current plane's rows go through LDS (plus
-// the ncomp words past the block's end, read from memory), so it is not
-// read again.  The three results of a word are staged through LDS so that
-// every store of a wave is contiguous.
+// field is a run of N0 ncomp words (site-major, components inner).  A row
+// is split evenly over the fewest blocks of at most 768 threads (one word a
+// thread): long contiguous runs per block matter more here than deep row
+// groups.  A block covers its words in GY consecutive rows and marches
+// through ZC planes: per plane it reads GY + 1 rows of the following plane
+// (the extra row is the y neighbour of the group's last row), which later
+// serve as the current plane.  Those reads run one plane ahead of the
+// arithmetic.  The x neighbour is the word ncomp further on: the current
+// plane's rows go through LDS (plus the ncomp words past the block's end,
+// read from memory), so it is not read again.  The three results of a word
+// are adjacent in the output and leave as one 12-byte store, so every store
+// of a wave is one contiguous run.  Tiles that overlap (the boundary rows,
+// planes and cache lines they share) are walked by one XCD at a time, so
+// the shared lines mostly come from L2.
 struct GradArgs {
     const float *in;
     float *out;
@@ -113,35 +117,55 @@ struct GradArgs {
     int nc;
     float inv_dx;
     int zc;
+    int width;       // words per tile along x (the block size)
+    int gx, gy, gz;  // tiles along x (width words), y (GY rows), z (zc planes)
 };
 
-constexpr int kGradThreads = 256;
-constexpr int kGradRows = 8;     // GY
+constexpr int kGradMaxThreads = 768;  // widest block (words of a row)
+constexpr int kGradRows = 4;          // GY
+constexpr int kGradPlanes = 32;       // ZC
 constexpr int kGradMaxComp = 64;  // largest ncomp
 
-__global__ __launch_bounds__(kGradThreads) void k_gradient(GradArgs a)
+// Three adjacent floats at a 4-byte aligned address.
+struct __attribute__((packed, aligned(4))) Float3 {
+    float x, y, z;
+};
+
+__global__ __launch_bounds__(kGradMaxThreads) void k_gradient(GradArgs a)
 {
     constexpr int GY = kGradRows;
-    __shared__ float stage[GY][3 * kGradThreads];
-    __shared__ float cur[GY][kGradThreads + kGradMaxComp];
+    __shared__ float cur[GY][kGradMaxThreads + kGradMaxComp];
     const int tid = threadIdx.x;
+    const int nt = a.width;  // threads (words) of a block
     const int64_t rowwords = a.n0 * a.nc;
-    const int64_t w0 = (int64_t)blockIdx.x * kGradThreads;
+    // The chip hands block ids to its 8 XCDs in turn.  Block i serves tile
+    // number start(i mod 8) + i / 8, so each XCD walks a contiguous range of
+    // tiles (x fastest, then y, then z): neighbouring tiles, which share the
+    // cache lines at their x ends (rows are not 128-byte aligned) and their
+    // boundary rows, run at the same time behind one L2.
+    const int nb = a.gx * a.gy * a.gz;
+    const int q = nb >> 3, r = nb & 7, j = blockIdx.x & 7;
+    const int tile = j * q + (j < r ? j : r) + (int)(blockIdx.x >> 3);
+    const int bx = tile % a.gx, byz = tile / a.gx;
+    const int by = byz % a.gy, bz = byz / a.gy;
+    const int64_t w0 = (int64_t)bx * nt;
     const int64_t w = w0 + tid;
     // words up to rowwords + ncomp - 1 (the upper halo site) are read: the
     // last interior words take their x neighbours from them
     const bool ld = w < rowwords + a.nc;
-    const int64_t y0 = (int64_t)blockIdx.y * GY;
+    const bool st = w < rowwords;
+    const int64_t y0 = (int64_t)by * GY;
     const int ny = (int)(a.n1 - y0 < GY ? a.n1 - y0 : GY);  // rows of this group
-    const int64_t z0 = (int64_t)blockIdx.z * a.zc;
+    const int64_t z0 = (int64_t)bz * a.zc;
     const int64_t z1 = z0 + a.zc < a.n2 ? z0 + a.zc : a.n2;
     const int64_t sy = a.p0 * a.nc, sz = a.p1 * a.p0 * a.nc;  // input strides (words)
     // input word w of interior row y0 + i of plane z0; rows past the group
     // are read from row min(y0 + i, n1), which exists (upper halo row n1)
     const float *f = a.in + ((a.h + z0) * a.p1 + a.h + y0) * sy + a.h * a.nc + (ld ? w : 0);
-    int64_t roff[GY + 1];
+    // row offsets (words; below 2^31: GY rows of at most 2^31 / GY words)
+    int roff[GY + 1];
 #pragma unroll
-    for (int i = 0; i <= GY; ++i) roff[i] = (i <= ny ? i : ny) * sy;
+    for (int i = 0; i <= GY; ++i) roff[i] = (i <= ny ? i : ny) * (int)sy;
     // c: plane z, nx: plane z + 1 (both rows y0 .. y0 + GY)
     float c[GY + 1], nx[GY + 1];
 #pragma unroll
@@ -149,13 +173,13 @@ __global__ __launch_bounds__(kGradThreads) void k_gradient(GradArgs a)
         c[i] = ld ? f[roff[i]] : 0.f;
         nx[i] = ld ? f[sz + roff[i]] : 0.f;
     }
-    // words w0 + 256 + t (t < ncomp) hold the last threads' x neighbours;
-    // they exist while w0 + 256 + t < rowwords + ncomp (upper halo site)
-    const bool extra = tid < a.nc && w0 + kGradThreads + tid < rowwords + a.nc;
+    // words w0 + nt + t (t < ncomp) hold the last threads' x neighbours;
+    // they exist while w0 + nt + t < rowwords + ncomp (upper halo site)
+    const bool extra = tid < a.nc && w0 + nt + tid < rowwords + a.nc;
     const float *fe = a.in + ((a.h + z0) * a.p1 + a.h + y0) * sy + a.h * a.nc +
-                      (extra ? w0 + kGradThreads + tid : 0);
-    const int nst = (int)(3 * (rowwords - w0 < kGradThreads ? rowwords - w0 : kGradThreads));
-    float *o = a.out + ((a.h + z0) * a.p1 + a.h + y0) * (sy * 3) + a.h * a.nc * 3 + 3 * w0;
+                      (extra ? w0 + nt + tid : 0);
+    float *o = a.out + ((a.h + z0) * a.p1 + a.h + y0) * (sy * 3) + a.h * a.nc * 3 + 3 * w;
+    const int64_t oy = sy * 3;
     for (int64_t z = z0; z < z1; ++z) {
         // the next step's planes, read only while z + 2 <= z1 <= n2 (the
         // upper halo plane n2 exists)
@@ -166,19 +190,17 @@ __global__ __launch_bounds__(kGradThreads) void k_gradient(GradArgs a)
 #pragma unroll
         for (int i = 0; i < GY; ++i) {
             cur[i][tid] = c[i];
-            if (extra) cur[i][kGradThreads + tid] = fe[roff[i]];
+            if (extra) cur[i][nt + tid] = fe[roff[i]];
         }
         __syncthreads();
 #pragma unroll
         for (int i = 0; i < GY; ++i) {
-            const float xn = cur[i][tid + a.nc];
-            stage[i][3 * tid + 0] = (xn - c[i]) * a.inv_dx;
-            stage[i][3 * tid + 1] = (c[i + 1] - c[i]) * a.inv_dx;
-            stage[i][3 * tid + 2] = (nx[i] - c[i]) * a.inv_dx;
+            if (st && i < ny) {
+                const float xn = cur[i][tid + a.nc];
+                *(Float3 *)(o + i * oy) = Float3{(xn - c[i]) * a.inv_dx, (c[i + 1] - c[i]) * a.inv_dx,
+                                                 (nx[i] - c[i]) * a.inv_dx};
+            }
         }
-        __syncthreads();
-        for (int i = 0; i < ny; ++i)
-            for (int j = tid; j < nst; j += kGradThreads) o[i * (sy * 3) + j] = stage[i][j];
         __syncthreads();
 #pragma unroll
         for (int i = 0; i <= GY; ++i) {
@@ -205,11 +227,19 @@ hipError_t launch_gradient(const float *in, float *out, const int64_t n[3], int6
     a.p1 = n[1] + 2 * h;
     a.nc = nc;
     a.inv_dx = (float)(1.0 / dx);
-    a.zc = 16;
+    a.zc = kGradPlanes;
     const int64_t rowwords = n[0] * nc;
-    dim3 grid((unsigned)((rowwords + kGradThreads - 1) / kGradThreads),
-              (unsigned)((n[1] + kGradRows - 1) / kGradRows), (unsigned)((n[2] + a.zc - 1) / a.zc));
-    hipLaunchKernelGGL(k_gradient, grid, dim3(kGradThreads), 0, s, a);
+    if ((int64_t)(kGradRows + 1) * a.p0 * nc > 0x7fffffff) return hipErrorInvalidValue;
+    // the fewest blocks of at most kGradMaxThreads words per row, as even
+    // as whole wavefronts allow
+    const int64_t gx = (rowwords + kGradMaxThreads - 1) / kGradMaxThreads;
+    a.width = (int)(((rowwords + gx - 1) / gx + 63) / 64 * 64);
+    const int64_t gy = (n[1] + kGradRows - 1) / kGradRows, gz = (n[2] + a.zc - 1) / a.zc;
+    if (gx * gy * gz > 0x7fffffff) return hipErrorInvalidValue;
+    a.gx = (int)gx;
+    a.gy = (int)gy;
+    a.gz = (int)gz;
+    hipLaunchKernelGGL(k_gradient, dim3((unsigned)(gx * gy * gz)), dim3(a.width), 0, s, a);
     return hipGetLastError();
 }
 

@@ -53,7 +53,10 @@ def test_update_halo_bitwise(lf2, shape, h, nc, cplx):
 
 @pytest.mark.parametrize("shape,h,nc,dx", [((16, 12, 10), 1, 1, 1.0), ((32, 24, 16), 1, 3, 0.5),
                                            ((8, 6, 40), 2, 2, 0.25), ((64, 48, 40), 1, 3, 1.0),
-                                           ((5, 7, 3), 1, 6, 1.0), ((100, 9, 5), 1, 2, 2.0)])
+                                           ((5, 7, 3), 1, 6, 1.0), ((100, 9, 5), 1, 2, 2.0),
+                                           # rows split over several blocks, the last one ragged
+                                           ((300, 6, 5), 1, 3, 1.0), ((520, 5, 3), 2, 2, 1.0),
+                                           ((20, 3, 3), 1, 64, 1.0)])
 def test_gradient_matches_oracle(lf2, shape, h, nc, dx):
     print(f"case gradient {shape} h={h} nc={nc}", flush=True)
     a = padded_field(shape, h, nc, seed=21)
