@@ -505,12 +505,14 @@ void launch_unit(lf2_server s, std::vector<Req *> &unit)
     }
 }
 
-// Return a finished request's resources (completion thread).  True when
-// this was the last request of its launch unit.
+// Return a finished request's resources but its workspace (completion
+// thread, server lock not held).  True when this was the last request of
+// its launch unit.  The workspace goes back to the pool under the server
+// lock, in the same step that takes the request's charge off the in-flight
+// bytes, so that no one sees it both idle and in flight.
 bool release(lf2_server s, Req *q)
 {
     bool unit_done = true;
-    if (q->ws) ws_put(s, q->ws);
     if (q->grp) {
         Group *g = q->grp;
         if (--g->refs == 0) {  // the completion thread is the only one touching refs here
@@ -524,7 +526,6 @@ bool release(lf2_server s, Req *q)
         ev_put(s, q->ev);
     }
     if (q->has_plan) put_plan(s, q->key);
-    q->ws = nullptr;
     q->ev = nullptr;
     q->grp = nullptr;
     return unit_done;
@@ -719,6 +720,8 @@ void completion_main(lf2_server s)
         for (Req *q : fin) {
             s->inflight.erase(std::find(s->inflight.begin(), s->inflight.end(), q));
             s->bytes_inflight -= q->charge;
+            ws_put(s, q->ws);  // pool lock inside the server lock, as in admission
+            q->ws = nullptr;
             q->t_done = tdone;
             q->done = true;
             if (q->st == LF2_OK)
