@@ -129,18 +129,22 @@ lf2_status lf2_fft_kspace(lf2_plan p, int64_t ksize[3], int64_t kstride[3]);
  * Tuning of the strided pass along `axis` (1 = y, 2 = z) for plain
  * transforms.  variant bit 0: wide tiles (twice the columns per tile, one
  * 1024-thread block per CU; lengths 256, 320, 384, 512, 640, 768, 1024,
- * 2048) instead of narrow tiles (all lengths); bit 1: nontemporal global
- * loads and stores (they pay on long strides, where each line is touched
- * once).  chunk = consecutive tiles given to one XCD in the tile order
- * (1..1024, default 16).  Every setting computes the same transform bit for
- * bit.  The fused Poisson / power-spectrum pass always uses narrow tiles,
+ * 2048) instead of narrow tiles (all lengths); bit 2: the register tile
+ * (length 1024 only, not with bit 0: 32 columns per tile held in registers
+ * as a 32 x 32 decomposition with one exchange through LDS); bit 1:
+ * nontemporal global loads and stores (they pay on long strides, where each
+ * line is touched once).  chunk = consecutive tiles given to one XCD in the
+ * tile order (1..1024, default 16).  Narrow and wide tiles compute the same
+ * transform bit for bit; the register tile computes it up to FP32 rounding
+ * (another order of the butterflies).  The fused Poisson / power-spectrum pass always uses narrow tiles,
  * nontemporal accesses and chunk 16.  get reports the setting and, after
  * LF2_PLAN_AUTOTUNE, the measured microseconds of the default setting
  * (variant 0, chunk 16) and of the chosen one (-1 if not measured); null
  * outputs are skipped; variant -1 means the axis runs a run-time radix
  * schedule (lf2_plan_get_schedule).  set overrides the setting and returns
- * the axis to its compiled kernels (LF2_ERR_UNSUPPORTED for wide tiles on a
- * length without them, or for a length without compiled kernels).
+ * the axis to its compiled kernels (LF2_ERR_UNSUPPORTED for wide tiles or
+ * the register tile on a length without them, or for a length without
+ * compiled kernels).
  * axis 0 (the x pass): variant = how the two radix-8 stages of a c2c row of
  * 64 points (one component) exchange their values -- 0 through LDS (every
  * plan), 1 across the row's eight lanes with ds_bpermute, 2 across them with

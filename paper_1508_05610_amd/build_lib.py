@@ -35,6 +35,7 @@ UNITS = [
     ("lf2_kx.hip", ["-DLF2_KX_PART=1"], "kx_c2r.o"),
     ("lf2_kx.hip", ["-DLF2_KX_PART=2"], "kx_c2c.o"),
     ("lf2_ks.hip", [], "ks.o"),
+    ("lf2_kreg.hip", [], "kreg.o"),
     ("lf2_kmisc.hip", [], "kmisc.o"),
     ("lf2_kbatch.hip", [], "kbatch.o"),
     ("lf2_kgen.hip", [], "kgen.o"),

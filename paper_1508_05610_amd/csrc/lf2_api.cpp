@@ -533,6 +533,7 @@ lf2_status run_strided(const lf2_plan_s *p, int axis, int sign, const SArgs &a, 
     // "<kernel symbol> <pass>": the symbol part matches the profiler's name
     const std::string sym = tr ? kname("k_strided_t<%d,%d>", p->len[axis], sign)
                             : (variant & 1) ? kname("k_strided_w<%d,%d,%d>", p->len[axis], sign, ntm)
+                            : (variant & 4) ? kname("k_strided_r<%d,%d>", sign, ntm)
                                             : kname("k_strided<%d,%d,%d,%d>", p->len[axis], sign,
                                                     epi ? 1 : 0, ntm);
     const int t = prof::begin(sym + kname(" %s%s%s %lldx%lldx%lld/%d", axis == 1 ? "y" : "z",
@@ -801,11 +802,13 @@ lf2_status autotune(lf2_plan p)
         }
         for (int axis = 1; axis <= 2 && st == LF2_OK; ++axis) {
             const bool wide = !p->gen_only[axis] && s_wide_supported(p->len[axis]);
+            const bool reg = !p->gen_only[axis] && s_reg_supported(p->len[axis]);
             const SArgs a = s_args(p, axis, w, w, EPI_STORE);
             double best = -1.0;
             if (!p->gen_only[axis]) {
-                for (int v = 0; v < 4 && st == LF2_OK; ++v) {
+                for (int v = 0; v < 8 && st == LF2_OK; ++v) {
                     if ((v & 1) && !wide) continue;
+                    if ((v & 4) && (!reg || (v & 1))) continue;
                     for (int c : kChunks) {
                         const double us = time_it([&] {
                             return launch_strided(p->len[axis], -1, a, kStridedGridCap, s, nullptr, v, c);
@@ -1055,12 +1058,15 @@ lf2_status lf2_plan_set_tuning(lf2_plan p, int32_t axis, int32_t variant, int32_
         return LF2_OK;
     }
     if (axis != 1 && axis != 2) return fail(LF2_ERR_INVALID_ARG, "axis %d is not 0, 1 or 2", axis);
-    if (variant < 0 || variant > 3) return fail(LF2_ERR_INVALID_ARG, "variant %d outside [0, 3]", variant);
+    if (variant < 0 || variant > 7) return fail(LF2_ERR_INVALID_ARG, "variant %d outside [0, 7]", variant);
     if (chunk < 1 || chunk > 1024) return fail(LF2_ERR_INVALID_ARG, "chunk %d outside [1, 1024]", chunk);
     if (p->gen_only[axis])
         return fail(LF2_ERR_UNSUPPORTED, "no compiled kernels for line length %d", p->len[axis]);
     if ((variant & 1) && !s_wide_supported(p->len[axis]))
         return fail(LF2_ERR_UNSUPPORTED, "no wide tiles for line length %d", p->len[axis]);
+    if ((variant & 4) && ((variant & 1) || !s_reg_supported(p->len[axis])))
+        return fail(LF2_ERR_UNSUPPORTED, "no register tile for line length %d (or with wide tiles)",
+                    p->len[axis]);
     p->svar[axis] = variant;
     p->schunk[axis] = chunk;
     p->gen[axis] = false;  // the compiled kernels again

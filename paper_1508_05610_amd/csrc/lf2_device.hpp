@@ -176,6 +176,45 @@ struct Dft<16, S> {
     }
 };
 
+template <int S>
+struct Dft<32, S> {
+    static __device__ __forceinline__ void run(c32 *v)
+    {
+        // 2 x 16: radix 2 over n1 (n = 16 n1 + n2), twiddle W32^{n2 k1},
+        // DFT16 over n2 for each k1; output k = k1 + 2 k2.
+        const float c1 = 0.98078528040323044913f;  // cos(pi/16)
+        const float s1 = 0.19509032201612826785f;  // sin(pi/16)
+        const float c2 = 0.92387953251128675613f;  // cos(pi/8)
+        const float s2 = 0.38268343236508977173f;  // sin(pi/8)
+        const float c3 = 0.83146961230254523708f;  // cos(3 pi/16)
+        const float s3 = 0.55557023301960222474f;  // sin(3 pi/16)
+        const float r2 = 0.70710678118654752440f;
+        // cos and sin of 2 pi m / 32, m = 0 .. 15
+        const float cs[16] = {1.f, c1, c2, c3, r2, s3, s2, s1, 0.f, -s1, -s2, -s3, -r2, -c3, -c2, -c1};
+        const float sn[16] = {0.f, s1, s2, s3, r2, c3, c2, c1, 1.f, c1, c2, c3, r2, s3, s2, s1};
+        c32 e[16], o[16];
+#pragma unroll
+        for (int n2 = 0; n2 < 16; ++n2) {
+            const c32 a = v[n2], b = v[16 + n2];
+            e[n2] = add(a, b);
+            const c32 d = sub(a, b);
+            if (n2 == 0)
+                o[n2] = d;
+            else if (n2 == 8)
+                o[n2] = muli<S>(d);
+            else
+                o[n2] = mul(d, c32{cs[n2], S * sn[n2]});
+        }
+        Dft<16, S>::run(e);
+        Dft<16, S>::run(o);
+#pragma unroll
+        for (int k2 = 0; k2 < 16; ++k2) {
+            v[2 * k2] = e[k2];
+            v[2 * k2 + 1] = o[k2];
+        }
+    }
+};
+
 // ---------------------------------------------------------------- radix plan
 // Radices for a line of length L = 2^a * 3^b * 5^c: the power-of-two part in
 // ceil(a/4) stages of 2..16 with the bits spread evenly (512 -> 8,8,8;

@@ -87,14 +87,19 @@ hipError_t launch_x_c2c(int len, int nc, int sign, const XArgs &a, hipStream_t s
 // ds_bpermute.
 hipError_t launch_x_c2c_shfl(int sign, bool dpp, const XArgs &a, hipStream_t s);
 // variant bit 0: STileW (wide tiles, plain passes of s_wide_supported
-// lengths) instead of STile (narrow, any pass); bit 1: nontemporal global
-// loads and stores (plain passes).  EPI_TSTORE / EPI_TLOAD in a.epi select
+// lengths) instead of STile (narrow, any pass); bit 2: the register tile
+// (k_strided_r: 32 x 32 decomposition, plain passes of s_reg_supported
+// lengths; not with bit 0); bit 1: nontemporal global loads and stores
+// (plain passes).  EPI_TSTORE / EPI_TLOAD in a.epi select
 // STileT (z pass to / from the paper's c2c k-space order) whatever the
 // variant.  chunk: consecutive tiles per XCD in the tile
 // order (16 by default).
 hipError_t launch_strided(int len, int sign, const SArgs &a, int grid_cap, hipStream_t s,
                           int *grid_used, int variant = 0, int chunk = 16);
 bool s_wide_supported(int len);
+bool s_reg_supported(int len);
+hipError_t launch_strided_reg(int len, int sign, const SArgs &a, int grid_cap, hipStream_t s,
+                              int *grid_used, int chunk, bool ntm);
 // LDS histogram copies of a fused last-axis tile of length len binning into
 // nbins bins, when the block's LDS is `budget` bytes: one per wave if they
 // fit with the tile, else one.  0 if len has no compiled fused tile.

@@ -135,6 +135,10 @@ hipError_t launch_strided(int len, int sign, const SArgs &a_in, int grid_cap, hi
         return launch_transposed(len, sign, a, grid_cap, s, grid_used);
     }
     const bool ntm = (variant & 2) != 0;
+    if (variant & 4) {
+        if (epi || (variant & 1) || !s_reg_supported(len)) return hipErrorInvalidValue;
+        return launch_strided_reg(len, sign, a, grid_cap, s, grid_used, kChunk, ntm);
+    }
     if (variant & 1) {
         if (epi || !s_wide_supported(len)) return hipErrorInvalidValue;
         return launch_wide(len, sign, a, grid_cap, s, grid_used, kChunk, ntm);

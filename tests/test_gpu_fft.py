@@ -227,6 +227,50 @@ def test_wide_tiles_match_oracle_and_narrow(lf2, shape, kind, ncomp):
     assert rel_l2(Fw.cpu().numpy(), Fn.cpu().numpy()) <= 1e-6
     assert rel_l2(bw.cpu().numpy(), bn.cpu().numpy()) <= 1e-6
 
+# lines of 1024 points along y or z in the register tile (32 columns held as a
+# 32 x 32 decomposition): column counts that leave the last tile ragged
+REG_CASES = [((8, 1024, 40), 1, 1), ((10, 6, 1024), 1, 3), ((12, 1024, 6), 0, 1),
+             ((6, 10, 1024), 0, 2), ((2, 1024, 1024), 1, 1)]
+
+
+@pytest.mark.parametrize("shape,kind,ncomp", REG_CASES)
+def test_register_tile_matches_oracle_and_narrow(lf2, shape, kind, ncomp):
+    print(f"case register tile {shape} kind={kind} ncomp={ncomp}", flush=True)
+    pn = lf2.Plan(shape, kind, ncomp=ncomp)
+    pr = lf2.Plan(shape, kind, ncomp=ncomp)
+    for axis in (1, 2):
+        if shape[axis] == 1024:  # plain and nontemporal accesses
+            v = 4 if axis == 1 else 6
+            pr.set_tuning(axis, v, chunk=8)
+            assert pr.tuning(axis)[:2] == (v, 8)
+    if kind == lf2.LF2_R2C:
+        fs = real_field(shape, seed=13, ncomp=ncomp)[0]
+        f = fs[..., 0]
+        x = torch.from_numpy(fs if ncomp > 1 else f).to(dev())
+        ref = oracle.r2c(f.astype(np.float64))
+    else:
+        z = complex_field(shape, seed=14, ncomp=ncomp)
+        x = torch.from_numpy(z if ncomp > 1 else z[..., 0]).to(dev())
+        ref = oracle.c2c(z[..., 0].astype(np.complex128), -1)
+    Fn = pn.forward(x)
+    Fr = pr.forward(x)
+    bn = pn.backward(Fn)
+    br = pr.backward(Fr)
+    torch.cuda.synchronize()
+    got = Fr.cpu().numpy()
+    if ncomp > 1:
+        got = got[..., 0]
+    e, em = rel_l2(got, ref), rel_max(got, ref)
+    report("register fwd", shape, e, em)
+    assert e <= tol(shape)
+    assert em <= tol(shape)
+    assert rel_l2(Fr.cpu().numpy(), Fn.cpu().numpy()) <= 1e-6
+    assert rel_l2(br.cpu().numpy(), bn.cpu().numpy()) <= 1e-6
+    if kind == lf2.LF2_R2C:
+        back = br.cpu().numpy() / float(np.prod(shape))
+        assert rel_l2(back, fs if ncomp > 1 else f) <= tol(shape)
+
+
 
 def test_autotune_picks_a_setting(lf2):
     shape = (64, 256, 512)
