@@ -130,8 +130,9 @@ lf2_status lf2_fft_kspace(lf2_plan p, int64_t ksize[3], int64_t kstride[3]);
  * transforms.  variant bit 0: wide tiles (twice the columns per tile, one
  * 1024-thread block per CU; lengths 256, 320, 384, 512, 640, 768, 1024,
  * 2048) instead of narrow tiles (all lengths); bit 2: the register tile
- * (length 1024 only, not with bit 0: 32 columns per tile held in registers
- * as a 32 x 32 decomposition with one exchange through LDS); bit 1:
+ * (lengths 1024 and 2048, not with bit 0: 32 or 16 columns per tile held in
+ * registers as a 32 x 32 or 32 x 64 decomposition with one exchange through
+ * LDS); bit 1:
  * nontemporal global loads and stores (they pay on long strides, where each
  * line is touched once).  chunk = consecutive tiles given to one XCD in the
  * tile order (1..1024, default 16).  Narrow and wide tiles compute the same

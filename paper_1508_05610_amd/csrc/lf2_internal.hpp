@@ -88,7 +88,7 @@ hipError_t launch_x_c2c(int len, int nc, int sign, const XArgs &a, hipStream_t s
 hipError_t launch_x_c2c_shfl(int sign, bool dpp, const XArgs &a, hipStream_t s);
 // variant bit 0: STileW (wide tiles, plain passes of s_wide_supported
 // lengths) instead of STile (narrow, any pass); bit 2: the register tile
-// (k_strided_r: 32 x 32 decomposition, plain passes of s_reg_supported
+// (k_strided_r: 32 x Q decomposition, plain passes of s_reg_supported
 // lengths; not with bit 0); bit 1: nontemporal global loads and stores
 // (plain passes).  EPI_TSTORE / EPI_TLOAD in a.epi select
 // STileT (z pass to / from the paper's c2c k-space order) whatever the

@@ -227,10 +227,12 @@ def test_wide_tiles_match_oracle_and_narrow(lf2, shape, kind, ncomp):
     assert rel_l2(Fw.cpu().numpy(), Fn.cpu().numpy()) <= 1e-6
     assert rel_l2(bw.cpu().numpy(), bn.cpu().numpy()) <= 1e-6
 
-# lines of 1024 points along y or z in the register tile (32 columns held as a
-# 32 x 32 decomposition): column counts that leave the last tile ragged
+# lines of 1024 or 2048 points along y or z in the register tile (32 or 16
+# columns held as a 32 x 32 or 32 x 64 decomposition): column counts that
+# leave the last tile ragged
 REG_CASES = [((8, 1024, 40), 1, 1), ((10, 6, 1024), 1, 3), ((12, 1024, 6), 0, 1),
-             ((6, 10, 1024), 0, 2), ((2, 1024, 1024), 1, 1)]
+             ((6, 10, 1024), 0, 2), ((2, 1024, 1024), 1, 1), ((6, 2048, 5), 1, 1),
+             ((4, 3, 2048), 1, 3), ((8, 2048, 3), 0, 1), ((10, 4, 2048), 0, 1)]
 
 
 @pytest.mark.parametrize("shape,kind,ncomp", REG_CASES)
@@ -239,7 +241,7 @@ def test_register_tile_matches_oracle_and_narrow(lf2, shape, kind, ncomp):
     pn = lf2.Plan(shape, kind, ncomp=ncomp)
     pr = lf2.Plan(shape, kind, ncomp=ncomp)
     for axis in (1, 2):
-        if shape[axis] == 1024:  # plain and nontemporal accesses
+        if shape[axis] in (1024, 2048):  # plain and nontemporal accesses
             v = 4 if axis == 1 else 6
             pr.set_tuning(axis, v, chunk=8)
             assert pr.tuning(axis)[:2] == (v, 8)
