@@ -25,17 +25,17 @@ namespace lf2 {
 namespace {
 
 constexpr int kRThreads = 1024;
-constexpr int kRP = 32;  // points per thread; the inner DFT length
 
 template <int L>
 struct RegTile {
-    static constexpr int Q = L / kRP;         // outer DFT length (range of j)
-    static constexpr int B = kRThreads / Q;   // columns per tile
-    static constexpr int H = Q / kRP;         // threads per (column, k1)
+    static constexpr int P = 32;                  // points per thread; inner DFT length
+    static constexpr int Q = L / P;               // outer DFT length (range of j)
+    static constexpr int B = kRThreads / Q;       // columns per tile
+    static constexpr int H = Q / P;               // threads per (column, k1)
     // exchange rows: value (k1, j, c) at k1 * ROW + j * B + c; the 32-word
     // pad puts the two k1 rows a wave reads in different banks
     static constexpr int ROW = Q * B + 32;
-    static_assert(Q * kRP == L && (H == 1 || H == 2), "1024 or 2048 points");
+    static_assert(Q * P == L && (H == 1 || H == 2), "1024 or 2048 points");
 };
 
 // The value of the adjacent lane (lane ^ 1), by a DPP quad permutation.
@@ -48,8 +48,8 @@ template <int L, int S, bool NTM>
 __global__ __launch_bounds__(kRThreads) void k_strided_r(SArgs a)
 {
     using T = RegTile<L>;
-    constexpr int B = T::B, H = T::H, ROW = T::ROW;
-    __shared__ float ex[kRP * ROW];
+    constexpr int P = T::P, B = T::B, H = T::H, ROW = T::ROW;
+    __shared__ float ex[P * ROW];
     __shared__ c32 tw[L];
     const int tid = threadIdx.x;
     load_table(tw, a.tw, L, tid, kRThreads);
@@ -71,40 +71,40 @@ __global__ __launch_bounds__(kRThreads) void k_strided_r(SArgs a)
         const int64_t f = t * B + c;
         // a column past the end reads column 0 (in bounds) and is not stored
         const int64_t base = f < a.ncols ? col_base(a, f) : 0;
-        c32 v[kRP];
-        gload_pts<kRP, NTM>(v, (const c32 *)a.in + base + (int64_t)j * a.stride,
+        c32 v[P];
+        gload_pts<P, NTM>(v, (const c32 *)a.in + base + (int64_t)j * a.stride,
                             (int64_t)T::Q * a.stride, true);
-        Dft<kRP, S>::run(v);  // v[k1] = inner DFT of x[j + Q r] over r
+        Dft<P, S>::run(v);  // v[k1] = inner DFT of x[j + Q r] over r
 #pragma unroll
-        for (int k1 = 1; k1 < kRP; ++k1) {
+        for (int k1 = 1; k1 < P; ++k1) {
             c32 w = tw[j * k1];  // W_L^{j k1}, j k1 < L
             if (S > 0) w = conjg(w);
             v[k1] = mul(v[k1], w);
         }
         // second half: thread (c2, k1, h) takes j = H j' + h, j' in [0, 32)
         const int h = ot % H, c2 = (ot / H) % B, k1 = ot / (H * B);
-        float re[kRP];
+        float re[P];
 #pragma unroll
-        for (int q = 0; q < kRP; ++q) ex[q * ROW + j * B + c] = v[q].x;
+        for (int q = 0; q < P; ++q) ex[q * ROW + j * B + c] = v[q].x;
         __syncthreads();
 #pragma unroll
-        for (int jj = 0; jj < kRP; ++jj) re[jj] = ex[k1 * ROW + (H * jj + h) * B + c2];
+        for (int jj = 0; jj < P; ++jj) re[jj] = ex[k1 * ROW + (H * jj + h) * B + c2];
         __syncthreads();
 #pragma unroll
-        for (int q = 0; q < kRP; ++q) ex[q * ROW + j * B + c] = v[q].y;
+        for (int q = 0; q < P; ++q) ex[q * ROW + j * B + c] = v[q].y;
         __syncthreads();
 #pragma unroll
-        for (int jj = 0; jj < kRP; ++jj) v[jj] = c32{re[jj], ex[k1 * ROW + (H * jj + h) * B + c2]};
+        for (int jj = 0; jj < P; ++jj) v[jj] = c32{re[jj], ex[k1 * ROW + (H * jj + h) * B + c2]};
         __syncthreads();  // the next tile rewrites ex
-        Dft<kRP, S>::run(v);  // v[k2'] = DFT over j' of the values of this h
+        Dft<P, S>::run(v);  // v[k2'] = DFT over j' of the values of this h
         if constexpr (H == 2) {
             // outputs k2' + 32 k3: Y0 + (-1)^k3 W_Q^{k2'} Y1; lane h gives
             // its own term (Y0, or W Y1: the twiddle is W_L^0 = 1 for h = 0)
             // and keeps k3 = h, so it adds (h = 0) or subtracts (h = 1) it
             const float sg = h ? -1.f : 1.f;
 #pragma unroll
-            for (int k2 = 0; k2 < kRP; ++k2) {
-                c32 w = tw[kRP * k2 * h];  // W_L^{32 k2' h} = W_Q^{k2' h}
+            for (int k2 = 0; k2 < P; ++k2) {
+                c32 w = tw[P * k2 * h];  // W_L^{P k2' h} = W_Q^{k2' h}
                 if (S > 0) w = conjg(w);
                 const c32 own = mul(v[k2], w);
                 const c32 p = c32{lane_swap(own.x), lane_swap(own.y)};
@@ -114,8 +114,8 @@ __global__ __launch_bounds__(kRThreads) void k_strided_r(SArgs a)
         const int64_t f2 = t * B + c2;
         if (f2 < a.ncols && store) {
             const int64_t base2 = col_base(a, f2);
-            gstore_pts<kRP, NTM>(v, (c32 *)a.out + base2 + (int64_t)(k1 + kRP * kRP * h) * a.stride,
-                                 (int64_t)kRP * a.stride);
+            gstore_pts<P, NTM>(v, (c32 *)a.out + base2 + (int64_t)(k1 + P * P * h) * a.stride,
+                                 (int64_t)P * a.stride);
         }
     }
 }
