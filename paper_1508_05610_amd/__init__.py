@@ -76,8 +76,9 @@ class Plan:
         self.ksize, self.kstride = lf2_fft_kspace(self.handle)
 
     def tuning(self, axis):
-        """(variant, chunk, us_default, us_tuned): the strided pass along axis 1 or 2, or
-        the x pass's stage exchange (axis 0: 0 LDS, 1 ds_bpermute, 2 DPP)."""
+        """(variant, chunk, us_default, us_tuned): the strided pass along axis 1 or 2, the
+        x pass's stage exchange (axis 0: 0 LDS, 1 ds_bpermute, 2 DPP), or the fused
+        Poisson pass (axis 3: 0 LDS stages, 1 register tile)."""
         return _lib.lf2_plan_get_tuning(self.handle, axis)
 
     def set_tuning(self, axis, variant, chunk=16):

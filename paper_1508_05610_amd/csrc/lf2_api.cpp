@@ -528,12 +528,15 @@ lf2_status run_strided(const lf2_plan_s *p, int axis, int sign, const SArgs &a, 
                         p->len[axis], hipGetErrorString(e));
         return LF2_OK;
     }
-    const int variant = (tr || epi) ? 0 : p->svar[axis];
+    const bool freg = epi && sign < 0 && (a.epi & EPI_POISSON) && p->fvar == 1 &&
+                      fused_reg_supported(p->len[axis]);
+    const int variant = tr ? 0 : epi ? (freg ? 8 : 0) : p->svar[axis];
     const int ntm = ((variant & 2) || epi) ? 1 : 0;  // the fused pass always streams
     // "<kernel symbol> <pass>": the symbol part matches the profiler's name
     const std::string sym = tr ? kname("k_strided_t<%d,%d>", p->len[axis], sign)
+                            : freg ? kname("k_fused_r<%d>", a.mt.k2z_unit > 0.0 ? 1 : 2)
                             : (variant & 1) ? kname("k_strided_w<%d,%d,%d>", p->len[axis], sign, ntm)
-                            : (variant & 4) ? kname("k_strided_r<%d,%d>", sign, ntm)
+                            : (variant & 4) ? kname("k_strided_r<%d,%d,%d>", p->len[axis], sign, ntm)
                                             : kname("k_strided<%d,%d,%d,%d>", p->len[axis], sign,
                                                     epi ? 1 : 0, ntm);
     const int t = prof::begin(sym + kname(" %s%s%s %lldx%lldx%lld/%d", axis == 1 ? "y" : "z",
@@ -908,6 +911,8 @@ lf2_status lf2_fft_plan(lf2_plan *out, const lf2_lattice *lat, int32_t ncomp, lf
         const std::vector<GSched> cand = sched_candidates(lens[i]);
         if (!cand.empty()) p->sched[i] = cand[0];
     }
+    // the fused Poisson pass keeps its tile in registers where it can
+    p->fvar = fused_reg_supported(lens[2]) ? 1 : 0;
     if (p->gen_only[0] && (p->gen_rb = gx_rows(p, lens[0], ncomp)) < 1) {
         delete p;
         return fail(LF2_ERR_UNSUPPORTED, "x lines of %d points with %d components do not fit a tile",
@@ -981,7 +986,14 @@ lf2_status lf2_plan_get_tuning(lf2_plan p, int32_t axis, int32_t *variant, int32
                                double *us_default, double *us_tuned)
 {
     if (!p) return fail(LF2_ERR_INVALID_ARG, "plan is NULL");
-    if (axis < 0 || axis > 2) return fail(LF2_ERR_INVALID_ARG, "axis %d is not 0, 1 or 2", axis);
+    if (axis < 0 || axis > 3) return fail(LF2_ERR_INVALID_ARG, "axis %d is not 0, 1, 2 or 3", axis);
+    if (axis == 3) {
+        if (variant) *variant = p->fvar;
+        if (chunk) *chunk = 16;
+        if (us_default) *us_default = -1.0;
+        if (us_tuned) *us_tuned = -1.0;
+        return LF2_OK;
+    }
     if (axis == 0) {
         if (variant) *variant = p->gen[0] ? -1 : p->xx;
         if (chunk) *chunk = 0;
@@ -1057,7 +1069,15 @@ lf2_status lf2_plan_set_tuning(lf2_plan p, int32_t axis, int32_t variant, int32_
         p->xx = variant;
         return LF2_OK;
     }
-    if (axis != 1 && axis != 2) return fail(LF2_ERR_INVALID_ARG, "axis %d is not 0, 1 or 2", axis);
+    if (axis == 3) {
+        if (variant < 0 || variant > 1) return fail(LF2_ERR_INVALID_ARG, "variant %d outside [0, 1]", variant);
+        if (variant == 1 && !fused_reg_supported(p->len[2]))
+            return fail(LF2_ERR_UNSUPPORTED, "no register tile for the fused pass over %d points",
+                        p->len[2]);
+        p->fvar = variant;
+        return LF2_OK;
+    }
+    if (axis != 1 && axis != 2) return fail(LF2_ERR_INVALID_ARG, "axis %d is not 0, 1, 2 or 3", axis);
     if (variant < 0 || variant > 7) return fail(LF2_ERR_INVALID_ARG, "variant %d outside [0, 7]", variant);
     if (chunk < 1 || chunk > 1024) return fail(LF2_ERR_INVALID_ARG, "chunk %d outside [1, 1024]", chunk);
     if (p->gen_only[axis])

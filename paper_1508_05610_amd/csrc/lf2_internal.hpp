@@ -98,6 +98,12 @@ hipError_t launch_strided(int len, int sign, const SArgs &a, int grid_cap, hipSt
                           int *grid_used, int variant = 0, int chunk = 16);
 bool s_wide_supported(int len);
 bool s_reg_supported(int len);
+// The fused Poisson pass (EPI_POISSON, any P(k) flags) with the tile in
+// registers (k_fused_r): 512-point lines.  launch_strided selects it with
+// variant bit 3 on such passes.
+bool fused_reg_supported(int len);
+hipError_t launch_fused_reg(int len, const SArgs &a, size_t shm, int grid_cap, hipStream_t s,
+                            int *grid_used);
 hipError_t launch_strided_reg(int len, int sign, const SArgs &a, int grid_cap, hipStream_t s,
                               int *grid_used, int chunk, bool ntm);
 // LDS histogram copies of a fused last-axis tile of length len binning into

@@ -134,6 +134,11 @@ hipError_t launch_strided(int len, int sign, const SArgs &a_in, int grid_cap, hi
         if (epi) return hipErrorInvalidValue;
         return launch_transposed(len, sign, a, grid_cap, s, grid_used);
     }
+    if (variant & 8) {
+        if (!epi || sign > 0 || !(a.epi & EPI_POISSON) || !fused_reg_supported(len))
+            return hipErrorInvalidValue;
+        return launch_fused_reg(len, a, shm, grid_cap, s, grid_used);
+    }
     const bool ntm = (variant & 2) != 0;
     if (variant & 4) {
         if (epi || (variant & 1) || !s_reg_supported(len)) return hipErrorInvalidValue;

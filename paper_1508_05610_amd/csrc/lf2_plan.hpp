@@ -45,6 +45,7 @@ struct lf2_plan_s {
     int64_t ntot = 0;  // N0 N1 N2
     int len[3] = {0, 0, 0};
     int svar[3] = {0, 0, 0};              // strided tile variant per axis (1, 2)
+    int fvar = 0;                         // fused last-axis pass: 0 LDS stages, 1 register tile
     int xx = 0;                           // x pass exchange (c2c, N0 = 64, one component):
                                           // 0 LDS, 1 ds_bpermute, 2 DPP
     int schunk[3] = {16, 16, 16};         // tiles per XCD chunk per axis

@@ -219,3 +219,43 @@ def test_parseval_many_x_blocks(lf2):
     assert np.array_equal(ct.cpu().numpy(), oct_)
     assert_close(pk.cpu().numpy(), opk, shape)
     assert_close(phi.cpu().numpy(), oracle.poisson(f64), shape)
+
+
+# the fused Poisson pass with its tile in registers (tuning axis 3, 512-point
+# z lines): phi and P(k) (of rho, of phi, with the Parseval sums) against the
+# oracle and against the LDS-staged tile, both k^2 kinds, ragged column counts
+@pytest.mark.parametrize("shape,nbins,flags,dx", [
+    ((16, 8, 512), 24, 0, 1.0), ((24, 10, 512), 32, 1, 0.5), ((10, 6, 512), 7, 2, 1.0),
+    ((64, 32, 512), 128, 0, 0.37), ((48, 20, 512), 0, 1, 1.0)])
+def test_fused_register_tile(lf2, shape, nbins, flags, dx):
+    print(f"case fused register tile {shape} nbins={nbins} flags={flags} dx={dx}", flush=True)
+    f = real_field(shape, seed=23)[0][..., 0]
+    f64 = f.astype(np.float64)
+    x = torch.from_numpy(f).to(dev())
+    fl = (lf2.LF2_POISSON_DISCRETE_K2 if flags & 1 else 0) | (lf2.LF2_PK_OF_PHI if flags & 2 else 0)
+    pr = lf2.Plan(shape, lf2.LF2_R2C)
+    assert pr.tuning(3)[0] == 1  # the default at 512 points
+    pl = lf2.Plan(shape, lf2.LF2_R2C)
+    pl.set_tuning(3, 0)
+    assert pl.tuning(3)[0] == 0
+    pv_on = nbins > 0 and not flags & 2  # Parseval sums are those of rho
+    res_r = pr.poisson(x, dx=dx, flags=fl, nbins=nbins, parseval=pv_on)
+    res_l = pl.poisson(x, dx=dx, flags=fl, nbins=nbins, parseval=pv_on)
+    torch.cuda.synchronize()
+    phi_r = (res_r[0] if nbins else res_r).cpu().numpy()
+    phi_l = (res_l[0] if nbins else res_l).cpu().numpy()
+    ref_phi = oracle.poisson(f64, dx=dx, k2mode=flags & 1)
+    assert_close(phi_r, ref_phi, shape, "phi")
+    assert rel_l2(phi_r, phi_l) <= 1e-6
+    if nbins:
+        src = ref_phi if flags & 2 else f64
+        opk, okm, oct_ = oracle.power_spectrum(oracle.r2c(src), shape, nbins, dx=dx)
+        pk, km, ct = (t.cpu().numpy() for t in res_r[1:4])
+        assert np.array_equal(ct, oct_)
+        assert_close(pk, opk, shape, "pk")
+        assert rel_l2(km, okm) <= 1e-12
+        if pv_on:
+            pv = res_r[4].cpu().numpy()
+            s2 = float(np.sum(f64 * f64))
+            assert abs(pv[0] - s2) <= 1e-12 * s2
+            assert abs(pv[1] - pv[0]) <= tol(shape) * pv[0]
