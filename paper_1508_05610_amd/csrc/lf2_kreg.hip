@@ -22,8 +22,6 @@
 
 namespace lf2 {
 
-namespace {
-
 constexpr int kRThreads = 1024;
 
 template <int L>
@@ -121,7 +119,7 @@ __global__ __launch_bounds__(kRThreads) void k_strided_r(SArgs a)
 }
 
 template <int L, bool NTM>
-void launch_r(int sign, int g, const SArgs &a, hipStream_t s)
+static void launch_r(int sign, int g, const SArgs &a, hipStream_t s)
 {
     if (sign < 0)
         hipLaunchKernelGGL((k_strided_r<L, -1, NTM>), dim3(g), dim3(kRThreads), 0, s, a);
@@ -130,7 +128,7 @@ void launch_r(int sign, int g, const SArgs &a, hipStream_t s)
 }
 
 template <int L>
-hipError_t launch_len(int sign, const SArgs &a, int grid_cap, hipStream_t s, int *grid_used,
+static hipError_t launch_len(int sign, const SArgs &a, int grid_cap, hipStream_t s, int *grid_used,
                       int chunk, bool ntm)
 {
     constexpr int B = RegTile<L>::B;
@@ -384,8 +382,6 @@ __global__ __launch_bounds__(kFThreads) __attribute__((amdgpu_waves_per_eu(4))) 
         hist_flush(nb, a.hcopies, hist, a.partial + (int64_t)blockIdx.x * (nb + 1), tid, kFThreads);
     }
 }
-
-}  // namespace
 
 bool s_reg_supported(int len) { return len == 1024 || len == 2048; }
 
