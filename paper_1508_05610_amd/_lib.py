@@ -326,12 +326,23 @@ def lf2_batch_destroy(batch: int):
     _check(load().lf2_batch_destroy(batch), "lf2_batch_destroy")
 
 
+_lattice_cache: dict = {}
+
+
 def make_request(sizes, rho_ptr: int, phi_ptr: int, dx: float = 1.0, flags: int = 0,
                  nbins: int = 0, pk_ptr: int = 0, kmean_ptr: int = 0, count_ptr: int = 0,
                  t_arrival: float = 0.0) -> lf2_request:
-    lat = lf2_lattice(3, 0, (ctypes.c_int64 * 3)(*[int(v) for v in sizes]))
-    return lf2_request(lat, rho_ptr or None, phi_ptr or None, float(dx), int(flags), int(nbins),
-                       pk_ptr or None, kmean_ptr or None, count_ptr or None, float(t_arrival))
+    # the lattice structs are cached per size (a request is built on every
+    # submission, and its cost is part of the request's latency); pointer
+    # fields take integers, 0 being NULL
+    key = tuple(sizes)
+    lat = _lattice_cache.get(key)
+    if lat is None:
+        lat = lf2_lattice(3, 0, (ctypes.c_int64 * 3)(*[int(v) for v in sizes]))
+        if len(_lattice_cache) < 4096:
+            _lattice_cache[key] = lat
+    return lf2_request(lat, rho_ptr, phi_ptr, dx, flags, nbins, pk_ptr, kmean_ptr, count_ptr,
+                       t_arrival)
 
 
 def lf2_server_create(budget_bytes: int, max_slots: int, nstreams: int, max_queue: int) -> int:
