@@ -255,7 +255,12 @@ lf2_status lf2_poisson_solve_noalloc(lf2_plan p, const float *rho, float *phi, d
  *   count = sum w,  pk = (dx^3/N) sum w |F|^2 / count,
  *   kmean = sum w |k| / count,  |k| = 2 pi sqrt(q) / (L dx),
  * with w = 1 at kx in {0, N0/2} and 2 elsewhere for an r2c plan (half
- * spectrum) and w = 1 for a c2c plan.  Empty bins give 0.  Sums are FP64.
+ * spectrum) and w = 1 for a c2c plan.  Empty bins give 0.  Sums are FP64
+ * (of FP32 |F|^2 in the register-tile Poisson pass, tuning axis 3).  Repeated
+ * calls give the same bits where each wave of a block bins into its own LDS
+ * histogram, summed in a fixed order (e.g. up to 169 bins on 512-point z
+ * lines); with more bins the waves of a block share one histogram and the
+ * last bits of the sums can differ from call to call.
  * field_is_kspace = 0: `field` is a real-space field (r2c: real; c2c:
  * complex), transformed on the way without being modified;
  * field_is_kspace = 1: `field` is already the spectrum.  ncomp must be 1.
