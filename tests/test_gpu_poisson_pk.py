@@ -259,3 +259,20 @@ def test_fused_register_tile(lf2, shape, nbins, flags, dx):
             s2 = float(np.sum(f64 * f64))
             assert abs(pv[0] - s2) <= 1e-12 * s2
             assert abs(pv[1] - pv[0]) <= tol(shape) * pv[0]
+
+
+def test_fused_register_tile_settings(lf2):
+    """Tuning axis 3 is the fused pass's tile: the register tile only for
+    512-point z lines, variants 0 and 1 only; the default follows the length."""
+    p = lf2.Plan((16, 8, 64), lf2.LF2_R2C)
+    assert p.tuning(3)[0] == 0
+    with pytest.raises(lf2.LF2Error) as ei:
+        p.set_tuning(3, 1)
+    assert ei.value.status == lf2.LF2_ERR_UNSUPPORTED
+    q = lf2.Plan((16, 8, 512), lf2.LF2_R2C)
+    assert q.tuning(3)[0] == 1
+    with pytest.raises(lf2.LF2Error) as ei:
+        q.set_tuning(3, 2)
+    assert ei.value.status == lf2.LF2_ERR_INVALID_ARG
+    q.set_tuning(3, 0)
+    assert q.tuning(3)[0] == 0
