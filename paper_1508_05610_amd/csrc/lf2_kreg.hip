@@ -146,45 +146,60 @@ static hipError_t launch_len(int sign, const SArgs &a, int grid_cap, hipStream_t
 // ---------------------------------------------------------------- fused pass
 // The fused last-axis Poisson pass (forward z transform, optional P(k) of
 // the modes, the FP64 Poisson scale, optional P(k) after it, backward z
-// transform) over 512-point lines with the tile in registers: 16 columns,
-// 512 threads, 16 points a thread.  The line splits as n = j + 32 r
-// (r in [0, 16), j in [0, 32)), k = k1 + 16 k2 (k1 in [0, 16), k2 in
-// [0, 32)).  Thread (c, j) loads points j + 32 r, takes the 16-point DFT
-// over r and multiplies by W_512^{j k1}; through LDS, the lane pair
-// (c, k1, h = 0, 1) receives the even (h = 0) and odd (h = 1) j, takes the
-// 16-point DFT over them and finishes the 32-point DFT over j with one
-// radix-2 step across the pair (DPP swap), so lane h holds the modes
-// kz = k1 + 16 k2' + 256 h (k2' in [0, 16)).  The scale is applied there;
-// the backward transform is the conjugate transpose of these steps in
-// reverse order (radix-2 step, 16-point DFTs, the exchange back, conjugate
-// twiddles, 16-point DFTs), which is the unnormalised inverse DFT.
+// transform) with the tile in registers: B columns, 512 threads, P points a
+// thread, over lines of L = P Q points (256 = 16 x 16, 512 = 16 x 32,
+// 1024 = 32 x 32).  The line splits as n = j + Q r (r in [0, P), j in
+// [0, Q)), k = k1 + P k2 (k1 in [0, P), k2 in [0, Q)).  Thread (c, j) loads
+// points j + Q r, takes the P-point DFT over r and multiplies by
+// W_L^{j k1}; through LDS, thread (c, k1) receives the Q values of j and
+// takes the Q-point DFT over them -- at L = 512 (Q = 2P) as a lane pair
+// (c, k1, h = 0, 1) taking the 16-point DFTs over the even (h = 0) and odd
+// (h = 1) j and one radix-2 step across the pair (DPP swap), so that lane h
+// holds the modes kz = k1 + 16 k2' + 256 h (k2' in [0, 16)).  The scale is
+// applied there; the backward transform is the conjugate transpose of these
+// steps in reverse order (radix-2 step, DFTs over k2', the exchange back,
+// conjugate twiddles, DFTs over k1), which is the unnormalised inverse DFT.
 // P(k): each mode's power |F|^2 (FP32) goes to an LDS table in natural
 // order, and the binning walk over it (the walk of the LDS-staged fused
 // tile: thread (c, j) takes |n_z| in [j EH, j EH + EH) and both modes of
 // each, q growing by integer steps, FP64 sums into the wave's histogram)
 // runs at the start of the next tile, while that tile's loads are in
 // flight; the last tile's walk follows the loop.  The exchanges go through
-// LDS in halves (real parts, then imaginary parts), so the exchange (32 KB)
-// and the power table (32 KB) leave room for two blocks per CU.  (Adding
-// the two powers of each |n_z| into one slot with LDS float atomics, to
-// halve the walk's reads, took the pass from 274 to 545 us.)
-constexpr int kFL = 512, kFP = 16, kFQ = 32, kFB = 16, kFThreads = 512;
-constexpr int kFMH = kFL / 2;                                        // largest |n_z|
-constexpr int kFEH = (kFMH + 1 + kFThreads / kFB - 1) / (kFThreads / kFB);  // |n_z| per thread
+// LDS in halves (real parts, then imaginary parts): at L <= 512 the exchange
+// (32 KB) and the power table (32 KB) leave room for two blocks per CU.
+// (Adding the two powers of each |n_z| into one slot with LDS float
+// atomics, to halve the walk's reads, took the 512-point pass from 274 to
+// 545 us.)
+constexpr int kFThreads = 512;
+
+template <int L>
+struct FusedTile {
+    static constexpr int P = L == 1024 ? 32 : 16;  // points a thread
+    static constexpr int Q = L / P;                // the outer DFT's length
+    static constexpr int H = Q / P;                // lanes per (column, k1)
+    static constexpr int B = kFThreads / Q;        // columns
+    static constexpr int MH = L / 2;               // largest |n_z|
+    static constexpr int RPT = kFThreads / B;      // walk rows (= Q)
+    static constexpr int EH = (MH + 1 + RPT - 1) / RPT;  // |n_z| a thread walks
+    static constexpr int LDS = (2 * L * B) * 4 + L * 8;  // exchange + powers + twiddles
+    static_assert(P * Q == L && (H == 1 || H == 2) && B * P * H == kFThreads, "tile shape");
+};
 
 // The binning walk of column col over |n_z| in [rg EH, rg EH + EH), from
 // the power table pw[kz * B + col] (both modes kz and L - kz of each |n_z|).
+template <int L>
 __device__ __forceinline__ void fused_walk(const SArgs &a, const float *pw, int col, int rg, int kx,
                                            bool corner, uint32_t qxy, bool valid, double *hist,
                                            const BinEdge *edges)
 {
+    using T = FusedTile<L>;
     const int nb = a.mt.nbins;
     const float cq = (float)((double)nb * nb / a.mt.qmax);
     const double wgt = (a.mt.half && !(kx == 0 || 2 * kx == a.mt.n0)) ? 2.0 : 1.0;
     const uint32_t qu = a.mt.qz_unit;
     const bool walk1 = a.mt.walk1 != 0;
-    const int m0 = rg * kFEH;
-    const int n = kFMH + 1 - m0 < kFEH ? kFMH + 1 - m0 : kFEH;  // may be <= 0
+    const int m0 = rg * T::EH;
+    const int n = T::MH + 1 - m0 < T::EH ? T::MH + 1 - m0 : T::EH;  // may be <= 0
     if (!valid || n <= 0) return;
     uint32_t q = qxy + sq24(m0) * qu;
     uint32_t dq = (uint32_t)(2 * m0 + 1) * qu;
@@ -201,12 +216,12 @@ __device__ __forceinline__ void fused_walk(const SArgs &a, const float *pw, int 
     }
     double acc = 0.0;
 #pragma unroll 3
-    for (int e = 0; e < kFEH; ++e) {
+    for (int e = 0; e < T::EH; ++e) {
         if (e >= n) break;
         const int m = m0 + e;
-        const bool two = m != 0 && 2 * m != kFL;  // the partner mode L - m
-        const float pu = pw[m * kFB + col];
-        const float pv = two ? pw[(kFL - m) * kFB + col] : 0.f;
+        const bool two = m != 0 && 2 * m != L;  // the partner mode L - m
+        const float pu = pw[m * T::B + col];
+        const float pv = two ? pw[(L - m) * T::B + col] : 0.f;
         if (q >= hi) {
             atomicAdd(&hist[b], wgt * acc);
             acc = 0.0;
@@ -223,13 +238,16 @@ __device__ __forceinline__ void fused_walk(const SArgs &a, const float *pw, int 
     atomicAdd(&hist[b], wgt * acc);
 }
 
-// The powers |F|^2 (FP32) of the modes kz = k1 + 16 k2' + 256 h a lane
+// The powers |F|^2 (FP32) of the modes kz = k1 + P (k2' + P h) a lane
 // holds, into the table in natural order.
-__device__ __forceinline__ void put_powers(float *pw, const c32 (&v)[kFP], int k1, int h, int c2)
+template <int L>
+__device__ __forceinline__ void put_powers(float *pw, const c32 (&v)[FusedTile<L>::P], int k1, int h,
+                                           int c2)
 {
+    using T = FusedTile<L>;
 #pragma unroll
-    for (int k2 = 0; k2 < kFP; ++k2)
-        pw[(k1 + kFP * k2 + 256 * h) * kFB + c2] = fmaf(v[k2].x, v[k2].x, v[k2].y * v[k2].y);
+    for (int k2 = 0; k2 < T::P; ++k2)
+        pw[(k1 + T::P * (k2 + T::P * h)) * T::B + c2] = fmaf(v[k2].x, v[k2].x, v[k2].y * v[k2].y);
 }
 
 // The walk's column data for column f of the (kx, ky) plane.
@@ -244,17 +262,20 @@ __device__ __forceinline__ void fused_col(const SArgs &a, int64_t f, bool valid,
     qxy = a.mt.qx_unit * sq24(mx) + a.mt.qy_unit * sq24(my);
 }
 
-template <int K2>
-__global__ __launch_bounds__(kFThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_fused_r(SArgs a)
+template <int L, int K2>
+__global__ __launch_bounds__(kFThreads) __attribute__((amdgpu_waves_per_eu(L >= 1024 ? 2 : 4)))
+void k_fused_r(SArgs a)
 {
+    using T = FusedTile<L>;
+    constexpr int P = T::P, Q = T::Q, H = T::H, B = T::B;
     constexpr bool CONT = K2 == 1;
-    constexpr int ROWX = kFQ * kFB;           // exchange words per k1
-    __shared__ float ex[kFP * ROWX];          // 32 KB: one half of the exchange
-    __shared__ float pw[kFL * kFB];           // 32 KB: the powers, natural order
-    __shared__ c32 tw[kFL];
+    constexpr int ROWX = Q * B;               // exchange words per k1
+    __shared__ float ex[P * ROWX];            // one half of the exchange
+    __shared__ float pw[L * B];               // the powers, natural order
+    __shared__ c32 tw[L];
     extern __shared__ double dyn[];           // hist[hcopies][nbins + 1], edges[nbins + 1]
     const int tid = threadIdx.x;
-    load_table(tw, a.tw, kFL, tid, kFThreads);
+    load_table(tw, a.tw, L, tid, kFThreads);
     const bool pk = (a.epi & (EPI_PK | EPI_PK_AFTER)) != 0;
     const bool pk_after = (a.epi & EPI_PK_AFTER) != 0;
     const int nb = a.mt.nbins;
@@ -264,7 +285,7 @@ __global__ __launch_bounds__(kFThreads) __attribute__((amdgpu_waves_per_eu(4))) 
     __syncthreads();
     double *wh = hist + (a.hcopies > 1 ? (tid >> 6) * (nb + 1) : 0);  // this wave's histogram
     const bool store = (a.epi & EPI_STORE) != 0;
-    const int64_t ntiles = (a.ncols + kFB - 1) / kFB;
+    const int64_t ntiles = (a.ncols + B - 1) / B;
     const int64_t K = a.xcd_chunk;  // the XCD-aware walk of k_strided
     const int64_t span = (ntiles + 8 * K - 1) / (8 * K) * (8 * K);
     int64_t tprev = -1;  // the tile whose powers wait in pw
@@ -274,52 +295,54 @@ __global__ __launch_bounds__(kFThreads) __attribute__((amdgpu_waves_per_eu(4))) 
         if (t >= ntiles) continue;  // uniform over the block
         const int ot = opaque_tid<true>(tid);
         // thread (c, j): loads, stores and the binning walk (as thread (col, rg))
-        const int c = ot % kFB, j = ot / kFB;
-        const int64_t f = t * kFB + c;
+        const int c = ot % B, j = ot / B;
+        const int64_t f = t * B + c;
         const bool valid = f < a.ncols;
         // a column past the end reads column 0 (in bounds) and is not stored
         const int64_t base = valid ? col_base(a, f) : 0;
-        c32 v[kFP];
-        gload_pts<kFP, true>(v, (const c32 *)a.in + base + (int64_t)j * a.stride,
-                             (int64_t)kFQ * a.stride, true);
+        c32 v[P];
+        gload_pts<P, true>(v, (const c32 *)a.in + base + (int64_t)j * a.stride, (int64_t)Q * a.stride,
+                           true);
         asm volatile("" ::: "memory");  // the loads go out before the walk
         if (pk && tprev >= 0) {
-            const int64_t fp = tprev * kFB + c;
+            const int64_t fp = tprev * B + c;
             int kx;
             bool corner;
             uint32_t qxy;
             fused_col(a, fp, fp < a.ncols, kx, corner, qxy);
-            fused_walk(a, pw, c, j, kx, corner, qxy, fp < a.ncols, wh, edges);
+            fused_walk<L>(a, pw, c, j, kx, corner, qxy, fp < a.ncols, wh, edges);
         }
-        Dft<kFP, -1>::run(v);  // v[k1]
+        Dft<P, -1>::run(v);  // v[k1]
 #pragma unroll
-        for (int k1 = 1; k1 < kFP; ++k1) v[k1] = mul(v[k1], tw[j * k1]);  // W_512^{j k1}
-        // lane pair (c2, k1, h): j = 2 j' + h
-        const int h = ot & 1, c2 = (ot >> 1) % kFB, k1 = ot / (2 * kFB);
-        float re[kFP];
+        for (int k1 = 1; k1 < P; ++k1) v[k1] = mul(v[k1], tw[j * k1]);  // W_L^{j k1}
+        // thread (c2, k1, h): j = H j' + h
+        const int h = ot % H, c2 = (ot / H) % B, k1 = ot / (H * B);
+        float re[P];
 #pragma unroll
-        for (int q = 0; q < kFP; ++q) ex[q * ROWX + j * kFB + c] = v[q].x;
+        for (int q = 0; q < P; ++q) ex[q * ROWX + j * B + c] = v[q].x;
         __syncthreads();  // also: the walk above is done with pw
 #pragma unroll
-        for (int jj = 0; jj < kFP; ++jj) re[jj] = ex[k1 * ROWX + (2 * jj + h) * kFB + c2];
+        for (int jj = 0; jj < P; ++jj) re[jj] = ex[k1 * ROWX + (H * jj + h) * B + c2];
         __syncthreads();
 #pragma unroll
-        for (int q = 0; q < kFP; ++q) ex[q * ROWX + j * kFB + c] = v[q].y;
+        for (int q = 0; q < P; ++q) ex[q * ROWX + j * B + c] = v[q].y;
         __syncthreads();
 #pragma unroll
-        for (int jj = 0; jj < kFP; ++jj) v[jj] = c32{re[jj], ex[k1 * ROWX + (2 * jj + h) * kFB + c2]};
-        Dft<kFP, -1>::run(v);  // v[k2'] over the j of this h
+        for (int jj = 0; jj < P; ++jj) v[jj] = c32{re[jj], ex[k1 * ROWX + (H * jj + h) * B + c2]};
+        Dft<P, -1>::run(v);  // v[k2'] over the j of this h
         const float sg = h ? -1.f : 1.f;
+        if constexpr (H == 2) {
 #pragma unroll
-        for (int k2 = 0; k2 < kFP; ++k2) {
-            const c32 own = mul(v[k2], tw[kFP * k2 * h]);  // W_32^{k2' h}
-            const c32 p = c32{lane_swap(own.x), lane_swap(own.y)};
-            v[k2] = c32{fmaf(sg, own.x, p.x), fmaf(sg, own.y, p.y)};  // mode k1 + 16 k2' + 256 h
+            for (int k2 = 0; k2 < P; ++k2) {
+                const c32 own = mul(v[k2], tw[P * k2 * h]);  // W_Q^{k2' h}
+                const c32 p = c32{lane_swap(own.x), lane_swap(own.y)};
+                v[k2] = c32{fmaf(sg, own.x, p.x), fmaf(sg, own.y, p.y)};  // mode k1 + P (k2' + P h)
+            }
         }
-        if (pk && !pk_after) put_powers(pw, v, k1, h, c2);
+        if (pk && !pk_after) put_powers<L>(pw, v, k1, h, c2);
         {
             // the Poisson scale -1/(N k^2), FP64, rounded once with the product
-            const int64_t f2 = t * kFB + c2;
+            const int64_t f2 = t * B + c2;
             const bool valid2 = f2 < a.ncols;
             const int kx2 = valid2 ? (int)f2 % a.mt.nxk : 0, ky2 = valid2 ? (int)f2 / a.mt.nxk : 0;
             const int mx2 = 2 * kx2 <= a.mt.n0 ? kx2 : a.mt.n0 - kx2;
@@ -330,77 +353,98 @@ __global__ __launch_bounds__(kFThreads) __attribute__((amdgpu_waves_per_eu(4))) 
                 k2xy = CONT ? fma(a.mt.k2x_unit, (double)sq24(mx2), a.mt.k2y_unit * (double)sq24(my2))
                             : a.mt.k2[0][kx2] + a.mt.k2[1][ky2];
 #pragma unroll
-            for (int k2 = 0; k2 < kFP; ++k2) {
-                const int kz = k1 + kFP * k2 + 256 * h;
-                const int m = 2 * kz < kFL ? kz : kFL - kz;
+            for (int k2 = 0; k2 < P; ++k2) {
+                const int kz = k1 + P * (k2 + P * h);
+                const int m = 2 * kz < L ? kz : L - kz;
                 const double k2z = CONT ? a.mt.k2z_unit * (double)sq24(m) : a.mt.k2[2][kz];
                 const double sc = (corner2 && kz == 0) ? 0.0 : -a.mt.scale_n * rcp_f64(k2xy + k2z);
                 v[k2] = c32{(float)((double)v[k2].x * sc), (float)((double)v[k2].y * sc)};
             }
         }
-        if (pk_after) put_powers(pw, v, k1, h, c2);
-        // backward: the radix-2 step across the pair (lane 0 keeps Z0 + Z1,
-        // lane 1 gets conj(W_32^{k2'}) (Z0 - Z1)), 16-point DFTs over k2'
+        if (pk_after) put_powers<L>(pw, v, k1, h, c2);
+        if constexpr (H == 2) {
+            // backward: the radix-2 step across the pair (lane 0 keeps Z0 + Z1,
+            // lane 1 gets conj(W_Q^{k2'}) (Z0 - Z1))
 #pragma unroll
-        for (int k2 = 0; k2 < kFP; ++k2) {
-            const c32 p = c32{lane_swap(v[k2].x), lane_swap(v[k2].y)};
-            const c32 d = c32{fmaf(sg, v[k2].x, p.x), fmaf(sg, v[k2].y, p.y)};
-            v[k2] = mul(d, conjg(tw[kFP * k2 * h]));
+            for (int k2 = 0; k2 < P; ++k2) {
+                const c32 p = c32{lane_swap(v[k2].x), lane_swap(v[k2].y)};
+                const c32 d = c32{fmaf(sg, v[k2].x, p.x), fmaf(sg, v[k2].y, p.y)};
+                v[k2] = mul(d, conjg(tw[P * k2 * h]));
+            }
         }
-        Dft<kFP, +1>::run(v);  // v[j'] for j = 2 j' + h
+        Dft<P, +1>::run(v);  // v[j'] for j = H j' + h
         __syncthreads();  // the forward exchange's reads are done
 #pragma unroll
-        for (int jj = 0; jj < kFP; ++jj) ex[k1 * ROWX + (2 * jj + h) * kFB + c2] = v[jj].x;
+        for (int jj = 0; jj < P; ++jj) ex[k1 * ROWX + (H * jj + h) * B + c2] = v[jj].x;
         __syncthreads();
 #pragma unroll
-        for (int q = 0; q < kFP; ++q) re[q] = ex[q * ROWX + j * kFB + c];
+        for (int q = 0; q < P; ++q) re[q] = ex[q * ROWX + j * B + c];
         __syncthreads();
 #pragma unroll
-        for (int jj = 0; jj < kFP; ++jj) ex[k1 * ROWX + (2 * jj + h) * kFB + c2] = v[jj].y;
+        for (int jj = 0; jj < P; ++jj) ex[k1 * ROWX + (H * jj + h) * B + c2] = v[jj].y;
         __syncthreads();
 #pragma unroll
-        for (int q = 0; q < kFP; ++q) v[q] = c32{re[q], ex[q * ROWX + j * kFB + c]};
+        for (int q = 0; q < P; ++q) v[q] = c32{re[q], ex[q * ROWX + j * B + c]};
         __syncthreads();  // the next tile rewrites ex; pw is complete for its walk
 #pragma unroll
-        for (int q = 1; q < kFP; ++q) v[q] = mul(v[q], conjg(tw[j * q]));
-        Dft<kFP, +1>::run(v);  // v[r]: point j + 32 r
+        for (int q = 1; q < P; ++q) v[q] = mul(v[q], conjg(tw[j * q]));
+        Dft<P, +1>::run(v);  // v[r]: point j + Q r
         if (valid && store)
-            gstore_pts<kFP, true>(v, (c32 *)a.out + base + (int64_t)j * a.stride, (int64_t)kFQ * a.stride);
+            gstore_pts<P, true>(v, (c32 *)a.out + base + (int64_t)j * a.stride, (int64_t)Q * a.stride);
         tprev = t;
     }
     if (pk) {
         if (tprev >= 0) {
-            const int c = tid % kFB, j = tid / kFB;
-            const int64_t fp = tprev * kFB + c;
+            const int c = tid % B, j = tid / B;
+            const int64_t fp = tprev * B + c;
             int kx;
             bool corner;
             uint32_t qxy;
             fused_col(a, fp, fp < a.ncols, kx, corner, qxy);
-            fused_walk(a, pw, c, j, kx, corner, qxy, fp < a.ncols, wh, edges);
+            fused_walk<L>(a, pw, c, j, kx, corner, qxy, fp < a.ncols, wh, edges);
         }
         __syncthreads();
         hist_flush(nb, a.hcopies, hist, a.partial + (int64_t)blockIdx.x * (nb + 1), tid, kFThreads);
     }
 }
 
-bool s_reg_supported(int len) { return len == 1024 || len == 2048; }
-
-bool fused_reg_supported(int len) { return len == kFL; }
-
-hipError_t launch_fused_reg(int len, const SArgs &a, size_t shm, int grid_cap, hipStream_t s,
-                            int *grid_used)
+template <int L>
+static hipError_t launch_fused_len(SArgs a, int grid_cap, hipStream_t s, int *grid_used)
 {
-    if (len != kFL || (a.epi & EPI_POISSON) == 0) return hipErrorInvalidValue;
-    const int64_t ntiles = (a.ncols + kFB - 1) / kFB;
+    using T = FusedTile<L>;
+    // LDS per block: two blocks per CU below 1024 points, one from there on;
+    // one histogram per wave where they fit beside the tile, else one
+    const size_t budget = L >= 1024 ? 160 * 1024 : 80 * 1024;
+    const bool pk = (a.epi & (EPI_PK | EPI_PK_AFTER)) != 0;
+    const size_t row = (size_t)(a.mt.nbins + 1) * 8;
+    constexpr int kWaves = kFThreads / 64;
+    a.hcopies = pk && T::LDS + row * (kWaves + 1) <= budget ? kWaves : 1;
+    const size_t shm = pk ? row * (a.hcopies + 1) : 0;
+    if (T::LDS + shm > budget) return hipErrorInvalidValue;
+    const int64_t ntiles = (a.ncols + T::B - 1) / T::B;
     const int chunk = a.xcd_chunk;
     const int64_t span = (ntiles + 8 * chunk - 1) / (8 * chunk) * (8 * chunk);
     const int g = (int)(span < grid_cap ? span : grid_cap);
     if (grid_used) *grid_used = g;
     if (a.mt.k2z_unit > 0.0)
-        hipLaunchKernelGGL((k_fused_r<1>), dim3(g), dim3(kFThreads), shm, s, a);
+        hipLaunchKernelGGL((k_fused_r<L, 1>), dim3(g), dim3(kFThreads), shm, s, a);
     else
-        hipLaunchKernelGGL((k_fused_r<2>), dim3(g), dim3(kFThreads), shm, s, a);
+        hipLaunchKernelGGL((k_fused_r<L, 2>), dim3(g), dim3(kFThreads), shm, s, a);
     return hipGetLastError();
+}
+
+bool s_reg_supported(int len) { return len == 1024 || len == 2048; }
+
+bool fused_reg_supported(int len) { return len == 256 || len == 512 || len == 1024; }
+
+hipError_t launch_fused_reg(int len, const SArgs &a, size_t, int grid_cap, hipStream_t s,
+                            int *grid_used)
+{
+    if ((a.epi & EPI_POISSON) == 0) return hipErrorInvalidValue;
+    if (len == 256) return launch_fused_len<256>(a, grid_cap, s, grid_used);
+    if (len == 512) return launch_fused_len<512>(a, grid_cap, s, grid_used);
+    if (len == 1024) return launch_fused_len<1024>(a, grid_cap, s, grid_used);
+    return hipErrorInvalidValue;
 }
 
 hipError_t launch_strided_reg(int len, int sign, const SArgs &a, int grid_cap, hipStream_t s,
