@@ -534,7 +534,7 @@ lf2_status run_strided(const lf2_plan_s *p, int axis, int sign, const SArgs &a, 
     const int ntm = ((variant & 2) || epi) ? 1 : 0;  // the fused pass always streams
     // "<kernel symbol> <pass>": the symbol part matches the profiler's name
     const std::string sym = tr ? kname("k_strided_t<%d,%d>", p->len[axis], sign)
-                            : freg ? kname("k_fused_r<%d>", a.mt.k2z_unit > 0.0 ? 1 : 2)
+                            : freg ? kname("k_fused_r<%d,%d>", p->len[axis], a.mt.k2z_unit > 0.0 ? 1 : 2)
                             : (variant & 1) ? kname("k_strided_w<%d,%d,%d>", p->len[axis], sign, ntm)
                             : (variant & 4) ? kname("k_strided_r<%d,%d,%d>", p->len[axis], sign, ntm)
                                             : kname("k_strided<%d,%d,%d,%d>", p->len[axis], sign,
