@@ -308,6 +308,70 @@ def bench_lane_exchange(args, torch, lf2, _lib):
     return {"lane_exchange": res, "lattice": list(shape), "steps": args.steps}
 
 
+def bench_tile_variants(args, torch, lf2, _lib):
+    """The strided passes of an N^3 lattice (c2c, and r2c) forward in each
+    tile setting of the y and z passes -- narrow (0), wide (1), register
+    tile (4, lines of 1024 and 2048 points), each plain or nontemporal (+2)
+    -- and the fused Poisson + 128-bin P(k) pass in its LDS-staged (0) and
+    register (1) tile (tuning axis 3, 256-, 512- and 1024-point z lines):
+    average microseconds and algorithmic GB/s per launch from the library's
+    event records.  Inputs: torch N(0,1) on the device, seed 12."""
+    n = args.variants
+    shape = (n, n, n)
+    g = torch.Generator(device="cuda").manual_seed(12)
+    out = {"lattice": list(shape), "steps": args.steps, "strided": {}, "fused": {}}
+
+    def records(run, prefix):
+        for _ in range(args.warmup):
+            run()
+        torch.cuda.synchronize()
+        _lib.lf2_profile_enable(True)
+        _lib.lf2_profile_reset()
+        for _ in range(args.steps):
+            run()
+        torch.cuda.synchronize()
+        t = _lib.profile_table()
+        _lib.lf2_profile_enable(False)
+        return {k: {"avg_us": round(1e3 * ms_ / n_, 1),
+                    "gbps": round(by_ / n_ / (ms_ / n_ * 1e-3) / 1e9, 1)}
+                for k, (n_, ms_, by_) in t.items() if prefix(k)}
+
+    kinds = [("r2c", lf2.LF2_R2C)] + ([("c2c", lf2.LF2_C2C)] if n <= 1024 else [])
+    for name, kind in kinds:
+        if kind == lf2.LF2_C2C:
+            x = torch.randn(n, n, n, dtype=torch.complex64, device="cuda", generator=g)
+        else:
+            x = torch.randn(n, n, n, dtype=torch.float32, device="cuda", generator=g)
+        res = {}
+        for v in (0, 1, 2, 3, 4, 6):
+            plan = lf2.Plan(shape, kind)
+            try:
+                plan.set_tuning(1, v)
+                plan.set_tuning(2, v)
+            except lf2.LF2Error:
+                continue  # no such tile for this length
+            y = plan.forward(x)
+            res[str(v)] = records(lambda: plan.forward(x, out=y),
+                                  lambda k: k.startswith("k_strided"))
+            del plan, y
+            torch.cuda.empty_cache()
+        out["strided"][name] = res
+        del x
+        torch.cuda.empty_cache()
+    x = torch.randn(n, n, n, dtype=torch.float32, device="cuda", generator=g)
+    phi = torch.empty_like(x)
+    for v in (0, 1):
+        plan = lf2.Plan(shape, lf2.LF2_R2C)
+        try:
+            plan.set_tuning(3, v)
+        except lf2.LF2Error:
+            continue
+        out["fused"][str(v)] = records(lambda: plan.poisson(x, phi=phi, nbins=128),
+                                       lambda k: "+poisson" in k)
+        del plan
+    return out
+
+
 def bench_serving(args, torch, np, lf2):
     """Request serving: Poisson + 64-bin P(k) solves on cubic lattices with
     N uniform over {32, 64, 128, 256, 384}, Poisson arrivals at 200 req/s
@@ -614,6 +678,9 @@ def main():
     ap.add_argument("--only", default=None,
                     help="time one op alone (r2c_fwd, c2r_bwd, c2c_fwd_3comp, c2c_bwd_3comp, "
                          "poisson_pk, copy, field_ops) for profiler runs")
+    ap.add_argument("--variants", type=int, default=0,
+                    help="only time the tile settings of the strided and fused passes of an "
+                         "N^3 lattice (one JSON line)")
     ap.add_argument("--lane-exchange", action="store_true",
                     help="only time the x pass of a 64x1024x1024 c2c lattice with its stage "
                          "exchange through LDS, ds_bpermute and DPP (one JSON line)")
@@ -636,6 +703,9 @@ def main():
     dev = torch.device("cuda:0")
     if args.lane_exchange:
         print(json.dumps(bench_lane_exchange(args, torch, lf2, _lib)), flush=True)
+        return
+    if args.variants:
+        print(json.dumps({"tile_variants": bench_tile_variants(args, torch, lf2, _lib)}), flush=True)
         return
     if args.only == "field_ops":
         print(json.dumps({"only": args.only, **bench_field_ops(args, torch, lf2)}), flush=True)
