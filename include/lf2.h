@@ -154,7 +154,7 @@ lf2_status lf2_fft_kspace(lf2_plan p, int64_t ksize[3], int64_t kstride[3]);
  * computes the same transform up to FP32 rounding.
  * axis 3 (the fused Poisson pass of lf2_poisson_solve along z): variant 0
  * runs its transforms through LDS stage by stage, 1 (the default where the
- * z extent is 256, 512 or 1024) holds its tile in registers with one LDS
+ * z extent is 256, 512, 1024 or 2048) holds its tile in registers with one LDS
  * exchange each way and bins P(k) from FP32 mode powers
  * (LF2_ERR_UNSUPPORTED for other z extents); chunk is ignored (16 on get),
  * the microseconds are -1.  Both compute the same solve up to FP32

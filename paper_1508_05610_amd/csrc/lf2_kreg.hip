@@ -147,15 +147,15 @@ static hipError_t launch_len(int sign, const SArgs &a, int grid_cap, hipStream_t
 // The fused last-axis Poisson pass (forward z transform, optional P(k) of
 // the modes, the FP64 Poisson scale, optional P(k) after it, backward z
 // transform) with the tile in registers: B columns, 512 threads, P points a
-// thread, over lines of L = P Q points (256 = 16 x 16, 512 = 16 x 32,
-// 1024 = 32 x 32).  The line splits as n = j + Q r (r in [0, P), j in
+// thread, over lines of L = P Q points (256 = 16 x 16 over 32 columns,
+// 512 = 16 x 32 over 16, 1024 = 32 x 32 over 16, 2048 = 32 x 64 over 8).  The line splits as n = j + Q r (r in [0, P), j in
 // [0, Q)), k = k1 + P k2 (k1 in [0, P), k2 in [0, Q)).  Thread (c, j) loads
 // points j + Q r, takes the P-point DFT over r and multiplies by
 // W_L^{j k1}; through LDS, thread (c, k1) receives the Q values of j and
-// takes the Q-point DFT over them -- at L = 512 (Q = 2P) as a lane pair
-// (c, k1, h = 0, 1) taking the 16-point DFTs over the even (h = 0) and odd
-// (h = 1) j and one radix-2 step across the pair (DPP swap), so that lane h
-// holds the modes kz = k1 + 16 k2' + 256 h (k2' in [0, 16)).  The scale is
+// takes the Q-point DFT over them -- at L = 512 and 2048 (Q = 2P) as a lane
+// pair (c, k1, h = 0, 1) taking the P-point DFTs over the even (h = 0) and
+// odd (h = 1) j and one radix-2 step across the pair (DPP swap), so that
+// lane h holds the modes kz = k1 + P (k2' + P h) (k2' in [0, P)).  The scale is
 // applied there; the backward transform is the conjugate transpose of these
 // steps in reverse order (radix-2 step, DFTs over k2', the exchange back,
 // conjugate twiddles, DFTs over k1), which is the unnormalised inverse DFT.
@@ -174,7 +174,7 @@ constexpr int kFThreads = 512;
 
 template <int L>
 struct FusedTile {
-    static constexpr int P = L == 1024 ? 32 : 16;  // points a thread
+    static constexpr int P = L >= 1024 ? 32 : 16;  // points a thread
     static constexpr int Q = L / P;                // the outer DFT's length
     static constexpr int H = Q / P;                // lanes per (column, k1)
     static constexpr int B = kFThreads / Q;        // columns
@@ -435,7 +435,7 @@ static hipError_t launch_fused_len(SArgs a, int grid_cap, hipStream_t s, int *gr
 
 bool s_reg_supported(int len) { return len == 1024 || len == 2048; }
 
-bool fused_reg_supported(int len) { return len == 256 || len == 512 || len == 1024; }
+bool fused_reg_supported(int len) { return len == 256 || len == 512 || len == 1024 || len == 2048; }
 
 hipError_t launch_fused_reg(int len, const SArgs &a, size_t, int grid_cap, hipStream_t s,
                             int *grid_used)
@@ -444,6 +444,7 @@ hipError_t launch_fused_reg(int len, const SArgs &a, size_t, int grid_cap, hipSt
     if (len == 256) return launch_fused_len<256>(a, grid_cap, s, grid_used);
     if (len == 512) return launch_fused_len<512>(a, grid_cap, s, grid_used);
     if (len == 1024) return launch_fused_len<1024>(a, grid_cap, s, grid_used);
+    if (len == 2048) return launch_fused_len<2048>(a, grid_cap, s, grid_used);
     return hipErrorInvalidValue;
 }
 

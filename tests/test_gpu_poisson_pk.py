@@ -221,8 +221,8 @@ def test_parseval_many_x_blocks(lf2):
     assert_close(phi.cpu().numpy(), oracle.poisson(f64), shape)
 
 
-# the fused Poisson pass with its tile in registers (tuning axis 3, 256-, 512-
-# and 1024-point z lines): phi and P(k) (of rho, of phi, with the Parseval
+# the fused Poisson pass with its tile in registers (tuning axis 3, 256-, 512-,
+# 1024- and 2048-point z lines): phi and P(k) (of rho, of phi, with the Parseval
 # sums) against the oracle and against the LDS-staged tile, both k^2 kinds,
 # ragged column counts, and a bin count (400 on 1024-point lines) whose
 # waves share one histogram per block
@@ -230,7 +230,8 @@ def test_parseval_many_x_blocks(lf2):
     ((16, 8, 512), 24, 0, 1.0), ((24, 10, 512), 32, 1, 0.5), ((10, 6, 512), 7, 2, 1.0),
     ((64, 32, 512), 128, 0, 0.37), ((48, 20, 512), 0, 1, 1.0),
     ((16, 12, 256), 40, 0, 1.0), ((40, 9, 256), 16, 3, 0.5), ((64, 64, 256), 128, 1, 1.0),
-    ((12, 8, 1024), 64, 0, 1.0), ((20, 6, 1024), 400, 1, 0.5), ((32, 16, 1024), 0, 2, 1.0)])
+    ((12, 8, 1024), 64, 0, 1.0), ((20, 6, 1024), 400, 1, 0.5), ((32, 16, 1024), 0, 2, 1.0),
+    ((8, 4, 2048), 32, 0, 1.0), ((6, 5, 2048), 64, 3, 0.5)])
 def test_fused_register_tile(lf2, shape, nbins, flags, dx):
     print(f"case fused register tile {shape} nbins={nbins} flags={flags} dx={dx}", flush=True)
     if nbins == 0 and flags & 2:
@@ -240,7 +241,7 @@ def test_fused_register_tile(lf2, shape, nbins, flags, dx):
     x = torch.from_numpy(f).to(dev())
     fl = (lf2.LF2_POISSON_DISCRETE_K2 if flags & 1 else 0) | (lf2.LF2_PK_OF_PHI if flags & 2 else 0)
     pr = lf2.Plan(shape, lf2.LF2_R2C)
-    assert pr.tuning(3)[0] == 1  # the default at 256, 512 and 1024 points
+    assert pr.tuning(3)[0] == 1  # the default at 256, 512, 1024 and 2048 points
     pl = lf2.Plan(shape, lf2.LF2_R2C)
     pl.set_tuning(3, 0)
     assert pl.tuning(3)[0] == 0
@@ -269,14 +270,14 @@ def test_fused_register_tile(lf2, shape, nbins, flags, dx):
 
 def test_fused_register_tile_settings(lf2):
     """Tuning axis 3 is the fused pass's tile: the register tile only for
-    256-, 512- and 1024-point z lines, variants 0 and 1 only; the default
-    follows the length."""
+    256-, 512-, 1024- and 2048-point z lines, variants 0 and 1 only; the
+    default follows the length."""
     p = lf2.Plan((16, 8, 64), lf2.LF2_R2C)
     assert p.tuning(3)[0] == 0
     with pytest.raises(lf2.LF2Error) as ei:
         p.set_tuning(3, 1)
     assert ei.value.status == lf2.LF2_ERR_UNSUPPORTED
-    for z in (256, 1024):
+    for z in (256, 1024, 2048):
         assert lf2.Plan((16, 8, z), lf2.LF2_R2C).tuning(3)[0] == 1
     q = lf2.Plan((16, 8, 512), lf2.LF2_R2C)
     assert q.tuning(3)[0] == 1
