@@ -153,10 +153,12 @@ lf2_status lf2_fft_kspace(lf2_plan p, int64_t ksize[3], int64_t kstride[3]);
  * get).  LF2_PLAN_AUTOTUNE times the three on such plans.  Every setting
  * computes the same transform up to FP32 rounding.
  * axis 3 (the fused Poisson pass of lf2_poisson_solve along z): variant 0
- * runs its transforms through LDS stage by stage, 1 (the default where the
- * z extent is 256, 512, 1024 or 2048) holds its tile in registers with one LDS
- * exchange each way and bins P(k) from FP32 mode powers
- * (LF2_ERR_UNSUPPORTED for other z extents); chunk is ignored (16 on get),
+ * runs its transforms through LDS stage by stage, 1 (z extents 32 to 2048
+ * that are powers of two; the default from 64) holds its tile in registers
+ * with one LDS exchange each way and bins P(k) from FP32 mode powers
+ * (LF2_ERR_UNSUPPORTED for other z extents; a solve whose bin tables do not
+ * fit beside that tile, e.g. 4096 bins on 1024-point lines, runs variant
+ * 0); chunk is ignored (16 on get),
  * the microseconds are -1.  Both compute the same solve up to FP32
  * rounding.
  */

@@ -529,7 +529,8 @@ lf2_status run_strided(const lf2_plan_s *p, int axis, int sign, const SArgs &a, 
         return LF2_OK;
     }
     const bool freg = epi && sign < 0 && (a.epi & EPI_POISSON) && p->fvar == 1 &&
-                      fused_reg_supported(p->len[axis]);
+                      fused_reg_supported(p->len[axis]) &&
+                      fused_reg_fits(p->len[axis], (a.epi & (EPI_PK | EPI_PK_AFTER)) ? a.mt.nbins : 0);
     const int variant = tr ? 0 : epi ? (freg ? 8 : 0) : p->svar[axis];
     const int ntm = ((variant & 2) || epi) ? 1 : 0;  // the fused pass always streams
     // "<kernel symbol> <pass>": the symbol part matches the profiler's name
@@ -934,8 +935,9 @@ lf2_status lf2_fft_plan(lf2_plan *out, const lf2_lattice *lat, int32_t ncomp, lf
         const std::vector<GSched> cand = sched_candidates(lens[i]);
         if (!cand.empty()) p->sched[i] = cand[0];
     }
-    // the fused Poisson pass keeps its tile in registers where it can
-    p->fvar = fused_reg_supported(lens[2]) ? 1 : 0;
+    // the fused Poisson pass keeps its tile in registers where it can (at 32
+    // points the LDS-staged tile is as fast)
+    p->fvar = fused_reg_supported(lens[2]) && lens[2] >= 64 ? 1 : 0;
     if (p->gen_only[0] && (p->gen_rb = gx_rows(p, lens[0], ncomp)) < 1) {
         delete p;
         return fail(LF2_ERR_UNSUPPORTED, "x lines of %d points with %d components do not fit a tile",

@@ -102,6 +102,9 @@ bool s_reg_supported(int len);
 // registers (k_fused_r): 512-point lines.  launch_strided selects it with
 // variant bit 3 on such passes.
 bool fused_reg_supported(int len);
+// Whether that tile's LDS holds the binning tables of nbins bins (0: no
+// binning) beside it; where it does not, the LDS-staged tile runs.
+bool fused_reg_fits(int len, int nbins);
 hipError_t launch_fused_reg(int len, const SArgs &a, size_t shm, int grid_cap, hipStream_t s,
                             int *grid_used);
 hipError_t launch_strided_reg(int len, int sign, const SArgs &a, int grid_cap, hipStream_t s,

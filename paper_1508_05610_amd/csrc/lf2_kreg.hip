@@ -147,12 +147,13 @@ static hipError_t launch_len(int sign, const SArgs &a, int grid_cap, hipStream_t
 // The fused last-axis Poisson pass (forward z transform, optional P(k) of
 // the modes, the FP64 Poisson scale, optional P(k) after it, backward z
 // transform) with the tile in registers: B columns, 512 threads, P points a
-// thread, over lines of L = P Q points (256 = 16 x 16 over 32 columns,
-// 512 = 16 x 32 over 16, 1024 = 32 x 32 over 16, 2048 = 32 x 64 over 8).  The line splits as n = j + Q r (r in [0, P), j in
+// thread, over lines of L = P Q points (32 = 4 x 8 over 64 columns, 64 =
+// 8 x 8 over 64, 128 = 8 x 16 over 32, 256 = 16 x 16 over 32, 512 = 16 x 32
+// over 16, 1024 = 32 x 32 over 16, 2048 = 32 x 64 over 8).  The line splits as n = j + Q r (r in [0, P), j in
 // [0, Q)), k = k1 + P k2 (k1 in [0, P), k2 in [0, Q)).  Thread (c, j) loads
 // points j + Q r, takes the P-point DFT over r and multiplies by
 // W_L^{j k1}; through LDS, thread (c, k1) receives the Q values of j and
-// takes the Q-point DFT over them -- at L = 512 and 2048 (Q = 2P) as a lane
+// takes the Q-point DFT over them -- where Q = 2P (32, 128, 512, 2048) as a lane
 // pair (c, k1, h = 0, 1) taking the P-point DFTs over the even (h = 0) and
 // odd (h = 1) j and one radix-2 step across the pair (DPP swap), so that
 // lane h holds the modes kz = k1 + P (k2' + P h) (k2' in [0, P)).  The scale is
@@ -174,7 +175,7 @@ constexpr int kFThreads = 512;
 
 template <int L>
 struct FusedTile {
-    static constexpr int P = L >= 1024 ? 32 : 16;  // points a thread
+    static constexpr int P = L >= 1024 ? 32 : L >= 256 ? 16 : L >= 64 ? 8 : 4;  // points a thread
     static constexpr int Q = L / P;                // the outer DFT's length
     static constexpr int H = Q / P;                // lanes per (column, k1)
     static constexpr int B = kFThreads / Q;        // columns
@@ -412,15 +413,16 @@ template <int L>
 static hipError_t launch_fused_len(SArgs a, int grid_cap, hipStream_t s, int *grid_used)
 {
     using T = FusedTile<L>;
-    // LDS per block: two blocks per CU below 1024 points, one from there on;
-    // one histogram per wave where they fit beside the tile, else one
+    // one histogram per wave where they fit beside the tile within the
+    // block's share of LDS (two blocks per CU below 1024 points, one from
+    // there on), else one for the block (which may then take a CU alone)
     const size_t budget = L >= 1024 ? 160 * 1024 : 80 * 1024;
     const bool pk = (a.epi & (EPI_PK | EPI_PK_AFTER)) != 0;
     const size_t row = (size_t)(a.mt.nbins + 1) * 8;
     constexpr int kWaves = kFThreads / 64;
     a.hcopies = pk && T::LDS + row * (kWaves + 1) <= budget ? kWaves : 1;
     const size_t shm = pk ? row * (a.hcopies + 1) : 0;
-    if (T::LDS + shm > budget) return hipErrorInvalidValue;
+    if (T::LDS + shm > 160 * 1024) return hipErrorInvalidValue;
     const int64_t ntiles = (a.ncols + T::B - 1) / T::B;
     const int chunk = a.xcd_chunk;
     const int64_t span = (ntiles + 8 * chunk - 1) / (8 * chunk) * (8 * chunk);
@@ -435,12 +437,39 @@ static hipError_t launch_fused_len(SArgs a, int grid_cap, hipStream_t s, int *gr
 
 bool s_reg_supported(int len) { return len == 1024 || len == 2048; }
 
-bool fused_reg_supported(int len) { return len == 256 || len == 512 || len == 1024 || len == 2048; }
+bool fused_reg_supported(int len)
+{
+    return len == 32 || len == 64 || len == 128 || len == 256 || len == 512 || len == 1024 || len == 2048;
+}
+
+template <int L>
+static bool fused_fits(int nbins)
+{
+    const size_t shm = nbins > 0 ? (size_t)(nbins + 1) * 8 * 2 : 0;  // one histogram and the edges
+    return FusedTile<L>::LDS + shm <= 160 * 1024;
+}
+
+bool fused_reg_fits(int len, int nbins)
+{
+    switch (len) {
+    case 32: return fused_fits<32>(nbins);
+    case 64: return fused_fits<64>(nbins);
+    case 128: return fused_fits<128>(nbins);
+    case 256: return fused_fits<256>(nbins);
+    case 512: return fused_fits<512>(nbins);
+    case 1024: return fused_fits<1024>(nbins);
+    case 2048: return fused_fits<2048>(nbins);
+    default: return false;
+    }
+}
 
 hipError_t launch_fused_reg(int len, const SArgs &a, size_t, int grid_cap, hipStream_t s,
                             int *grid_used)
 {
     if ((a.epi & EPI_POISSON) == 0) return hipErrorInvalidValue;
+    if (len == 32) return launch_fused_len<32>(a, grid_cap, s, grid_used);
+    if (len == 64) return launch_fused_len<64>(a, grid_cap, s, grid_used);
+    if (len == 128) return launch_fused_len<128>(a, grid_cap, s, grid_used);
     if (len == 256) return launch_fused_len<256>(a, grid_cap, s, grid_used);
     if (len == 512) return launch_fused_len<512>(a, grid_cap, s, grid_used);
     if (len == 1024) return launch_fused_len<1024>(a, grid_cap, s, grid_used);

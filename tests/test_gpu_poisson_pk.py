@@ -123,7 +123,7 @@ def test_grf_spectrum_256(lf2):
 
 
 @pytest.mark.parametrize("shape,nbins", [((64, 48, 40), 4096), ((160, 96, 64), 4096),
-                                         ((96, 160, 192), 1000)])
+                                         ((96, 160, 192), 1000), ((8, 6, 1024), 4096)])
 def test_many_bins_every_bin(lf2, shape, nbins):
     """Up to the 4096-bin maximum, on lattices whose lcm makes q large: the
     fused pass's bin of every mode must be the exact integer rule's, so each
@@ -221,8 +221,8 @@ def test_parseval_many_x_blocks(lf2):
     assert_close(phi.cpu().numpy(), oracle.poisson(f64), shape)
 
 
-# the fused Poisson pass with its tile in registers (tuning axis 3, 256-, 512-,
-# 1024- and 2048-point z lines): phi and P(k) (of rho, of phi, with the Parseval
+# the fused Poisson pass with its tile in registers (tuning axis 3, z lines of
+# 32 to 2048 points, powers of two): phi and P(k) (of rho, of phi, with the Parseval
 # sums) against the oracle and against the LDS-staged tile, both k^2 kinds,
 # ragged column counts, and a bin count (400 on 1024-point lines) whose
 # waves share one histogram per block
@@ -231,7 +231,9 @@ def test_parseval_many_x_blocks(lf2):
     ((64, 32, 512), 128, 0, 0.37), ((48, 20, 512), 0, 1, 1.0),
     ((16, 12, 256), 40, 0, 1.0), ((40, 9, 256), 16, 3, 0.5), ((64, 64, 256), 128, 1, 1.0),
     ((12, 8, 1024), 64, 0, 1.0), ((20, 6, 1024), 400, 1, 0.5), ((32, 16, 1024), 0, 2, 1.0),
-    ((8, 4, 2048), 32, 0, 1.0), ((6, 5, 2048), 64, 3, 0.5)])
+    ((8, 4, 2048), 32, 0, 1.0), ((6, 5, 2048), 64, 3, 0.5),
+    ((32, 32, 32), 16, 0, 1.0), ((10, 6, 32), 8, 2, 0.5), ((12, 10, 64), 16, 1, 1.0),
+    ((20, 6, 128), 24, 2, 1.0), ((64, 48, 128), 64, 0, 0.37)])
 def test_fused_register_tile(lf2, shape, nbins, flags, dx):
     print(f"case fused register tile {shape} nbins={nbins} flags={flags} dx={dx}", flush=True)
     if nbins == 0 and flags & 2:
@@ -241,7 +243,9 @@ def test_fused_register_tile(lf2, shape, nbins, flags, dx):
     x = torch.from_numpy(f).to(dev())
     fl = (lf2.LF2_POISSON_DISCRETE_K2 if flags & 1 else 0) | (lf2.LF2_PK_OF_PHI if flags & 2 else 0)
     pr = lf2.Plan(shape, lf2.LF2_R2C)
-    assert pr.tuning(3)[0] == 1  # the default at 256, 512, 1024 and 2048 points
+    if shape[2] >= 64:
+        assert pr.tuning(3)[0] == 1  # the default on power-of-two z lines of 64 to 2048
+    pr.set_tuning(3, 1)
     pl = lf2.Plan(shape, lf2.LF2_R2C)
     pl.set_tuning(3, 0)
     assert pl.tuning(3)[0] == 0
@@ -269,16 +273,20 @@ def test_fused_register_tile(lf2, shape, nbins, flags, dx):
 
 
 def test_fused_register_tile_settings(lf2):
-    """Tuning axis 3 is the fused pass's tile: the register tile only for
-    256-, 512-, 1024- and 2048-point z lines, variants 0 and 1 only; the
-    default follows the length."""
-    p = lf2.Plan((16, 8, 64), lf2.LF2_R2C)
+    """Tuning axis 3 is the fused pass's tile: the register tile only for z
+    lines of 32 to 2048 points (powers of two; the default from 64), variants
+    0 and 1 only."""
+    p = lf2.Plan((16, 8, 96), lf2.LF2_R2C)
     assert p.tuning(3)[0] == 0
     with pytest.raises(lf2.LF2Error) as ei:
         p.set_tuning(3, 1)
     assert ei.value.status == lf2.LF2_ERR_UNSUPPORTED
-    for z in (256, 1024, 2048):
+    for z in (64, 128, 256, 1024, 2048):
         assert lf2.Plan((16, 8, z), lf2.LF2_R2C).tuning(3)[0] == 1
+    r = lf2.Plan((16, 8, 32), lf2.LF2_R2C)  # supported, not the default
+    assert r.tuning(3)[0] == 0
+    r.set_tuning(3, 1)
+    assert r.tuning(3)[0] == 1
     q = lf2.Plan((16, 8, 512), lf2.LF2_R2C)
     assert q.tuning(3)[0] == 1
     with pytest.raises(lf2.LF2Error) as ei:
