@@ -124,8 +124,8 @@ def test_c2c_in_place(lf2, shape, ncomp):
     assert_close(b.cpu().numpy() / np.prod(shape), zz, shape)
 
 
-def test_poisson_in_place(lf2):
-    shape = (32, 24, 16)
+@pytest.mark.parametrize("shape", [(32, 24, 16), (32, 24, 64)])  # LDS-staged, register fused pass
+def test_poisson_in_place(lf2, shape):
     n0, n1, n2 = shape
     f = real_field(shape, seed=36)[0][..., 0]
     p = lf2.Plan(shape, lf2.LF2_R2C, in_place=True)
