@@ -147,16 +147,17 @@ static hipError_t launch_len(int sign, const SArgs &a, int grid_cap, hipStream_t
 // The fused last-axis Poisson pass (forward z transform, optional P(k) of
 // the modes, the FP64 Poisson scale, optional P(k) after it, backward z
 // transform) with the tile in registers: B columns, 512 threads, P points a
-// thread, over lines of L = P Q points (32 = 4 x 8 over 64 columns, 64 =
-// 8 x 8 over 64, 128 = 8 x 16 over 32, 256 = 16 x 16 over 32, 512 = 16 x 32
-// over 16, 1024 = 32 x 32 over 16, 2048 = 32 x 64 over 8).  The line splits as n = j + Q r (r in [0, P), j in
-// [0, Q)), k = k1 + P k2 (k1 in [0, P), k2 in [0, Q)).  Thread (c, j) loads
-// points j + Q r, takes the P-point DFT over r and multiplies by
-// W_L^{j k1}; through LDS, thread (c, k1) receives the Q values of j and
-// takes the Q-point DFT over them -- where Q = 2P (32, 128, 512, 2048) as a lane
-// pair (c, k1, h = 0, 1) taking the P-point DFTs over the even (h = 0) and
-// odd (h = 1) j and one radix-2 step across the pair (DPP swap), so that
-// lane h holds the modes kz = k1 + P (k2' + P h) (k2' in [0, P)).  The scale is
+// thread, over lines of L = P Q points (32 = 4 x 8 over 64 columns,
+// 64 = 8 x 8 over 64, 128 = 8 x 16 over 32, 256 = 16 x 16 over 32,
+// 512 = 16 x 32 over 16, 1024 = 32 x 32 over 16, 2048 = 32 x 64 over 8).
+// The line splits as n = j + Q r (r in [0, P), j in [0, Q)),
+// k = k1 + P k2 (k1 in [0, P), k2 in [0, Q)).  Thread (c, j) loads points
+// j + Q r, takes the P-point DFT over r and multiplies by W_L^{j k1};
+// through LDS, thread (c, k1) receives the Q values of j and takes the
+// Q-point DFT over them -- where Q = 2P (32, 128, 512, 2048) as a lane pair
+// (c, k1, h = 0, 1) taking the P-point DFTs over the even (h = 0) and odd
+// (h = 1) j and one radix-2 step across the pair (DPP swap), so that lane h
+// holds the modes kz = k1 + P (k2' + P h) (k2' in [0, P)).  The scale is
 // applied there; the backward transform is the conjugate transpose of these
 // steps in reverse order (radix-2 step, DFTs over k2', the exchange back,
 // conjugate twiddles, DFTs over k1), which is the unnormalised inverse DFT.
@@ -166,11 +167,11 @@ static hipError_t launch_len(int sign, const SArgs &a, int grid_cap, hipStream_t
 // each, q growing by integer steps, FP64 sums into the wave's histogram)
 // runs at the start of the next tile, while that tile's loads are in
 // flight; the last tile's walk follows the loop.  The exchanges go through
-// LDS in halves (real parts, then imaginary parts): at L <= 512 the exchange
-// (32 KB) and the power table (32 KB) leave room for two blocks per CU.
-// (Adding the two powers of each |n_z| into one slot with LDS float
-// atomics, to halve the walk's reads, took the 512-point pass from 274 to
-// 545 us.)
+// LDS in halves (real parts, then imaginary parts): below 1024 points the
+// exchange and the power table (at most 32 KB each) leave room for two
+// blocks per CU.  (Adding the two powers of each |n_z| into one slot with
+// LDS float atomics, to halve the walk's reads, took the 512-point pass
+// from 274 to 545 us.)
 constexpr int kFThreads = 512;
 
 template <int L>
