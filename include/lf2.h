@@ -208,9 +208,8 @@ lf2_status lf2_fft_execute(lf2_plan p, lf2_direction dir, const void *in, void *
  * Spectral Poisson solve, laplacian(phi) = rho, periodic, zero mode
  * removed (the Poisson-solver example of sections 2 and 3.6):
  *   phi_hat = -rho_hat / k^2 (k != 0), phi_hat(0) = 0, phi = c2r(phi_hat)/N,
- * with the factor -1/(N k^2) applied in one pass between the forward and
- * backward transforms along dimension 2 (formed in FP32 from k^2 parts
- * computed in FP64: a few units in the last place per mode).  r2c plan with ncomp = 1.
+ * with the FP64 factor -1/(N k^2) applied in one pass between the forward
+ * and backward transforms along dimension 2.  r2c plan with ncomp = 1.
  * rho and phi are real fields (halo as in the plan) and must not overlap,
  * except rho == phi on a plan made with LF2_IN_PLACE.
  * dx > 0 is the lattice spacing.

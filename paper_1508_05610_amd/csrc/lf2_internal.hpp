@@ -15,7 +15,7 @@ constexpr int kMaxBins = 4096;  // LDS histogram limit of the fused binning epil
 enum : int {
     EPI_STORE = 1,    // write the transformed column back
     EPI_PK = 2,       // accumulate w|F|^2 per bin after the forward transform
-    EPI_POISSON = 4,  // scale by -1/(N k^2) (FP32) and run the backward transform
+    EPI_POISSON = 4,  // scale by -1/(N k^2) (FP64) and run the backward transform
     EPI_PK_AFTER = 8, // accumulate after the Poisson scale instead (spectrum of phi)
     EPI_TSTORE = 16,  // store in the c2c (k_z, k_x, k_y) order (k_strided_t)
     EPI_TLOAD = 32    // load from the c2c (k_z, k_x, k_y) order (k_strided_t)

@@ -713,14 +713,13 @@ __device__ __forceinline__ void hist_flush(int nbins, int copies, double *hist, 
     }
 }
 
-// The Poisson factor -1/(N k^2) of a mode in FP32: k^2 = k2xy + k2z, each
-// part rounded to FP32 once (k2z of the continuous k^2 as its FP32 unit
-// times the exact m^2), the hardware reciprocal (1 ulp) and sn = -1/N in
-// FP32.  Its relative error, a few units in the last place, stays below the
-// transforms' own rounding; the mode is then multiplied in FP32.
-__device__ __forceinline__ float poisson_factor(float sn, float k2xy, float k2z)
+// 1/d for d > 0 in FP64: the hardware reciprocal refined by one Newton step,
+// which squares the estimate's relative error; the scale it feeds multiplies
+// FP32 modes in FP64 and is rounded to FP32 with the product.
+__device__ __forceinline__ double rcp_f64(double d)
 {
-    return sn * __builtin_amdgcn_rcpf(k2xy + k2z);
+    double r = __builtin_amdgcn_rcp(d);
+    return fma(fma(-d, r, 1.0), r, r);
 }
 
 // The thread index, hidden from the optimiser once per tile when OPAQUE: the
@@ -898,13 +897,13 @@ struct STile {
         if (a.epi & EPI_POISSON) {
             if (K2 == 1 || (K2 == 0 && a.mt.k2z_unit > 0.0)) {
                 // continuous k^2 from |n_x|, |n_y|, |n_z|
-                const float k2xy = valid ? (float)fma(a.mt.k2x_unit, (double)sq24(mx),
-                                                      a.mt.k2y_unit * (double)sq24(my))
-                                         : 1.f;
+                const double k2xy = valid ? fma(a.mt.k2x_unit, (double)sq24(mx),
+                                                a.mt.k2y_unit * (double)sq24(my))
+                                          : 1.0;
                 scale_modes<true>(a, v, j0, k2xy, corner);
             } else {
                 // the tables
-                const float k2xy = valid ? (float)(a.mt.k2[0][kx] + a.mt.k2[1][ky]) : 1.f;
+                const double k2xy = valid ? a.mt.k2[0][kx] + a.mt.k2[1][ky] : 1.0;
                 scale_modes<false>(a, v, j0, k2xy, corner);
             }
         }
@@ -933,15 +932,14 @@ struct STile {
             col_stage_out<L, RL, QL, B, NT, true, NTM>(buf, gout, a.stride, valid, tid, v);
     }
 
-    // The Poisson factor -1/(N k^2) (poisson_factor) on the modes
-    // kz = j + r QL a thread holds after the forward transform.
+    // The Poisson scale -1/(N k^2) (FP64, rounded once with the product) of
+    // the modes kz = j + r QL a thread holds after the forward transform.
     template <bool CONT, int RL, int NB>
     static __device__ __forceinline__ void scale_modes(const SArgs &a, c32 (&v)[NB][RL], int j0,
-                                                       float k2xy, bool corner)
+                                                       double k2xy, bool corner)
     {
         constexpr int QL = L / RL;
         constexpr int JS = NT / B;
-        const float sn = (float)(-a.mt.scale_n), kzu = (float)a.mt.k2z_unit;
 #pragma unroll
         for (int i = 0; i < NB; ++i) {
             const int j = j0 + i * JS;
@@ -950,9 +948,10 @@ struct STile {
                 const int kz = j + r * QL;
                 if (QL % JS == 0 || j < QL) {
                     const int m = 2 * kz < L ? kz : L - kz;
-                    const float k2z = CONT ? kzu * (float)sq24(m) : (float)a.mt.k2[2][kz];
-                    const float sc = (corner && kz == 0) ? 0.f : poisson_factor(sn, k2xy, k2z);
-                    v[i][r] = c32{v[i][r].x * sc, v[i][r].y * sc};
+                    const double k2z = CONT ? a.mt.k2z_unit * (double)sq24(m) : a.mt.k2[2][kz];
+                    const double sc =
+                        (corner && kz == 0) ? 0.0 : -a.mt.scale_n * rcp_f64(k2xy + k2z);
+                    v[i][r] = c32{(float)((double)v[i][r].x * sc), (float)((double)v[i][r].y * sc)};
                 }
             }
         }

@@ -296,12 +296,9 @@ __global__ __launch_bounds__(kGThreads) void k_gs(SArgs a, GSched sc, int L, int
                         atomicAdd(&hist[b], w * ((double)v.x * v.x + (double)v.y * v.y));
                     }
                     if (scale_now) {
-                        const float sc2 =
-                            zero ? 0.f
-                                 : poisson_factor((float)(-a.mt.scale_n),
-                                                  (float)(a.mt.k2[0][kx] + a.mt.k2[1][ky]),
-                                                  (float)a.mt.k2[2][kz]);
-                        v = c32{v.x * sc2, v.y * sc2};
+                        const double k2 = a.mt.k2[0][kx] + a.mt.k2[1][ky] + a.mt.k2[2][kz];
+                        const double sc2 = zero ? 0.0 : -a.mt.scale_n / k2;
+                        v = c32{(float)((double)v.x * sc2), (float)((double)v.y * sc2)};
                         res[e] = v;
                     }
                 }

@@ -145,7 +145,7 @@ static hipError_t launch_len(int sign, const SArgs &a, int grid_cap, hipStream_t
 
 // ---------------------------------------------------------------- fused pass
 // The fused last-axis Poisson pass (forward z transform, optional P(k) of
-// the modes, the Poisson factor, optional P(k) after it, backward z
+// the modes, the FP64 Poisson scale, optional P(k) after it, backward z
 // transform) with the tile in registers: B columns, 512 threads, P points a
 // thread, over lines of L = P Q points (32 = 4 x 8 over 64 columns,
 // 64 = 8 x 8 over 64, 128 = 8 x 16 over 32, 256 = 16 x 16 over 32,
@@ -343,25 +343,24 @@ void k_fused_r(SArgs a)
         }
         if (pk && !pk_after) put_powers<L>(pw, v, k1, h, c2);
         {
-            // the Poisson factor -1/(N k^2) (poisson_factor)
+            // the Poisson scale -1/(N k^2), FP64, rounded once with the product
             const int64_t f2 = t * B + c2;
             const bool valid2 = f2 < a.ncols;
             const int kx2 = valid2 ? (int)f2 % a.mt.nxk : 0, ky2 = valid2 ? (int)f2 / a.mt.nxk : 0;
             const int mx2 = 2 * kx2 <= a.mt.n0 ? kx2 : a.mt.n0 - kx2;
             const int my2 = 2 * ky2 <= a.mt.n1 ? ky2 : a.mt.n1 - ky2;
             const bool corner2 = kx2 == 0 && ky2 == 0;
-            float k2xy = 1.f;
+            double k2xy = 1.0;
             if (valid2)
-                k2xy = CONT ? (float)fma(a.mt.k2x_unit, (double)sq24(mx2), a.mt.k2y_unit * (double)sq24(my2))
-                            : (float)(a.mt.k2[0][kx2] + a.mt.k2[1][ky2]);
-            const float sn = (float)(-a.mt.scale_n), kzu = (float)a.mt.k2z_unit;
+                k2xy = CONT ? fma(a.mt.k2x_unit, (double)sq24(mx2), a.mt.k2y_unit * (double)sq24(my2))
+                            : a.mt.k2[0][kx2] + a.mt.k2[1][ky2];
 #pragma unroll
             for (int k2 = 0; k2 < P; ++k2) {
                 const int kz = k1 + P * (k2 + P * h);
                 const int m = 2 * kz < L ? kz : L - kz;
-                const float k2z = CONT ? kzu * (float)sq24(m) : (float)a.mt.k2[2][kz];
-                const float sc = (corner2 && kz == 0) ? 0.f : poisson_factor(sn, k2xy, k2z);
-                v[k2] = c32{v[k2].x * sc, v[k2].y * sc};
+                const double k2z = CONT ? a.mt.k2z_unit * (double)sq24(m) : a.mt.k2[2][kz];
+                const double sc = (corner2 && kz == 0) ? 0.0 : -a.mt.scale_n * rcp_f64(k2xy + k2z);
+                v[k2] = c32{(float)((double)v[k2].x * sc), (float)((double)v[k2].y * sc)};
             }
         }
         if (pk_after) put_powers<L>(pw, v, k1, h, c2);
