@@ -813,7 +813,6 @@ struct STile {
         c32 *buf = (c32 *)(sm + O_BUF);
         const c32 *tw = (const c32 *)(sm + O_TW);
         const int col = tid % B;
-        const int rg = tid / B;
         const bool store = (a.epi & EPI_STORE) != 0;
         const int64_t f = t * B + col;
         const bool valid = f < a.ncols;
@@ -860,7 +859,6 @@ struct STile {
         constexpr int NST = nstages(L);
         constexpr int RL = NST == 0 ? 1 : radix_at(L, NST - 1);
         constexpr int QL = L / RL;
-        constexpr int JS = NT / B;
         constexpr int NB = col_nb(L, RL, B, NT);
         const int j0 = tid / B;
         // first forward stage (no twiddles) on the loaded inputs
