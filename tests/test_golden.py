@@ -24,3 +24,18 @@ def test_oracle_poisson_fixture():
     for dx, k2mode, a in cases:
         phi = oracle.poisson(rho, dx=dx, k2mode=k2mode)
         assert np.abs(phi - a * rho).max() <= 1e-12 * abs(a), (dx, k2mode)
+
+
+def test_fixtures_catch_planted_mistakes():
+    """Plausible mistakes, planted in copies of the oracle's results, fail the
+    fixtures: the opposite sign convention, transposed axes, a dropped dx^2
+    and the continuous k^2 in place of the discrete one."""
+    f, F = line_4x2x2()
+    assert np.abs(np.conj(oracle.c2c(f.astype(np.complex128))) - F).max() > 1.0
+    f, F = ramp_2x2x2()
+    assert np.abs(oracle.c2c(np.ascontiguousarray(f.transpose(2, 1, 0)).astype(np.complex128)) - F).max() > 1.0
+    rho, cases = poisson_cos_8x4x4()
+    for dx, k2mode, a in cases:
+        if dx != 1.0:
+            assert np.abs(oracle.poisson(rho, dx=1.0, k2mode=k2mode) - a * rho).max() > 0.1 * abs(a)
+        assert np.abs(oracle.poisson(rho, dx=dx, k2mode=1 - k2mode) - a * rho).max() > 0.01 * abs(a)
