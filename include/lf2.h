@@ -64,7 +64,7 @@ extern "C" {
 typedef enum {
     LF2_OK = 0,
     LF2_ERR_INVALID_ARG = -1,  /* null pointer, bad size, bad enum, misaligned pointer */
-    LF2_ERR_UNSUPPORTED = -2,  /* valid request outside what this build implements */
+    LF2_ERR_UNSUPPORTED = -2,  /* valid request outside what the library implements */
     LF2_ERR_OUT_OF_MEMORY = -3,
     LF2_ERR_DEVICE = -4,       /* HIP runtime error */
     LF2_ERR_BUDGET = -5,       /* server: request larger than the memory budget */
